@@ -1,0 +1,195 @@
+"""ctypes wrapper of the CPU oracle (oracle/ltl_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product path never imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import sys
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ltl_oracle.c")
+LIB = os.environ.get("LTL_ORACLE_LIB") or os.path.join(HERE, "libltl_oracle.so")
+
+ATOM, NOT, AND, OR, X, F, G, U = range(8)
+MODE_QUANT, MODE_EXPAND = 0, 1
+ST_OK, ST_NOT_FOUND, ST_EINVAL, ST_EINCONS, ST_EOOM = 0, 1, -1, -2, -4
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP for the candidate map)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", LIB + ".tmp", SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Spec(C.Structure):
+    _fields_ = [("num_props", C.c_int32), ("num_pos", C.c_int32), ("num_neg", C.c_int32),
+                ("pad_", C.c_int32), ("letters", C.c_void_p), ("offsets", C.c_void_p)]
+
+
+class _Node(C.Structure):
+    _fields_ = [("op", C.c_int32), ("a", C.c_int32), ("b", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.environ.get("LTL_ORACLE_LIB") and (
+                not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
+            build()
+        L = C.CDLL(LIB)
+        L.oracle_holds.argtypes = [C.POINTER(_Spec), C.c_int, C.c_int64, C.POINTER(_Node), C.c_int]
+        L.oracle_holds.restype = C.c_int
+        L.oracle_apply.argtypes = [C.POINTER(_Spec), C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+        L.oracle_apply.restype = C.c_int
+        L.oracle_eval_formula.argtypes = [C.POINTER(_Spec), C.POINTER(_Node), C.c_int, C.c_int, C.c_void_p]
+        L.oracle_eval_formula.restype = C.c_int
+        L.oracle_run.argtypes = [C.POINTER(_Spec), C.POINTER(C.c_int32), C.c_uint32, C.c_int, C.c_int,
+                                 C.c_int, C.c_int64]
+        L.oracle_run.restype = C.c_void_p
+        L.oracle_free.argtypes = [C.c_void_p]
+        for name, rt in [("oracle_status", C.c_int), ("oracle_found_cost", C.c_int),
+                         ("oracle_levels_done", C.c_int), ("oracle_first_index", C.c_int64)]:
+            getattr(L, name).argtypes = [C.c_void_p]
+            getattr(L, name).restype = rt
+        for name, rt in [("oracle_level_new", C.c_int64), ("oracle_level_candidates", C.c_int64),
+                         ("oracle_level_seconds", C.c_double)]:
+            getattr(L, name).argtypes = [C.c_void_p, C.c_int]
+            getattr(L, name).restype = rt
+        L.oracle_entry_formula.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.POINTER(_Node), C.c_int]
+        L.oracle_entry_formula.restype = C.c_int
+        L.oracle_solution_formula.argtypes = [C.c_void_p, C.POINTER(_Node), C.c_int]
+        L.oracle_solution_formula.restype = C.c_int
+        L.oracle_entry_cm.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p]
+        L.oracle_entry_cm.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class Spec:
+    """Keeps the numpy buffers alive for the C structure."""
+
+    def __init__(self, num_props: int, letters: np.ndarray, offsets: np.ndarray, num_pos: int, num_neg: int):
+        self.letters = np.ascontiguousarray(letters, dtype=np.uint32)
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        self.num_pos, self.num_neg, self.num_props = num_pos, num_neg, num_props
+        self.c = _Spec(num_props, num_pos, num_neg, 0, self.letters.ctypes.data if self.letters.size else None,
+                       self.offsets.ctypes.data)
+        self.tb = int(self.offsets[-1])
+
+    @classmethod
+    def of(cls, inst) -> "Spec":
+        return cls(inst.num_props, inst.letters, inst.offsets, inst.num_pos, inst.num_neg)
+
+
+def _nodes(nodes) -> "C.Array":
+    arr = (_Node * len(nodes))()
+    for k, (op, a, b) in enumerate(nodes):
+        arr[k].op, arr[k].a, arr[k].b = op, a, b
+    return arr
+
+
+def holds(spec: Spec, t: int, i: int, nodes) -> bool:
+    r = lib().oracle_holds(C.byref(spec.c), t, i, _nodes(nodes), len(nodes))
+    assert r >= 0
+    return bool(r)
+
+
+def eval_formula(spec: Spec, nodes, mode: int = MODE_QUANT) -> np.ndarray:
+    out = np.zeros(spec.tb, dtype=np.uint8)
+    assert lib().oracle_eval_formula(C.byref(spec.c), _nodes(nodes), len(nodes), mode, out.ctypes.data) == 0
+    return out
+
+
+def apply(spec: Spec, op: int, a: np.ndarray, b: Optional[np.ndarray] = None, mode: int = MODE_QUANT) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    out = np.zeros(spec.tb, dtype=np.uint8)
+    bp = None
+    if b is not None:
+        b = np.ascontiguousarray(b, dtype=np.uint8)
+        bp = b.ctypes.data
+    assert lib().oracle_apply(C.byref(spec.c), op, a.ctypes.data, bp, mode, out.ctypes.data) == 0
+    return out
+
+
+UNIT_COST = [1] * 8
+ALL_OPS = 0xFF
+
+
+@dataclass
+class Result:
+    status: int
+    cost: int
+    levels_done: int
+    level_new: List[int]          # index = cost level
+    level_candidates: List[int]
+    level_seconds: List[float]
+    first_index: int
+    solution: Optional[list] = None
+    run: Optional["Run"] = field(default=None, repr=False)
+
+
+class Run:
+    def __init__(self, spec: Spec, bound: int, cost=UNIT_COST, op_mask: int = ALL_OPS, mode: int = MODE_QUANT,
+                 threads: int = 1, max_entries: int = 0):
+        self.spec = spec
+        self.bound = bound
+        c = (C.c_int32 * 8)(*cost)
+        self.h = lib().oracle_run(C.byref(spec.c), c, op_mask, bound, mode, threads, max_entries)
+        assert self.h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().oracle_free(self.h)
+            self.h = None
+
+    def result(self) -> Result:
+        L = lib()
+        st = L.oracle_status(self.h)
+        done = L.oracle_levels_done(self.h)
+        E = [max(0, L.oracle_level_new(self.h, c)) for c in range(self.bound + 1)]
+        Cc = [max(0, L.oracle_level_candidates(self.h, c)) for c in range(self.bound + 1)]
+        S = [L.oracle_level_seconds(self.h, c) for c in range(self.bound + 1)]
+        sol = None
+        if st == ST_OK:
+            buf = (_Node * 4096)()
+            n = L.oracle_solution_formula(self.h, buf, 4096)
+            sol = [(buf[k].op, buf[k].a, buf[k].b) for k in range(n)]
+        return Result(st, L.oracle_found_cost(self.h), done, E, Cc, S, L.oracle_first_index(self.h), sol, self)
+
+    def entry_formula(self, c: int, i: int):
+        buf = (_Node * 4096)()
+        n = lib().oracle_entry_formula(self.h, c, i, buf, 4096)
+        assert n > 0
+        return [(buf[k].op, buf[k].a, buf[k].b) for k in range(n)]
+
+    def entry_cm(self, c: int, i: int) -> np.ndarray:
+        out = np.zeros(self.spec.tb, dtype=np.uint8)
+        assert lib().oracle_entry_cm(self.h, c, i, out.ctypes.data) == 0
+        return out
+
+
+def learn(inst, bound: int, cost=UNIT_COST, op_mask: int = ALL_OPS, mode: int = MODE_QUANT, threads: int = 1,
+          max_entries: int = 0) -> Result:
+    spec = Spec.of(inst)
+    run = Run(spec, bound, cost, op_mask, mode, threads, max_entries)
+    return run.result()
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    print("built", LIB, file=sys.stderr)
