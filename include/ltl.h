@@ -1,0 +1,224 @@
+/*
+ * ltl.h -- C-ABI of the MI355X (gfx950) enumerative LTL learner.
+ *
+ * The library learns a minimal-cost LTL formula separating positive traces P
+ * from negative traces N (the "LTL learning problem" of Sec. 2 of "LTL
+ * learning on GPUs", arXiv 2402.12373): bottom-up, cost-ordered enumeration
+ * (Sec. 3, enum / handleOp), every candidate represented by its characteristic
+ * matrix over all positions of all traces (Sec. 4), computed from its
+ * children's matrices by branch-free word-parallel operators (Sec. 4 and
+ * App. B), deduplicated exactly by observational equivalence modulo the
+ * suffix-closure of P and N (Sec. 4; the exhaustive case of Sec. 5), and
+ * checked against the separation predicate of Sec. 4 at position 0.
+ *
+ * Conventions common to all calls
+ *   - Traces are numbered P first (in the given order), then N (Sec. 4 fixes a
+ *     total order on P and N).
+ *   - Functions return LTL_OK (0), LTL_NOT_FOUND (1, not an error) or a
+ *     negative error code; nothing is thrown and nothing aborts.
+ *   - Device memory: the library allocates none.  All device buffers live in
+ *     the caller-provided workspace (ltl_ctx_opts.workspace); host-side state
+ *     is ordinary malloc'd memory owned by the context / job.
+ *   - A context runs one job at a time; calls on one context are not
+ *     thread-safe.  Different contexts may share a device if their workspaces
+ *     are disjoint.
+ */
+#ifndef LTL_H
+#define LTL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define LTL_OK              0    /* success; for learning: a separating formula was found     */
+#define LTL_NOT_FOUND       1    /* no separating formula of cost <= bound; counts are valid   */
+#define LTL_E_INVAL        (-1)  /* null pointer, bad size, bad letter, empty trace, bad costs */
+#define LTL_E_INCONSISTENT (-2)  /* a trace occurs in both P and N (Sec. 2 requires P, N disjoint) */
+#define LTL_E_TOO_LONG     (-3)  /* a trace is longer than LTL_MAX_TRACE_LEN positions         */
+#define LTL_E_OOM          (-4)  /* a level that must be stored exceeds the workspace or the
+                                    entry cap; counts of the completed levels stay valid       */
+#define LTL_E_DEVICE       (-5)  /* a HIP runtime error                                        */
+#define LTL_E_STATE        (-6)  /* call out of order (e.g. levels not evaluated in order)     */
+
+#define LTL_MAX_TRACE_LEN  4096  /* positions per trace (64 words of 64 bits)                  */
+#define LTL_MAX_LEVELS     64    /* cost levels 0..63                                          */
+#define LTL_MAX_NODES      64    /* nodes of a returned formula                                */
+#define LTL_NO_SOLUTION    UINT64_MAX
+
+/* ---------------------------------------------------------------- connectives (Sec. 2 grammar) */
+enum {
+    LTL_ATOM = 0,   /* atomic proposition p                                     */
+    LTL_NOT  = 1,   /* negation                                                 */
+    LTL_AND  = 2,   /* conjunction                                              */
+    LTL_OR   = 3,   /* disjunction                                              */
+    LTL_X    = 4,   /* next (strong: false at the last position)                */
+    LTL_F    = 5,   /* eventually                                               */
+    LTL_G    = 6,   /* always (until the end of the trace)                      */
+    LTL_U    = 7    /* until                                                    */
+};
+
+/* ---------------------------------------------------------------- context */
+typedef struct ltl_ctx ltl_ctx;
+typedef struct ltl_job ltl_job;
+
+#define LTL_CTX_U_CARRY   0x1u   /* compute U by a carry-propagating add (one add per word)
+                                    instead of the log2(n) shift-doubling of App. B; both give
+                                    identical matrices                                         */
+#define LTL_CTX_TIMING    0x2u   /* record per-level kernel time with HIP events              */
+
+typedef struct {
+    int32_t  device;            /* HIP device ordinal used by every call of this context        */
+    uint32_t flags;             /* LTL_CTX_*                                                    */
+    void    *workspace;         /* device pointer, caller-owned, 256-byte aligned, valid until
+                                   ltl_ctx_destroy; the library writes only inside it           */
+    uint64_t workspace_bytes;   /* its size                                                     */
+    void    *stream;            /* hipStream_t for all work; NULL = the null stream             */
+    uint32_t hash_slots_log2;   /* language-cache hash table size; 0 = automatic                */
+    uint32_t word_bits;         /* 0 = automatic (32 if every trace has <= 32 positions, else 64),
+                                   or 32 / 64                                                   */
+    uint32_t fp_bits;           /* debug: keep only this many fingerprint bits (1..64), forcing
+                                   collisions that the exact compare must resolve; 0 = 64       */
+    uint32_t reserved;
+    uint64_t max_entries;       /* cap on stored language-cache entries; 0 = derived from the
+                                   hash table (half its slots)                                  */
+} ltl_ctx_opts;
+
+/* Create a context on opts->device.  Returns LTL_E_INVAL for a null/unaligned
+ * workspace or size < LTL_MIN_WORKSPACE, LTL_E_DEVICE if the device cannot be
+ * selected.  *out is set only on success. */
+#define LTL_MIN_WORKSPACE (16ull << 20)
+int  ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out);
+void ltl_ctx_destroy(ltl_ctx *ctx);
+
+/* ---------------------------------------------------------------- specification */
+#define LTL_SPEC_DEVICE 0x1u    /* letters and offsets are device pointers (already in HBM) */
+
+typedef struct {
+    uint32_t num_props;         /* |Sigma|, 1..32; a letter is a bitmask of true propositions */
+    uint32_t num_pos;           /* |P|: traces 0 .. num_pos-1                                 */
+    uint32_t num_neg;           /* |N|: traces num_pos .. num_pos+num_neg-1                   */
+    uint32_t flags;             /* LTL_SPEC_*                                                 */
+    const uint32_t *letters;    /* offsets[num_pos+num_neg] letters, trace after trace;
+                                   read during the call only (copied to the device)           */
+    const uint64_t *offsets;    /* num_pos+num_neg+1 prefix offsets, offsets[0] = 0           */
+} ltl_spec;
+
+/* Cost-homomorphism restricted to an operator set (Sec. 2): cost(op phi psi) =
+ * cost[op] + cost(phi) + cost(psi).  Disabled connectives are never used. */
+typedef struct {
+    uint32_t op_mask;           /* bit k enables connective k; bit LTL_ATOM must be set        */
+    uint32_t cost[8];           /* cost of each enabled connective, >= 1                       */
+} ltl_opset;
+
+/* Kernel kinds for per-kind GPU time (LTL_CTX_TIMING). */
+enum {
+    LTL_K_EVAL = 0,          /* level evaluation: matrices, fingerprints, separation, cache claims */
+    LTL_K_VERIFY = 1,        /* full compare of every presumed duplicate with its owner            */
+    LTL_K_MATERIALIZE = 2,   /* writing the new entries of a level                                  */
+    LTL_K_COMPACT = 3,       /* representative bits, prefix scan, recipes, slot settlement          */
+    LTL_K_FALLBACK = 4,      /* exact resolution of fingerprint collisions                          */
+    LTL_K_INTAKE = 5,        /* specification intake: packing, table init, validation               */
+    LTL_K_KINDS = 6
+};
+
+/* Formula as postfix nodes; children are earlier node indices. */
+typedef struct {
+    uint32_t op;                /* LTL_ATOM .. LTL_U                                           */
+    uint32_t a;                 /* ATOM: proposition index; otherwise first child node         */
+    uint32_t b;                 /* second child node for AND, OR, U; else 0                    */
+} ltl_node;
+
+typedef struct {
+    int32_t  status;                           /* LTL_OK / LTL_NOT_FOUND / error           */
+    uint32_t cost;                             /* minimal cost when status == LTL_OK        */
+    uint32_t levels_done;                      /* highest cost level fully evaluated        */
+    uint32_t num_nodes;                        /* nodes of the solution                     */
+    ltl_node nodes[LTL_MAX_NODES];             /* the solution (root = last node)           */
+    uint64_t solution_index;                   /* canonical index of the solution in its
+                                                  level, or LTL_NO_SOLUTION                 */
+    uint64_t level_new[LTL_MAX_LEVELS];        /* distinct new languages per cost level     */
+    uint64_t level_candidates[LTL_MAX_LEVELS]; /* candidates evaluated per cost level       */
+    double   level_ms[LTL_MAX_LEVELS];         /* GPU time per level (LTL_CTX_TIMING)       */
+    uint64_t colliders;                        /* fingerprint collisions resolved exactly   */
+    double   kernel_ms[LTL_K_KINDS];           /* GPU time per kernel kind (LTL_CTX_TIMING) */
+    uint32_t kernel_launches[LTL_K_KINDS];     /* launches per kernel kind                  */
+} ltl_result;
+
+/* ---------------------------------------------------------------- learning */
+
+/* Learn a sound and minimal formula for (P, N) under the cost-homomorphism
+ * (Sec. 2 "LTL learning problem"), searching costs up to cost_bound inclusive.
+ * Returns the status also stored in out->status: LTL_OK with the solution, or
+ * LTL_NOT_FOUND (no separating formula of cost <= cost_bound), or an error.
+ * Per-level counts in *out are valid for levels 1..levels_done in every case.
+ * Deterministic: the same inputs give the same result, whatever the launch
+ * configuration. */
+int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
+              ltl_result *out);
+
+/* ---------------------------------------------------------------- level-by-level interface */
+
+/* Validate and pack the specification (atom matrices, row layout) into the
+ * context's workspace.  Errors: LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG,
+ * LTL_E_OOM (workspace too small for the fixed tables), LTL_E_DEVICE. */
+int ltl_job_create(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
+                   ltl_job **out);
+
+typedef struct {
+    uint32_t cost;               /* the level evaluated                                   */
+    uint32_t stored;             /* 1 if its matrices were kept for later levels          */
+    uint64_t candidates;         /* candidates of this level in the canonical order       */
+    uint64_t new_entries;        /* distinct languages first reached at this cost         */
+    uint64_t first_solution;     /* smallest separating canonical index, or LTL_NO_SOLUTION */
+    uint64_t colliders;          /* fingerprint matches whose full compare failed         */
+    double   kernel_ms;          /* GPU time of the level (LTL_CTX_TIMING), else 0        */
+} ltl_level_stats;
+
+/* Evaluate exactly one cost level: every candidate of cost `cost` built from the
+ * stored levels by one connective (Sec. 3 handleOp), in the canonical order
+ * (op in F, U, G, X, AND, OR, NOT; splits a ascending; pairs row-major; AND/OR
+ * with a <= b and i < j on the diagonal), with the separation check and exact
+ * dedup.  Levels must be evaluated in order 1, 2, ... (LTL_E_STATE otherwise,
+ * and after a solution was found, after LTL_E_OOM, or beyond the job's bound).
+ * Returns LTL_OK or an error; stats may be NULL. */
+int ltl_eval_level(ltl_job *job, uint32_t cost, ltl_level_stats *stats);
+
+/* Result so far (status LTL_OK once a level has a separating candidate,
+ * LTL_NOT_FOUND while none has, or the error that stopped the job). */
+int ltl_job_result(ltl_job *job, ltl_result *out);
+
+/* Formula of stored entry `entry` of level `cost` (postfix nodes into buf, at
+ * most cap).  Errors: LTL_E_INVAL (no such entry, cap too small). */
+int ltl_job_formula(ltl_job *job, uint32_t cost, uint64_t entry, ltl_node *buf, uint32_t cap,
+                    uint32_t *num_nodes);
+
+/* Characteristic matrix of stored entry `entry` of level `cost`, one byte (0/1)
+ * per position, traces in order P then N, positions 0..|tr|-1 of each.  cap must
+ * be >= the total number of positions.  For tests and debugging. */
+int ltl_job_dump_cm(ltl_job *job, uint32_t cost, uint64_t entry, uint8_t *pos_bits, uint64_t cap);
+
+typedef struct {
+    uint32_t word_bits;          /* 32 or 64                                               */
+    uint32_t rows;               /* machine words per characteristic matrix                */
+    uint64_t cm_bytes;           /* bytes per stored matrix                                */
+    uint64_t total_positions;    /* sum of trace lengths                                   */
+    uint32_t hash_slots_log2;
+    uint32_t doubling_steps;     /* ceil(log2(longest trace)) steps of U doubling          */
+    uint64_t arena_bytes;        /* workspace bytes available for stored matrices          */
+    uint64_t max_entries;
+} ltl_job_info;
+
+int  ltl_job_get_info(ltl_job *job, ltl_job_info *out);
+void ltl_job_destroy(ltl_job *job);
+
+/* Static description of a status code. */
+const char *ltl_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTL_H */

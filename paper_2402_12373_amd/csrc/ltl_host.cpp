@@ -1,0 +1,918 @@
+// Host runtime of the LTL learner: the C-ABI of include/ltl.h.
+//
+// Per job it lays out the specification as characteristic-matrix rows, carves
+// the caller's workspace into fixed tables (row metadata, atom matrices, the
+// language-cache hash table, recipes) and the level arena, and drives the
+// level loop of Sec. 3 (enum): for each cost level, build the canonical block
+// list (connective x split), run the evaluation kernel, read back 64 bytes of
+// counters, compact the representatives, write the new entries and verify
+// every presumed duplicate in full.  All matrix work runs in the kernels of
+// ltl_kernels.hip; the host only plans, launches and reads counters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "ltl.h"
+#include "ltl_internal.h"
+
+using namespace ltl;
+
+namespace {
+
+constexpr int ORDER[7] = {LTL_F, LTL_U, LTL_G, LTL_X, LTL_AND, LTL_OR, LTL_NOT};   // Sec. 3 listing
+constexpr uint32_t MAX_GRID = 8192;
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+uint64_t splitmix64(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+bool is_unary(int op) { return op == LTL_NOT || op == LTL_X || op == LTL_F || op == LTL_G; }
+
+}  // namespace
+
+struct ltl_ctx {
+    ltl_ctx_opts o;
+    hipStream_t s = nullptr;
+    bool busy = false;
+};
+
+struct LevelInfo {
+    bool evaluated = false;
+    bool stored = false;
+    uint32_t n = 0;            // entries (distinct new languages)
+    uint32_t gid_base = 0;     // global id of the first entry
+    uint64_t cands = 0;
+    uint64_t first = LTL_NO_SOLUTION;
+    uint64_t colliders = 0;
+    double ms = 0.0;
+    std::vector<Block> blocks;
+    std::vector<int> a_level, b_level;   // child levels per block (host decode)
+};
+
+struct TimedLaunch {
+    int kind;
+    hipEvent_t e0, e1;
+};
+
+struct ltl_job {
+    ltl_ctx *ctx = nullptr;
+    hipStream_t s = nullptr;
+    uint32_t A = 0, T = 0, npos = 0, nneg = 0;
+    std::vector<uint64_t> off;     // host copy of offsets
+    uint64_t TB = 0;
+    ltl_opset ops{};
+    uint32_t bound = 0;
+    uint32_t wbits = 32;
+    bool mw = false;
+    uint32_t R = 0, NB = 0, ksteps = 0, maxw = 1;
+    uint64_t wbytes = 4, cm_bytes = 0;
+    std::vector<uint32_t> row0, nwords;   // per trace: first row, words
+    // workspace
+    char *ws = nullptr;
+    uint64_t wsb = 0, used = 0;
+    Counters *ctr = nullptr;
+    void *valid = nullptr, *sepm = nullptr, *sepw = nullptr, *atoms = nullptr;
+    uint64_t *nxt = nullptr, *key = nullptr, *tfp = nullptr, *offsets_d = nullptr;
+    uint32_t *row_trace = nullptr, *row_word = nullptr, *letters_d = nullptr;
+    Block *blocks_d = nullptr;
+    unsigned long long *tkey = nullptr;
+    uint32_t *tval = nullptr;
+    uint32_t slots_log2 = 0;
+    uint32_t *recipe = nullptr;
+    uint64_t recipe_cap = 0, max_entries = 0;
+    char *arena = nullptr;
+    uint64_t arena_region = 0;     // bytes from arena to the end of the workspace
+    uint64_t total_entries = 0;    // entries in the arena
+    uint64_t stored_entries = 0;   // entries of stored levels
+    std::vector<LevelInfo> L;
+    uint32_t levels_done = 0;
+    int status = LTL_NOT_FOUND;
+    bool searching = true;
+    uint32_t sol_level = 0;
+    uint64_t sol_index = LTL_NO_SOLUTION;
+    uint64_t colliders = 0;
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[LTL_K_KINDS] = {0};
+    uint32_t kernel_launches[LTL_K_KINDS] = {0};
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return LTL_E_DEVICE;            \
+    } while (0)
+
+static void *ws_take(ltl_job *j, uint64_t bytes) {
+    uint64_t at = align_up(j->used, 256);
+    if (at + bytes > j->wsb) return nullptr;
+    j->used = at + bytes;
+    return j->ws + at;
+}
+
+static hipEvent_t pool_event(ltl_job *j) {
+    if (!j->event_pool.empty()) {
+        hipEvent_t e = j->event_pool.back();
+        j->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records events around a launch when timing is on.
+struct Timer {
+    ltl_job *j;
+    TimedLaunch t{};
+    bool on = false;
+    Timer(ltl_job *job, int kind) : j(job) {
+        j->kernel_launches[kind]++;
+        if (!j->timing) return;
+        t.kind = kind;
+        t.e0 = pool_event(j);
+        t.e1 = pool_event(j);
+        if (t.e0 && t.e1) {
+            (void)hipEventRecord(t.e0, j->s);
+            on = true;
+        }
+    }
+    ~Timer() {
+        if (on) {
+            (void)hipEventRecord(t.e1, j->s);
+            j->pending.push_back(t);
+        }
+    }
+};
+
+// Adds the elapsed times of completed launches; returns their sum.
+static double collect_times(ltl_job *j) {
+    double tot = 0.0;
+    for (auto &t : j->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess) {
+            j->kernel_ms[t.kind] += ms;
+            tot += ms;
+        }
+        j->event_pool.push_back(t.e0);
+        j->event_pool.push_back(t.e1);
+    }
+    j->pending.clear();
+    return tot;
+}
+
+static int sync_read_counters(ltl_job *j, Counters *host) {
+    HIP_TRY(hipMemcpyAsync(host, j->ctr, sizeof(Counters), hipMemcpyDeviceToHost, j->s));
+    HIP_TRY(hipStreamSynchronize(j->s));
+    return LTL_OK;
+}
+
+template <typename T>
+static Rows<T> make_rows(const ltl_job *j) {
+    Rows<T> r;
+    r.valid = (const T *)j->valid;
+    r.sepm = (const T *)j->sepm;
+    r.sepw = (const T *)j->sepw;
+    r.nxt = j->nxt;
+    r.key = j->key;
+    r.R = j->R;
+    r.NB = j->NB;
+    r.ksteps = j->ksteps;
+    r.maxw = j->maxw;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// ABI: context
+// ---------------------------------------------------------------------------
+extern "C" int ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out) {
+    if (!opts || !out || !opts->workspace || opts->workspace_bytes < LTL_MIN_WORKSPACE) return LTL_E_INVAL;
+    if (((uintptr_t)opts->workspace) & 255u) return LTL_E_INVAL;
+    if (opts->fp_bits > 64) return LTL_E_INVAL;
+    if (opts->word_bits != 0 && opts->word_bits != 32 && opts->word_bits != 64) return LTL_E_INVAL;
+    if (opts->hash_slots_log2 != 0 && (opts->hash_slots_log2 < 8 || opts->hash_slots_log2 > 31)) return LTL_E_INVAL;
+    if (hipSetDevice(opts->device) != hipSuccess) return LTL_E_DEVICE;
+    ltl_ctx *c = new (std::nothrow) ltl_ctx;
+    if (!c) return LTL_E_INVAL;
+    c->o = *opts;
+    c->s = (hipStream_t)opts->stream;
+    *out = c;
+    return LTL_OK;
+}
+
+extern "C" void ltl_ctx_destroy(ltl_ctx *ctx) { delete ctx; }
+
+extern "C" const char *ltl_status_str(int st) {
+    switch (st) {
+    case LTL_OK: return "ok";
+    case LTL_NOT_FOUND: return "no separating formula within the cost bound";
+    case LTL_E_INVAL: return "invalid argument";
+    case LTL_E_INCONSISTENT: return "a trace is both positive and negative";
+    case LTL_E_TOO_LONG: return "trace too long";
+    case LTL_E_OOM: return "out of workspace or entry cap";
+    case LTL_E_DEVICE: return "HIP device error";
+    case LTL_E_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Job creation: validation, row layout, workspace carve, atom packing
+// ---------------------------------------------------------------------------
+static int job_setup(ltl_job *j, const ltl_spec *spec) {
+    ltl_ctx *c = j->ctx;
+    j->ws = (char *)c->o.workspace;
+    j->wsb = c->o.workspace_bytes;
+    j->used = 0;
+    j->s = c->s;
+    j->timing = (c->o.flags & LTL_CTX_TIMING) != 0;
+    const uint32_t T = j->T;
+
+    // offsets on the host (device specs: copy them back; the letters stay on the device)
+    j->off.resize((size_t)T + 1);
+    if (spec->flags & LTL_SPEC_DEVICE) {
+        HIP_TRY(hipMemcpy(j->off.data(), spec->offsets, sizeof(uint64_t) * ((size_t)T + 1), hipMemcpyDeviceToHost));
+    } else {
+        memcpy(j->off.data(), spec->offsets, sizeof(uint64_t) * ((size_t)T + 1));
+    }
+    if (j->off[0] != 0) return LTL_E_INVAL;
+    uint64_t maxlen = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+        if (j->off[t + 1] <= j->off[t]) return LTL_E_INVAL;          // empty trace (or decreasing)
+        maxlen = std::max<uint64_t>(maxlen, j->off[t + 1] - j->off[t]);
+    }
+    if (maxlen > LTL_MAX_TRACE_LEN) return LTL_E_TOO_LONG;
+    j->TB = j->off[T];
+
+    // word size and row layout
+    uint32_t wb = c->o.word_bits ? c->o.word_bits : (maxlen <= 32 ? 32u : 64u);
+    if (wb == 32 && maxlen > 32) return LTL_E_TOO_LONG;
+    j->wbits = wb;
+    j->wbytes = wb / 8;
+    j->row0.resize(T);
+    j->nwords.resize(T);
+    uint64_t r = 0;
+    uint32_t maxw = 1;
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint64_t len = j->off[t + 1] - j->off[t];
+        const uint32_t w = (uint32_t)((len + wb - 1) / wb);
+        if ((r & 63u) + w > 64u) r = align_up(r, 64);                 // no trace straddles a row block
+        j->row0[t] = (uint32_t)r;
+        j->nwords[t] = w;
+        r += w;
+        maxw = std::max(maxw, w);
+    }
+    const uint64_t R = align_up(std::max<uint64_t>(r, 1), 64);
+    if (R > 0x7FFFFFFFull) return LTL_E_TOO_LONG;
+    j->R = (uint32_t)R;
+    j->NB = (uint32_t)(R / 64);
+    j->maxw = maxw;
+    j->mw = (wb == 64 && maxw > 1);     // words of one trace exchange bits across lanes
+    uint32_t k = 0;
+    while ((1ull << k) < maxlen) ++k;
+    j->ksteps = k;
+    j->cm_bytes = R * j->wbytes;
+
+    // host row metadata
+    const uint64_t W = wb;
+    std::vector<uint64_t> valid(R, 0), sepm(R, 0), sepw(R, 0), nxt(R, 0);
+    std::vector<uint32_t> row_trace(R, 0xFFFFFFFFu), row_word(R, 0);
+    const uint64_t full = (wb == 64) ? ~0ull : 0xFFFFFFFFull;
+    const uint64_t msb = 1ull << (wb - 1);
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint64_t len = j->off[t + 1] - j->off[t];
+        for (uint32_t w = 0; w < j->nwords[t]; ++w) {
+            const uint64_t row = j->row0[t] + w;
+            const uint64_t n = std::min<uint64_t>(W, len - (uint64_t)w * W);
+            valid[row] = (n == W) ? full : ((full << (W - n)) & full);
+            sepm[row] = (w == 0) ? msb : 0;
+            sepw[row] = (w == 0 && t < j->npos) ? msb : 0;
+            const uint32_t later = j->nwords[t] - 1 - w;
+            const uint32_t lane = (uint32_t)(row & 63u);
+            nxt[row] = later ? (((later == 64 ? 0ull : (1ull << later)) - 1ull) << (lane + 1)) : 0ull;
+            row_trace[row] = t;
+            row_word[row] = w;
+        }
+    }
+    const uint32_t nkeys = (wb == 64) ? 2u : 1u;
+    std::vector<uint64_t> keys((size_t)R * nkeys);
+    uint64_t seed = 0x5eed1e55c0ffee11ull;
+    for (auto &kk : keys) kk = splitmix64(seed) | 1ull;
+
+    // workspace carve: fixed tables
+    j->ctr = (Counters *)ws_take(j, sizeof(Counters));
+    j->valid = ws_take(j, R * j->wbytes);
+    j->sepm = ws_take(j, R * j->wbytes);
+    j->sepw = ws_take(j, R * j->wbytes);
+    j->nxt = (uint64_t *)ws_take(j, R * 8);
+    j->key = (uint64_t *)ws_take(j, R * 8 * nkeys);
+    j->row_trace = (uint32_t *)ws_take(j, R * 4);
+    j->row_word = (uint32_t *)ws_take(j, R * 4);
+    j->atoms = ws_take(j, (uint64_t)j->A * R * j->wbytes);
+    j->tfp = (uint64_t *)ws_take(j, (uint64_t)T * 8);
+    j->blocks_d = (Block *)ws_take(j, sizeof(Block) * MAX_BLOCKS);
+    if (!(spec->flags & LTL_SPEC_DEVICE)) {
+        j->letters_d = (uint32_t *)ws_take(j, j->TB * 4);
+        j->offsets_d = (uint64_t *)ws_take(j, ((uint64_t)T + 1) * 8);
+    } else {
+        j->letters_d = (uint32_t *)spec->letters;
+        j->offsets_d = (uint64_t *)spec->offsets;
+    }
+    if (!j->ctr || !j->valid || !j->sepm || !j->sepw || !j->nxt || !j->key || !j->row_trace || !j->row_word ||
+        !j->atoms || !j->tfp || !j->blocks_d || !j->letters_d || !j->offsets_d)
+        return LTL_E_OOM;
+
+    // language-cache hash table: 12 bytes per slot
+    uint32_t sl = c->o.hash_slots_log2;
+    if (!sl) {
+        sl = 26;
+        while (sl > 10 && (16ull << sl) > (j->wsb - j->used) / 4) --sl;
+    }
+    j->slots_log2 = sl;
+    const uint64_t nslots = 1ull << sl;
+    j->tkey = (unsigned long long *)ws_take(j, nslots * 8);
+    j->tval = (uint32_t *)ws_take(j, nslots * 4);
+    j->max_entries = c->o.max_entries ? c->o.max_entries : nslots / 2;
+    j->recipe_cap = nslots;
+    j->recipe = (uint32_t *)ws_take(j, nslots * 4);
+    if (!j->tkey || !j->tval || !j->recipe) return LTL_E_OOM;
+    j->arena = j->ws + align_up(j->used, 256);
+    if ((uint64_t)(j->arena - j->ws) >= j->wsb) return LTL_E_OOM;
+    j->arena_region = j->wsb - (uint64_t)(j->arena - j->ws);
+
+    // uploads
+    std::vector<uint32_t> v32;
+    auto up_words = [&](void *dst, const std::vector<uint64_t> &src) -> hipError_t {
+        if (wb == 64) return hipMemcpyAsync(dst, src.data(), R * 8, hipMemcpyHostToDevice, j->s);
+        v32.resize(R);
+        for (uint64_t i = 0; i < R; ++i) v32[i] = (uint32_t)src[i];
+        return hipMemcpy(dst, v32.data(), R * 4, hipMemcpyHostToDevice);
+    };
+    HIP_TRY(up_words(j->valid, valid));
+    HIP_TRY(up_words(j->sepm, sepm));
+    HIP_TRY(up_words(j->sepw, sepw));
+    HIP_TRY(hipMemcpyAsync(j->nxt, nxt.data(), R * 8, hipMemcpyHostToDevice, j->s));
+    HIP_TRY(hipMemcpyAsync(j->key, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, j->s));
+    HIP_TRY(hipMemcpyAsync(j->row_trace, row_trace.data(), R * 4, hipMemcpyHostToDevice, j->s));
+    HIP_TRY(hipMemcpyAsync(j->row_word, row_word.data(), R * 4, hipMemcpyHostToDevice, j->s));
+    if (!(spec->flags & LTL_SPEC_DEVICE)) {
+        HIP_TRY(hipMemcpyAsync(j->letters_d, spec->letters, j->TB * 4, hipMemcpyHostToDevice, j->s));
+        HIP_TRY(hipMemcpyAsync(j->offsets_d, spec->offsets, ((uint64_t)T + 1) * 8, hipMemcpyHostToDevice, j->s));
+    }
+    HIP_TRY(hipMemsetAsync(j->ctr, 0, sizeof(Counters), j->s));
+    {
+        Timer tm(j, LTL_K_INTAKE);
+        HIP_TRY(launch_table_init(j->tkey, j->tval, nslots, j->s));
+        if (wb == 64)
+            HIP_TRY(Launch<uint64_t>::pack(j->letters_d, j->offsets_d, j->row_trace, j->row_word, j->R, j->A,
+                                           (uint64_t *)j->atoms, j->ctr, j->s));
+        else
+            HIP_TRY(Launch<uint32_t>::pack(j->letters_d, j->offsets_d, j->row_trace, j->row_word, j->R, j->A,
+                                           (uint32_t *)j->atoms, j->ctr, j->s));
+        HIP_TRY(launch_trace_fp(j->letters_d, j->offsets_d, T, j->tfp, j->s));
+    }
+    Counters hc;
+    if (int e = sync_read_counters(j, &hc)) return e;
+    collect_times(j);
+    if (j->A < 32 && (hc.letter_or >> j->A)) return LTL_E_INVAL;      // a letter names a missing proposition
+
+    // P and N must be disjoint (Sec. 2): equal fingerprints are compared exactly
+    std::vector<uint64_t> tf(T);
+    HIP_TRY(hipMemcpy(tf.data(), j->tfp, (uint64_t)T * 8, hipMemcpyDeviceToHost));
+    std::unordered_multimap<uint64_t, uint32_t> pos;
+    pos.reserve(j->npos * 2 + 1);
+    for (uint32_t t = 0; t < j->npos; ++t) pos.emplace(tf[t], t);
+    for (uint32_t t = j->npos; t < T; ++t) {
+        auto rg = pos.equal_range(tf[t]);
+        for (auto it = rg.first; it != rg.second; ++it) {
+            const uint32_t p = it->second;
+            const uint64_t lp = j->off[p + 1] - j->off[p], ln = j->off[t + 1] - j->off[t];
+            if (lp != ln) continue;
+            std::vector<uint32_t> a(lp), b(ln);
+            if (spec->flags & LTL_SPEC_DEVICE) {
+                HIP_TRY(hipMemcpy(a.data(), spec->letters + j->off[p], lp * 4, hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(b.data(), spec->letters + j->off[t], ln * 4, hipMemcpyDeviceToHost));
+            } else {
+                memcpy(a.data(), spec->letters + j->off[p], lp * 4);
+                memcpy(b.data(), spec->letters + j->off[t], ln * 4);
+            }
+            if (a == b) return LTL_E_INCONSISTENT;
+        }
+    }
+    j->L.assign((size_t)j->bound + 1, LevelInfo());
+    return LTL_OK;
+}
+
+extern "C" int ltl_job_create(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
+                              ltl_job **out) {
+    if (!ctx || !spec || !ops || !out) return LTL_E_INVAL;
+    if (ctx->busy) return LTL_E_STATE;
+    if (spec->num_props < 1 || spec->num_props > 32) return LTL_E_INVAL;
+    const uint64_t T = (uint64_t)spec->num_pos + spec->num_neg;
+    if (T < 1 || T > 0x7FFFFFFFull || !spec->letters || !spec->offsets) return LTL_E_INVAL;
+    if (cost_bound < 1 || cost_bound >= LTL_MAX_LEVELS) return LTL_E_INVAL;
+    if (!(ops->op_mask & 1u) || (ops->op_mask >> 8)) return LTL_E_INVAL;
+    for (int k = 0; k < 8; ++k)
+        if ((ops->op_mask >> k) & 1u)
+            if (ops->cost[k] < 1 || ops->cost[k] >= LTL_MAX_LEVELS) return LTL_E_INVAL;
+    if (hipSetDevice(ctx->o.device) != hipSuccess) return LTL_E_DEVICE;
+    ltl_job *j = new (std::nothrow) ltl_job;
+    if (!j) return LTL_E_INVAL;
+    j->ctx = ctx;
+    j->A = spec->num_props;
+    j->T = (uint32_t)T;
+    j->npos = spec->num_pos;
+    j->nneg = spec->num_neg;
+    j->ops = *ops;
+    j->bound = cost_bound;
+    int st = job_setup(j, spec);
+    if (st != LTL_OK) {
+        for (auto &t : j->pending) { (void)hipEventDestroy(t.e0); (void)hipEventDestroy(t.e1); }
+        for (auto e : j->event_pool) (void)hipEventDestroy(e);
+        delete j;
+        return st;
+    }
+    ctx->busy = true;
+    *out = j;
+    return LTL_OK;
+}
+
+extern "C" void ltl_job_destroy(ltl_job *j) {
+    if (!j) return;
+    if (j->s) (void)hipStreamSynchronize(j->s); else (void)hipDeviceSynchronize();
+    for (auto &t : j->pending) { (void)hipEventDestroy(t.e0); (void)hipEventDestroy(t.e1); }
+    for (auto e : j->event_pool) (void)hipEventDestroy(e);
+    if (j->ctx) j->ctx->busy = false;
+    delete j;
+}
+
+// ---------------------------------------------------------------------------
+// Levels
+// ---------------------------------------------------------------------------
+static void add_block(LevelInfo &lv, int op, int la, int lb, const ltl_job *j, bool tri, uint32_t &cand,
+                      uint32_t &tile) {
+    Block b{};
+    b.op = (uint32_t)op;
+    b.tri = tri ? 1u : 0u;
+    const uint64_t R = j->R;
+    if (op == LTL_ATOM) {
+        b.na = j->A;
+        b.nb = 0;
+        b.a_gid = 0;
+        b.a_ptr = (uint64_t)(uintptr_t)j->atoms;
+    } else {
+        const LevelInfo &A = j->L[la];
+        b.na = A.n;
+        b.a_gid = A.gid_base;
+        b.a_ptr = (uint64_t)(uintptr_t)(j->arena + (uint64_t)A.gid_base * R * j->wbytes);
+        if (lb >= 0) {
+            const LevelInfo &B = j->L[lb];
+            b.nb = B.n;
+            b.b_gid = B.gid_base;
+            b.b_ptr = (uint64_t)(uintptr_t)(j->arena + (uint64_t)B.gid_base * R * j->wbytes);
+        }
+    }
+    uint64_t nc, nt;
+    if (b.nb == 0) {
+        nc = b.na;
+        b.nti = (b.na + TILE - 1) / TILE;
+        b.ntj = 1;
+        nt = b.nti;
+    } else if (!tri) {
+        nc = (uint64_t)b.na * b.nb;
+        b.nti = (b.na + TILE - 1) / TILE;
+        b.ntj = (b.nb + TILE - 1) / TILE;
+        nt = (uint64_t)b.nti * b.ntj;
+    } else {
+        nc = (uint64_t)b.na * (b.na - 1) / 2;
+        b.nti = b.ntj = (b.na + TILE - 1) / TILE;
+        nt = (uint64_t)b.nti * (b.nti + 1) / 2;
+    }
+    if (nc == 0) return;
+    b.cand_base = cand;
+    b.ncand = (uint32_t)std::min<uint64_t>(nc, 0xFFFFFFFFull);
+    b.tile_base = tile;
+    b.ntile = (uint32_t)std::min<uint64_t>(nt, 0xFFFFFFFFull);
+    // overflow of the 31-bit candidate space is checked by the caller on the u64 totals
+    cand = (uint32_t)std::min<uint64_t>((uint64_t)cand + nc, 0xFFFFFFFFull);
+    tile = (uint32_t)std::min<uint64_t>((uint64_t)tile + nt, 0xFFFFFFFFull);
+    lv.blocks.push_back(b);
+    lv.a_level.push_back(la);
+    lv.b_level.push_back(lb);
+}
+
+// Canonical block order of level c (Sec. 3 listing: ops F, U, G, X, And, Or, Not).
+static uint64_t build_blocks(ltl_job *j, uint32_t c, LevelInfo &lv, uint64_t &ntiles) {
+    lv.blocks.clear();
+    lv.a_level.clear();
+    lv.b_level.clear();
+    uint32_t cand = 0, tile = 0;
+    uint64_t total = 0, tiles = 0;
+    auto has = [&](int x) { return x >= 1 && (uint32_t)x < c && j->L[x].evaluated && j->L[x].n > 0; };
+    if (c == j->ops.cost[LTL_ATOM]) {
+        add_block(lv, LTL_ATOM, -1, -1, j, false, cand, tile);
+        total = j->A;
+        tiles = (j->A + TILE - 1) / TILE;
+    } else {
+        for (int op : ORDER) {
+            if (!((j->ops.op_mask >> op) & 1u)) continue;
+            const int x = (int)c - (int)j->ops.cost[op];
+            if (x < 1) continue;
+            if (is_unary(op)) {
+                if (!has(x)) continue;
+                total += j->L[x].n;
+                tiles += (j->L[x].n + TILE - 1) / TILE;
+                add_block(lv, op, x, -1, j, false, cand, tile);
+            } else if (op == LTL_U) {
+                for (int a = 1; a < x; ++a) {
+                    const int b = x - a;
+                    if (!has(a) || !has(b)) continue;
+                    total += (uint64_t)j->L[a].n * j->L[b].n;
+                    tiles += (uint64_t)((j->L[a].n + TILE - 1) / TILE) * ((j->L[b].n + TILE - 1) / TILE);
+                    add_block(lv, op, a, b, j, false, cand, tile);
+                }
+            } else {
+                for (int a = 1; a <= x - a; ++a) {
+                    const int b = x - a;
+                    if (!has(a) || !has(b)) continue;
+                    if (a < b) {
+                        total += (uint64_t)j->L[a].n * j->L[b].n;
+                        tiles += (uint64_t)((j->L[a].n + TILE - 1) / TILE) * ((j->L[b].n + TILE - 1) / TILE);
+                        add_block(lv, op, a, b, j, false, cand, tile);
+                    } else {
+                        const uint64_t n = j->L[a].n;
+                        if (n < 2) continue;
+                        total += n * (n - 1) / 2;
+                        const uint64_t nt = (n + TILE - 1) / TILE;
+                        tiles += nt * (nt + 1) / 2;
+                        add_block(lv, op, a, a, j, true, cand, tile);
+                    }
+                }
+            }
+        }
+    }
+    ntiles = tiles;
+    return total;
+}
+
+template <typename T>
+static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
+    uint64_t ntiles = 0;
+    const uint64_t C = build_blocks(j, c, lv, ntiles);
+    lv.cands = C;
+    lv.gid_base = (uint32_t)j->total_entries;
+    if (C == 0) {
+        lv.n = 0;
+        return LTL_OK;
+    }
+    if (C >= 0x7FFFFFFFull || lv.blocks.size() > (size_t)MAX_BLOCKS || ntiles >= 0xFFFFFFFFull) return LTL_E_OOM;
+    const uint32_t nc = (uint32_t)C;
+    const uint32_t nw = (nc + 31) / 32;
+    const uint32_t nchunks = (nw + SCAN_CHUNK_WORDS - 1) / SCAN_CHUNK_WORDS;
+    const uint64_t nslots = 1ull << j->slots_log2;
+    const uint32_t new_cap = (uint32_t)std::min<uint64_t>(C, nslots);
+
+    // per-level scratch at the top of the workspace
+    uint64_t top = j->wsb;
+    auto take_top = [&](uint64_t bytes) -> char * {
+        if (bytes + 256 > top) return nullptr;
+        top = (top - bytes) & ~255ull;
+        return j->ws + top;
+    };
+    uint32_t *cand_slot = (uint32_t *)take_top((uint64_t)nc * 4);
+    uint32_t *bitmap = (uint32_t *)take_top((uint64_t)nw * 4);
+    uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
+    uint32_t *coll_bits = (uint32_t *)take_top((uint64_t)nw * 4);
+    uint32_t *fb_bits = (uint32_t *)take_top((uint64_t)nw * 4);
+    uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
+    uint32_t *new_slots = (uint32_t *)take_top((uint64_t)new_cap * 4);
+    T *stage = (T *)take_top((uint64_t)j->R * sizeof(T));
+    const uint64_t arena_off = (uint64_t)(j->arena - j->ws);
+    const uint64_t arena_used = j->total_entries * j->cm_bytes;
+    if (!cand_slot || !bitmap || !wordpre || !coll_bits || !fb_bits || !chunks || !new_slots || !stage ||
+        arena_off + arena_used > top)
+        return LTL_E_OOM;
+    const uint64_t arena_free = top - (arena_off + arena_used);
+
+    HIP_TRY(hipMemcpyAsync(j->blocks_d, lv.blocks.data(), sizeof(Block) * lv.blocks.size(), hipMemcpyHostToDevice,
+                           j->s));
+    Counters init{};
+    init.first_sol = ~0ull;
+    HIP_TRY(hipMemcpyAsync(j->ctr, &init, sizeof(Counters), hipMemcpyHostToDevice, j->s));
+    HIP_TRY(hipMemsetAsync(bitmap, 0, (uint64_t)nw * 4, j->s));
+    HIP_TRY(hipMemsetAsync(coll_bits, 0, (uint64_t)nw * 4, j->s));
+    HIP_TRY(hipMemsetAsync(fb_bits, 0, (uint64_t)nw * 4, j->s));
+
+    LevelArgs<T> A{};
+    A.rows = make_rows<T>(j);
+    A.blocks = j->blocks_d;
+    A.nblocks = (uint32_t)lv.blocks.size();
+    A.ntiles = (uint32_t)ntiles;
+    A.tkey = j->tkey;
+    A.tval = j->tval;
+    A.slot_mask = (uint32_t)(nslots - 1);
+    const uint32_t fb = j->ctx->o.fp_bits;
+    A.fp_mask = (fb == 0 || fb >= 64) ? ~0ull : ((1ull << fb) - 1ull);
+    A.ctr = j->ctr;
+    A.cand_slot = cand_slot;
+    A.new_slots = new_slots;
+    A.new_cap = new_cap;
+    A.bitmap = bitmap;
+    A.wordpre = wordpre;
+    A.coll_bits = coll_bits;
+    A.fb_bits = fb_bits;
+    A.arena = (T *)j->arena;
+    A.level_base = lv.gid_base;
+    A.recipe = j->recipe;
+    A.stage = stage;
+    A.ucarry = (j->ctx->o.flags & LTL_CTX_U_CARRY) ? 1 : 0;
+
+    const uint32_t grid_tiles = (uint32_t)std::min<uint64_t>((ntiles + 3) / 4, MAX_GRID);
+    {
+        Timer tm(j, LTL_K_EVAL);
+        HIP_TRY(Launch<T>::level(A, j->mw, false, grid_tiles, j->s));
+    }
+    Counters hc;
+    if (int e = sync_read_counters(j, &hc)) return e;
+    if (hc.overflow) return LTL_E_OOM;
+    lv.first = (hc.first_sol == ~0ull) ? LTL_NO_SOLUTION : (uint64_t)hc.first_sol;
+    uint32_t n_new = hc.n_new;
+    const bool found = lv.first != LTL_NO_SOLUTION;
+    lv.stored = !found && c < j->bound;
+
+    // the level's new entries go to the arena (they serve as owners for the verify pass)
+    if ((uint64_t)n_new * j->cm_bytes > arena_free || j->total_entries + n_new > j->recipe_cap) return LTL_E_OOM;
+    {
+        Timer tm(j, LTL_K_COMPACT);
+        HIP_TRY(launch_mark(new_slots, n_new, j->tval, bitmap, j->s));
+        HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
+        HIP_TRY(launch_scatter(new_slots, n_new, j->tval, bitmap, wordpre, j->recipe, lv.gid_base, j->s));
+    }
+    const uint32_t grid_mat = std::max<uint32_t>(1, std::min<uint32_t>((n_new + 3) / 4, MAX_GRID));
+    if (n_new) {
+        Timer tm(j, LTL_K_MATERIALIZE);
+        HIP_TRY(Launch<T>::materialize(A, j->mw, n_new, grid_mat, j->s));
+    }
+    {
+        Timer tm(j, LTL_K_VERIFY);
+        HIP_TRY(Launch<T>::level(A, j->mw, true, grid_tiles, j->s));
+    }
+    if (int e = sync_read_counters(j, &hc)) return e;
+    lv.colliders = hc.n_coll;
+    if (hc.n_coll) {
+        // exact resolution of fingerprint collisions, in canonical order
+        {
+            Timer tm(j, LTL_K_FALLBACK);
+            HIP_TRY(Launch<T>::fallback(A, j->mw, nw, nc, j->s));
+        }
+        if (int e = sync_read_counters(j, &hc)) return e;
+        if (hc.overflow) return LTL_E_OOM;
+        n_new = hc.n_new;
+        if ((uint64_t)n_new * j->cm_bytes > arena_free || j->total_entries + n_new > j->recipe_cap) return LTL_E_OOM;
+        {
+            Timer tm(j, LTL_K_COMPACT);
+            HIP_TRY(launch_or_bits(bitmap, fb_bits, nw, j->s));
+            HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
+            HIP_TRY(launch_scatter(new_slots, n_new, j->tval, bitmap, wordpre, j->recipe, lv.gid_base, j->s));
+        }
+        {
+            Timer tm(j, LTL_K_MATERIALIZE);
+            HIP_TRY(Launch<T>::materialize(A, j->mw, n_new,
+                                           std::max<uint32_t>(1, std::min<uint32_t>((n_new + 3) / 4, MAX_GRID)),
+                                           j->s));
+        }
+    }
+    {
+        Timer tm(j, LTL_K_COMPACT);
+        HIP_TRY(launch_finalize(new_slots, n_new, j->tval, bitmap, wordpre, lv.gid_base, j->s));
+    }
+    HIP_TRY(hipStreamSynchronize(j->s));
+    lv.n = n_new;
+    j->total_entries += n_new;
+    return LTL_OK;
+}
+
+extern "C" int ltl_eval_level(ltl_job *j, uint32_t c, ltl_level_stats *stats) {
+    if (!j) return LTL_E_INVAL;
+    if (!j->searching || c != j->levels_done + 1 || c > j->bound) return LTL_E_STATE;
+    if (hipSetDevice(j->ctx->o.device) != hipSuccess) return LTL_E_DEVICE;
+    LevelInfo &lv = j->L[c];
+    lv = LevelInfo();
+    const double before = [&] { double s = 0; for (double v : j->kernel_ms) s += v; return s; }();
+    int st = LTL_OK;
+    if (c >= j->ops.cost[LTL_ATOM]) st = (j->wbits == 64) ? eval_level_t<uint64_t>(j, c, lv) : eval_level_t<uint32_t>(j, c, lv);
+    else lv.gid_base = (uint32_t)j->total_entries;
+    collect_times(j);
+    double after = 0;
+    for (double v : j->kernel_ms) after += v;
+    lv.ms = after - before;
+    if (st != LTL_OK) {
+        j->status = st;
+        j->searching = false;
+        return st;
+    }
+    lv.evaluated = true;
+    j->levels_done = c;
+    j->colliders += lv.colliders;
+    if (stats) {
+        stats->cost = c;
+        stats->stored = lv.stored ? 1u : 0u;
+        stats->candidates = lv.cands;
+        stats->new_entries = lv.n;
+        stats->first_solution = lv.first;
+        stats->colliders = lv.colliders;
+        stats->kernel_ms = lv.ms;
+    }
+    if (lv.first != LTL_NO_SOLUTION) {
+        j->status = LTL_OK;
+        j->searching = false;
+        j->sol_level = c;
+        j->sol_index = lv.first;
+        return LTL_OK;
+    }
+    if (c == j->bound) {
+        j->status = LTL_NOT_FOUND;
+        j->searching = false;
+        return LTL_OK;
+    }
+    lv.stored = true;
+    j->stored_entries += lv.n;
+    if (j->stored_entries > j->max_entries) {
+        j->status = LTL_E_OOM;
+        j->searching = false;
+        return LTL_E_OOM;
+    }
+    return LTL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Formula reconstruction from recipes (host decode of the canonical order)
+// ---------------------------------------------------------------------------
+static void host_cand_decode(const Block &b, uint32_t l, uint32_t &i, uint32_t &j) {
+    if (b.nb == 0) { i = l; j = 0; return; }
+    if (!b.tri) { i = l / b.nb; j = l % b.nb; return; }
+    const uint64_t n = b.na;
+    auto Tt = [&](uint64_t ii) -> uint64_t { return ii * n - ii * (ii + 1) / 2; };
+    uint64_t ii = 0;
+    uint64_t lo = 0, hi = n - 1;           // largest ii with Tt(ii) <= l
+    while (lo < hi) {
+        uint64_t mid = (lo + hi + 1) / 2;
+        if (Tt(mid) <= l) lo = mid; else hi = mid - 1;
+    }
+    ii = lo;
+    i = (uint32_t)ii;
+    j = (uint32_t)(l - Tt(ii) + ii + 1);
+}
+
+static int emit_candidate(ltl_job *j, uint32_t level, uint32_t x, ltl_node *buf, uint32_t cap, uint32_t &n,
+                          uint32_t &root);
+
+static int emit_entry(ltl_job *j, uint32_t level, uint32_t e, ltl_node *buf, uint32_t cap, uint32_t &n,
+                      uint32_t &root) {
+    const LevelInfo &lv = j->L[level];
+    if (e >= lv.n) return LTL_E_INVAL;
+    uint32_t x = 0;
+    HIP_TRY(hipMemcpy(&x, j->recipe + lv.gid_base + e, 4, hipMemcpyDeviceToHost));
+    return emit_candidate(j, level, x, buf, cap, n, root);
+}
+
+static int emit_candidate(ltl_job *j, uint32_t level, uint32_t x, ltl_node *buf, uint32_t cap, uint32_t &n,
+                          uint32_t &root) {
+    const LevelInfo &lv = j->L[level];
+    size_t bi = 0;
+    for (size_t k = 0; k < lv.blocks.size(); ++k)
+        if (lv.blocks[k].cand_base <= x) bi = k;
+    const Block &b = lv.blocks[bi];
+    if (x - b.cand_base >= b.ncand) return LTL_E_INVAL;
+    uint32_t i, jj;
+    host_cand_decode(b, x - b.cand_base, i, jj);
+    if (b.op == LTL_ATOM) {
+        if (n >= cap) return LTL_E_INVAL;
+        buf[n] = ltl_node{LTL_ATOM, i, 0};
+        root = n++;
+        return LTL_OK;
+    }
+    uint32_t ra = 0, rb = 0;
+    int st = emit_entry(j, (uint32_t)lv.a_level[bi], i, buf, cap, n, ra);
+    if (st) return st;
+    if (b.nb) {
+        st = emit_entry(j, (uint32_t)lv.b_level[bi], jj, buf, cap, n, rb);
+        if (st) return st;
+    }
+    if (n >= cap) return LTL_E_INVAL;
+    buf[n] = ltl_node{b.op, ra, b.nb ? rb : 0u};
+    root = n++;
+    return LTL_OK;
+}
+
+extern "C" int ltl_job_formula(ltl_job *j, uint32_t cost, uint64_t entry, ltl_node *buf, uint32_t cap,
+                               uint32_t *num_nodes) {
+    if (!j || !buf || !num_nodes || cost > j->levels_done || cost >= j->L.size()) return LTL_E_INVAL;
+    if (!j->L[cost].evaluated || entry >= j->L[cost].n) return LTL_E_INVAL;
+    uint32_t n = 0, root = 0;
+    int st = emit_entry(j, cost, (uint32_t)entry, buf, cap, n, root);
+    if (st) return st;
+    *num_nodes = n;
+    return LTL_OK;
+}
+
+extern "C" int ltl_job_dump_cm(ltl_job *j, uint32_t cost, uint64_t entry, uint8_t *pos_bits, uint64_t cap) {
+    if (!j || !pos_bits || cost > j->levels_done || cost >= j->L.size()) return LTL_E_INVAL;
+    const LevelInfo &lv = j->L[cost];
+    if (!lv.evaluated || entry >= lv.n || cap < j->TB) return LTL_E_INVAL;
+    std::vector<uint64_t> words(j->R);
+    const char *src = j->arena + (uint64_t)(lv.gid_base + entry) * j->cm_bytes;
+    if (j->wbits == 64) {
+        HIP_TRY(hipMemcpy(words.data(), src, j->cm_bytes, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<uint32_t> w32(j->R);
+        HIP_TRY(hipMemcpy(w32.data(), src, j->cm_bytes, hipMemcpyDeviceToHost));
+        for (uint32_t r = 0; r < j->R; ++r) words[r] = w32[r];
+    }
+    const uint64_t W = j->wbits;
+    uint64_t q = 0;
+    for (uint32_t t = 0; t < j->T; ++t) {
+        const uint64_t len = j->off[t + 1] - j->off[t];
+        for (uint64_t i = 0; i < len; ++i) {
+            const uint64_t w = words[j->row0[t] + i / W];
+            pos_bits[q++] = (uint8_t)((w >> (W - 1 - (i % W))) & 1ull);
+        }
+    }
+    return LTL_OK;
+}
+
+extern "C" int ltl_job_get_info(ltl_job *j, ltl_job_info *out) {
+    if (!j || !out) return LTL_E_INVAL;
+    out->word_bits = j->wbits;
+    out->rows = j->R;
+    out->cm_bytes = j->cm_bytes;
+    out->total_positions = j->TB;
+    out->hash_slots_log2 = j->slots_log2;
+    out->doubling_steps = j->ksteps;
+    out->arena_bytes = j->arena_region;
+    out->max_entries = j->max_entries;
+    return LTL_OK;
+}
+
+extern "C" int ltl_job_result(ltl_job *j, ltl_result *out) {
+    if (!j || !out) return LTL_E_INVAL;
+    memset(out, 0, sizeof(*out));
+    out->status = j->searching ? LTL_NOT_FOUND : j->status;
+    out->levels_done = j->levels_done;
+    out->solution_index = LTL_NO_SOLUTION;
+    for (uint32_t c = 1; c <= j->levels_done && c < LTL_MAX_LEVELS; ++c) {
+        out->level_new[c] = j->L[c].n;
+        out->level_candidates[c] = j->L[c].cands;
+        out->level_ms[c] = j->L[c].ms;
+    }
+    out->colliders = j->colliders;
+    for (int k = 0; k < LTL_K_KINDS; ++k) {
+        out->kernel_ms[k] = j->kernel_ms[k];
+        out->kernel_launches[k] = j->kernel_launches[k];
+    }
+    if (!j->searching && j->status == LTL_OK) {
+        out->cost = j->sol_level;
+        out->solution_index = j->sol_index;
+        uint32_t n = 0, root = 0;
+        int st = emit_candidate(j, j->sol_level, (uint32_t)j->sol_index, out->nodes, LTL_MAX_NODES, n, root);
+        if (st) return st;
+        out->num_nodes = n;
+    }
+    return out->status;
+}
+
+extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
+                         ltl_result *out) {
+    if (!out) return LTL_E_INVAL;
+    memset(out, 0, sizeof(*out));
+    out->solution_index = LTL_NO_SOLUTION;
+    ltl_job *j = nullptr;
+    int st = ltl_job_create(ctx, spec, ops, cost_bound, &j);
+    if (st != LTL_OK) {
+        out->status = st;
+        return st;
+    }
+    for (uint32_t c = 1; c <= cost_bound; ++c) {
+        st = ltl_eval_level(j, c, nullptr);
+        if (st != LTL_OK || !j->searching) break;
+    }
+    st = ltl_job_result(j, out);
+    ltl_job_destroy(j);
+    return st;
+}

@@ -1,0 +1,103 @@
+// Internal structures shared by the host runtime and the gfx950 kernels of the
+// LTL learner.  Not part of the public C-ABI (include/ltl.h).
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace ltl {
+
+// Language-cache hash table slot values (tval[]).  Keys (tkey[]) are 64-bit
+// fingerprints of a characteristic matrix; 0 marks an empty slot.
+constexpr uint32_t VAL_OPEN = 0x7FFFFFFFu;     // empty slot / group not yet elected
+constexpr uint32_t VAL_SETTLED = 0x80000000u;  // tag: low 31 bits = global entry id
+constexpr uint32_t NO_SLOT = 0xFFFFFFFFu;
+constexpr uint32_t MAX_PROBES = 1u << 16;
+constexpr int MAX_BLOCKS = 512;                // op x split blocks per level
+constexpr int TILE = 4;                        // children per tile side
+
+// One block of the canonical candidate order of a level: one connective and,
+// for binary connectives, one split (a, b) of the remaining cost.
+struct Block {
+    uint32_t op;          // LTL_ATOM .. LTL_U
+    uint32_t tri;         // AND/OR with a == b: pairs (i, j) with i < j of one level
+    uint32_t na, nb;      // entries of the child levels (nb = 0 for unary)
+    uint32_t cand_base;   // canonical index of the block's first candidate
+    uint32_t ncand;       // candidates in the block
+    uint32_t tile_base;   // first tile of the block in the level's tile list
+    uint32_t ntile;       // tiles of the block
+    uint32_t nti, ntj;    // tile grid (rows of a-tiles, columns of b-tiles)
+    uint32_t a_gid, b_gid;   // global entry id of the first a / b entry (ATOM: prop 0)
+    uint64_t a_ptr;       // device address of the first a matrix
+    uint64_t b_ptr;       // device address of the first b matrix (0 for unary)
+};
+
+struct Counters {
+    unsigned long long first_sol;   // smallest separating canonical index (atomicMin)
+    uint32_t n_new;                 // new fingerprint groups claimed this level
+    uint32_t overflow;              // hash table or list capacity exceeded
+    uint32_t n_coll;                // candidates whose full compare failed
+    uint32_t letter_or;             // OR of all letters (validation)
+    uint32_t n_fallback_new;        // representatives added by the exact fallback
+    uint32_t pad[9];
+};
+
+template <typename T>
+struct Rows {
+    const T *valid;          // valid position bits of each word
+    const T *sepm;           // top bit for the first word of a live trace, else 0
+    const T *sepw;           // expected value of that bit: set for P traces
+    const uint64_t *nxt;     // lanes (in the row block) holding later words of the same trace
+    const uint64_t *key;     // fingerprint keys: 1 (W=32) or 2 (W=64) per row
+    uint32_t R, NB;          // words per matrix, 64-word row blocks
+    uint32_t ksteps;         // U doubling steps = ceil(log2(longest trace))
+    uint32_t maxw;           // longest trace in words
+};
+
+template <typename T>
+struct LevelArgs {
+    Rows<T> rows;
+    const Block *blocks;
+    uint32_t nblocks, ntiles;
+    unsigned long long *tkey;
+    uint32_t *tval;
+    uint32_t slot_mask;
+    uint64_t fp_mask;
+    Counters *ctr;
+    uint32_t *cand_slot;     // per candidate: its hash slot (or NO_SLOT)
+    uint32_t *new_slots;     // slots claimed this level
+    uint32_t new_cap;
+    uint32_t *bitmap;        // per candidate: group representative bit
+    uint32_t *wordpre;       // exclusive prefix of popcounts of bitmap words
+    uint32_t *coll_bits;     // per candidate: full compare failed
+    uint32_t *fb_bits;       // per candidate: representative found by the exact fallback
+    T *arena;
+    uint32_t level_base;     // global id of the level's first entry
+    uint32_t *recipe;        // per global entry: canonical candidate index in its level
+    T *stage;                // R words of scratch for the fallback
+    int ucarry;
+};
+
+
+template <typename T>
+struct Launch {
+    static hipError_t level(const LevelArgs<T> &A, bool mw, bool verify, uint32_t grid, hipStream_t s);
+    static hipError_t materialize(const LevelArgs<T> &A, bool mw, uint32_t n, uint32_t grid, hipStream_t s);
+    static hipError_t fallback(const LevelArgs<T> &A, bool mw, uint32_t nwords, uint32_t ncand, hipStream_t s);
+    static hipError_t pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
+                           const uint32_t *row_word, uint32_t R, uint32_t nprops, T *atoms, Counters *ctr,
+                           hipStream_t s);
+};
+
+hipError_t launch_scan(const uint32_t *bits, uint32_t nw, uint32_t *chunk_sums, uint32_t *wordpre, hipStream_t s);
+hipError_t launch_mark(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, uint32_t *bitmap, hipStream_t s);
+hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipStream_t s);
+hipError_t launch_scatter(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, const uint32_t *bitmap,
+                          const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base, hipStream_t s);
+hipError_t launch_finalize(const uint32_t *new_slots, uint32_t n, uint32_t *tval, const uint32_t *bitmap,
+                           const uint32_t *wordpre, uint32_t level_base, hipStream_t s);
+hipError_t launch_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t nslots, hipStream_t s);
+hipError_t launch_trace_fp(const uint32_t *letters, const uint64_t *offsets, uint32_t ntr, uint64_t *out,
+                           hipStream_t s);
+constexpr uint32_t SCAN_CHUNK_WORDS = 2048;   // bitmap words per scan block
+
+}  // namespace ltl

@@ -1,0 +1,903 @@
+// gfx950 kernels of the enumerative LTL learner.
+//
+// Data layout (all inside the caller's workspace):
+//   * A characteristic matrix (CM, Sec. 4) is R machine words, contiguous: the
+//     characteristic sequences of all traces in the fixed order P then N.  A
+//     trace of n positions takes ceil(n / W) consecutive words (W = 32 or 64),
+//     position 0 in the most significant bit of its first word (the paper's
+//     pictures: X is a left shift).  Bits past the end of a trace are 0.
+//     Traces never straddle a 64-word row block, so the words of one trace sit
+//     in consecutive lanes of one wave.
+//   * Stored levels live in one arena: entry g (global id) at arena + g * R.
+//   * Waves work with lanes across the words of a matrix ("rows"): a wave
+//     evaluates a tile of up to 4 x 4 candidates, streaming row blocks of 64
+//     words, so every load and store of a matrix is a coalesced 256/512-byte
+//     access, whether it reads a child, a stored owner or writes a new entry.
+//
+// Connectives as branch-free word operations (Sec. 4, App. B), lane = word:
+//   NOT  : ~w & valid
+//   AND/OR: bitwise
+//   X    : w << 1, with the next word's top bit carried in (wave ballot)
+//   F    : w | -w (the "round up to a power of two minus one" reading of the
+//          footnote in Sec. 4, MSB-first), or all-valid if a later word of the
+//          trace is non-zero (wave ballot)
+//   G    : valid & ~F(valid & ~w)   (always = not eventually not, within the trace)
+//   U    : log2(n) shift-by-power-of-two doubling of App. B:
+//             cs2 |= cs1 & (cs2 << s);  cs1 &= cs1 << s;   s = 1, 2, 4, ...
+//          with cross-word shifts through lane shuffles; optionally a
+//          carry-propagating add (psi | phi) + psi whose carry vector is the
+//          until-chain psi_i | (phi_i & U_{i+1}).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ltl.h"
+#include "ltl_internal.h"
+
+namespace ltl {
+
+constexpr int OP_UC = 8;   // U computed by the carry-chain adder
+
+template <typename T> struct Word;
+template <> struct Word<uint32_t> { static constexpr int BITS = 32; };
+template <> struct Word<uint64_t> { static constexpr int BITS = 64; };
+
+// ---------------------------------------------------------------------------
+// Row metadata and kernel arguments
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RowMeta {
+    T v, sm, sw;
+    uint64_t nx, hn, k0, k1;
+};
+
+template <typename T, bool MW>
+__device__ __forceinline__ RowMeta<T> load_meta(const Rows<T> &rw, uint32_t r, int lane) {
+    RowMeta<T> m;
+    m.v = rw.valid[r];
+    m.sm = rw.sepm[r];
+    m.sw = rw.sepw[r];
+    if constexpr (MW) {
+        m.nx = rw.nxt[r];
+        m.hn = __ballot((m.nx & (2ull << lane)) != 0ull);
+    } else {
+        m.nx = 0;
+        m.hn = 0;
+    }
+    if constexpr (sizeof(T) == 8) {       // two 32-bit halves, two keys per row
+        m.k0 = rw.key[2 * (size_t)r];
+        m.k1 = rw.key[2 * (size_t)r + 1];
+    } else {
+        m.k0 = rw.key[r];
+        m.k1 = 0;
+    }
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Connectives
+// ---------------------------------------------------------------------------
+
+// Shift toward earlier positions by s within each trace: bits of later words of
+// the same trace move in; nothing crosses into another trace.
+template <typename T, bool MW>
+__device__ __forceinline__ T shl_pos(T x, uint32_t s, const RowMeta<T> &m, int lane) {
+    if constexpr (!MW) {
+        return x << s;
+    } else {
+        if (s < 64) {
+            uint64_t nw = __shfl_down((unsigned long long)x, 1u);
+            if (!(m.nx & (2ull << lane))) nw = 0;
+            return (x << s) | (nw >> (64u - s));
+        } else {
+            uint32_t q = s >> 6;
+            uint32_t src = (uint32_t)lane + q;
+            uint64_t v = __shfl((unsigned long long)x, (int)(src & 63u));
+            bool in = src < 64u && ((m.nx >> (src & 63u)) & 1ull);
+            return in ? (T)v : (T)0;
+        }
+    }
+}
+
+template <typename T, bool MW>
+__device__ __forceinline__ T op_F(T x, const RowMeta<T> &m) {
+    T f = x | (T)((T)0 - x);
+    if constexpr (MW) {
+        uint64_t nz = __ballot(x != 0);
+        if (nz & m.nx) f = m.v;
+    }
+    return f;
+}
+
+template <typename T, bool MW>
+__device__ __forceinline__ T op_X(T x, const RowMeta<T> &m, int lane) {
+    if constexpr (!MW) {
+        return x << 1;
+    } else {
+        uint64_t top = __ballot((x >> 63) != 0);
+        T cin = (top & m.nx & (2ull << lane)) ? (T)1 : (T)0;
+        return (x << 1) | cin;
+    }
+}
+
+template <typename T, bool MW>
+__device__ __forceinline__ T op_U(T phi, T psi, const RowMeta<T> &m, uint32_t k, int lane) {
+    T c1 = phi, c2 = psi;
+    for (uint32_t i = 0; i < k; ++i) {
+        uint32_t s = 1u << i;
+        c2 |= c1 & shl_pos<T, MW>(c2, s, m, lane);
+        if (i + 1 < k) c1 &= shl_pos<T, MW>(c1, s, m, lane);
+    }
+    return c2;
+}
+
+template <typename T, bool MW>
+__device__ __forceinline__ T op_UC(T phi, T psi, const RowMeta<T> &m, uint32_t maxw, int lane) {
+    if constexpr (!MW && sizeof(T) == 4) {
+        uint64_t A = (uint64_t)(phi | psi), B = (uint64_t)psi;
+        uint64_t C = (A + B) ^ A ^ B;   // carry into each bit; bit 32 = carry out
+        return (T)(C >> 1);
+    } else if constexpr (!MW) {
+        uint64_t A = phi | psi, B = psi;
+        uint64_t S = A + B;
+        uint64_t cout = S < A ? 1ull : 0ull;
+        return ((S ^ A ^ B) >> 1) | (cout << 63);
+    } else {
+        uint64_t A = phi | psi, B = psi;
+        uint64_t S = A + B;
+        bool g = S < A;                    // carry out without carry in
+        bool p = (S == ~0ull);             // carry out iff carry in
+        uint64_t Gm = __ballot(g), Pm = __ballot(p);
+        uint64_t Cm = 0;                   // carry into each lane from the next word of its trace
+        for (uint32_t it = 1; it < maxw; ++it) Cm = ((Gm | (Pm & Cm)) >> 1) & m.hn;
+        uint64_t cin = (Cm >> lane) & 1ull;
+        uint64_t S2 = S + cin;
+        uint64_t cout = (uint64_t)g | ((uint64_t)p & cin);
+        return ((S2 ^ A ^ B) >> 1) | (cout << 63);
+    }
+}
+
+template <typename T, bool MW, int OP>
+__device__ __forceinline__ T apply(T a, T b, const RowMeta<T> &m, const Rows<T> &rw, int lane) {
+    if constexpr (OP == LTL_ATOM) return a;
+    else if constexpr (OP == LTL_NOT) return ~a & m.v;
+    else if constexpr (OP == LTL_AND) return a & b;
+    else if constexpr (OP == LTL_OR) return a | b;
+    else if constexpr (OP == LTL_X) return op_X<T, MW>(a, m, lane);
+    else if constexpr (OP == LTL_F) return op_F<T, MW>(a, m);
+    else if constexpr (OP == LTL_G) return m.v & ~op_F<T, MW>((T)(m.v & ~a), m);
+    else if constexpr (OP == LTL_U) return op_U<T, MW>(a, b, m, rw.ksteps, lane);
+    else return op_UC<T, MW>(a, b, m, rw.maxw, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Fingerprint: fp = sum over 32-bit halves h of premix(h) * key (mod 2^64),
+// keys random odd 64-bit numbers per row.  premix is the bijection
+// y = w ^ w>>8; y ^ y>>16, which keeps the 2-adic valuation of any difference
+// below 8, so two matrices differing anywhere collide with probability about
+// 2^-56 over the keys.  Only a function of the matrix matters: every match is
+// confirmed by a full compare.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t premix(uint32_t w) {
+    uint32_t y = w ^ (w >> 8);
+    return y ^ (y >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ void fp_add(uint64_t &acc, T w, const RowMeta<T> &m) {
+    if constexpr (sizeof(T) == 4) {
+        acc += (uint64_t)premix((uint32_t)w) * m.k0;
+    } else {
+        acc += (uint64_t)premix((uint32_t)w) * m.k0;
+        acc += (uint64_t)premix((uint32_t)(w >> 32)) * m.k1;
+    }
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor((unsigned long long)x, o);
+    return x;
+}
+
+// Stafford's "Mix13" 64-bit finalizer (as used by SplitMix64).
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t finish_fp(uint64_t s, uint64_t mask) {
+    s &= mask;
+    return s ? s : 1ull;
+}
+
+// ---------------------------------------------------------------------------
+// Canonical order: blocks, tiles, candidate indices
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_block_tile(const Block *B, int nb, uint32_t t) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (B[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int find_block_cand(const Block *B, int nb, uint32_t x) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (B[mid].cand_base <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void decode_tile(const Block &b, uint32_t lt, uint32_t &i0, uint32_t &j0) {
+    if (b.nb == 0) { i0 = lt * TILE; j0 = 0; return; }
+    if (!b.tri) { i0 = (lt / b.ntj) * TILE; j0 = (lt % b.ntj) * TILE; return; }
+    const uint64_t n = b.nti;
+    // row it holds n - it tiles; start(it) = it*n - it*(it-1)/2
+    double nn = 2.0 * (double)n + 1.0;
+    double disc = nn * nn - 8.0 * (double)lt;
+    uint64_t it = (uint64_t)((nn - sqrt(disc > 0 ? disc : 0.0)) * 0.5);
+    if (it >= n) it = n - 1;
+    auto start = [&](uint64_t i) -> uint64_t { return i * n - (i * (i ? i - 1 : 0)) / 2; };
+    while (it > 0 && start(it) > lt) --it;
+    while (it + 1 < n && start(it + 1) <= lt) ++it;
+    uint64_t jt = it + (lt - start(it));
+    i0 = (uint32_t)it * TILE;
+    j0 = (uint32_t)jt * TILE;
+}
+
+__host__ __device__ __forceinline__ uint32_t cand_index(const Block &b, uint32_t i, uint32_t j) {
+    if (b.nb == 0) return b.cand_base + i;
+    if (!b.tri) return b.cand_base + (uint32_t)((uint64_t)i * b.nb + j);
+    uint64_t n = b.na;
+    return b.cand_base + (uint32_t)((uint64_t)i * n - (uint64_t)i * (i + 1) / 2 + (j - i - 1));
+}
+
+// Inverse of cand_index within a block: local index l -> (i, j).
+__host__ __device__ __forceinline__ void cand_decode(const Block &b, uint32_t l, uint32_t &i, uint32_t &j) {
+    if (b.nb == 0) { i = l; j = 0; return; }
+    if (!b.tri) { i = l / b.nb; j = l % b.nb; return; }
+    const uint64_t n = b.na;
+    auto T = [&](uint64_t ii) -> uint64_t { return ii * n - ii * (ii + 1) / 2; };
+    double nn = 2.0 * (double)n - 1.0;
+    double disc = nn * nn - 8.0 * (double)l;
+    uint64_t ii = (uint64_t)((nn - sqrt(disc > 0 ? disc : 0.0)) * 0.5);
+    if (ii >= n) ii = n - 1;
+    while (ii > 0 && T(ii) > l) --ii;
+    while (ii + 1 < n && T(ii + 1) <= l) ++ii;
+    i = (uint32_t)ii;
+    j = (uint32_t)(l - T(ii) + ii + 1);
+}
+
+__device__ __forceinline__ uint32_t rank_of(const uint32_t *bitmap, const uint32_t *wordpre, uint32_t x) {
+    uint32_t w = bitmap[x >> 5];
+    uint32_t below = (x & 31u) ? (w & ((1u << (x & 31u)) - 1u)) : 0u;
+    return wordpre[x >> 5] + (uint32_t)__popc(below);
+}
+
+// ---------------------------------------------------------------------------
+// Language-cache probe (one lane per candidate).  A slot whose key equals the
+// fingerprint is either a settled entry of an earlier level (the candidate is a
+// presumed duplicate of it, confirmed by the verify pass) or the group of this
+// level (the smallest canonical index wins by atomicMin).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx) {
+    uint32_t h = (uint32_t)(mix64(fp) >> 32) & A.slot_mask;
+    for (uint32_t n = 0; n < MAX_PROBES; ++n) {
+        unsigned long long k = __hip_atomic_load(&A.tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == 0ull) {
+            unsigned long long prev = atomicCAS(&A.tkey[h], 0ull, (unsigned long long)fp);
+            if (prev == 0ull) {
+                atomicMin(&A.tval[h], idx);
+                uint32_t pos = atomicAdd(&A.ctr->n_new, 1u);
+                if (pos < A.new_cap) A.new_slots[pos] = h;
+                else atomicOr(&A.ctr->overflow, 1u);
+                return h;
+            }
+            k = prev;
+        }
+        if (k == (unsigned long long)fp) {
+            uint32_t v = __hip_atomic_load(&A.tval[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!(v & VAL_SETTLED)) atomicMin(&A.tval[h], idx);
+            return h;
+        }
+        h = (h + 1) & A.slot_mask;
+    }
+    atomicOr(&A.ctr->overflow, 1u);
+    return NO_SLOT;
+}
+
+// ---------------------------------------------------------------------------
+// Level evaluation tile: TI x TJ candidates of one block (TJ = 1 for unary).
+// EVAL   : fingerprint + separation, probe/claim in the language cache.
+// VERIFY : recompute, compare in full with the presumed owner.
+// ---------------------------------------------------------------------------
+template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY>
+__device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane) {
+    constexpr int NP = TI * TJ;
+    constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
+    const uint32_t R = A.rows.R;
+    const uint32_t nbj = b.tri ? b.na : b.nb;
+    const T *ap[TI];
+    const T *bp[TJ];
+#pragma unroll
+    for (int ii = 0; ii < TI; ++ii) {
+        uint32_t i = min(i0 + ii, b.na - 1);
+        ap[ii] = (const T *)b.a_ptr + (size_t)i * R;
+    }
+#pragma unroll
+    for (int jj = 0; jj < TJ; ++jj) {
+        if constexpr (BIN) {
+            uint32_t j = min(j0 + jj, nbj - 1);
+            bp[jj] = (const T *)b.b_ptr + (size_t)j * R;
+        } else {
+            bp[jj] = nullptr;
+        }
+    }
+    bool ok[NP];
+    uint32_t idx[NP];
+#pragma unroll
+    for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < TJ; ++jj) {
+            const int p = ii * TJ + jj;
+            uint32_t i = i0 + ii, j = j0 + jj;
+            bool v = i < b.na;
+            if constexpr (BIN) v = v && (b.tri ? (j < b.na && j > i) : (j < b.nb));
+            ok[p] = v;
+            idx[p] = v ? cand_index(b, i, j) : 0u;
+        }
+
+    if constexpr (!VERIFY) {
+        uint64_t acc[NP];
+        T viol[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) { acc[p] = 0; viol[p] = 0; }
+        for (uint32_t blk = 0; blk < A.rows.NB; ++blk) {
+            const uint32_t r = blk * 64u + (uint32_t)lane;
+            RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+            T av[TI], bv[TJ];
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii) av[ii] = ap[ii][r];
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) bv[jj] = BIN ? bp[jj][r] : (T)0;
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < TJ; ++jj) {
+                    const int p = ii * TJ + jj;
+                    T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
+                    viol[p] |= (w ^ m.sw) & m.sm;
+                    fp_add<T>(acc[p], w, m);
+                }
+        }
+        uint64_t my_fp = 0;
+        uint32_t my_idx = 0;
+        bool my_ok = false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            uint64_t s = wave_sum(acc[p]);
+            bool bad = __ballot(viol[p] != 0) != 0ull;
+            if (ok[p] && !bad && lane == 0) atomicMin(&A.ctr->first_sol, (unsigned long long)idx[p]);
+            if (lane == p) { my_fp = s; my_idx = idx[p]; my_ok = ok[p]; }
+        }
+        if (my_ok) {
+            uint64_t fp = finish_fp(my_fp, A.fp_mask);
+            A.cand_slot[my_idx] = probe_claim<T>(A, fp, my_idx);
+        }
+    } else {
+        const T *tg[NP];
+        T diff[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            diff[p] = 0;
+            tg[p] = nullptr;
+            if (!ok[p]) continue;
+            uint32_t h = A.cand_slot[idx[p]];
+            if (h == NO_SLOT) continue;
+            uint32_t v = A.tval[h];
+            uint32_t g;
+            if (v & VAL_SETTLED) g = v & ~VAL_SETTLED;
+            else if (v == idx[p]) continue;                       // the representative itself
+            else g = A.level_base + rank_of(A.bitmap, A.wordpre, v);
+            tg[p] = A.arena + (size_t)g * R;
+        }
+        for (uint32_t blk = 0; blk < A.rows.NB; ++blk) {
+            const uint32_t r = blk * 64u + (uint32_t)lane;
+            RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+            T av[TI], bv[TJ];
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii) av[ii] = ap[ii][r];
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) bv[jj] = BIN ? bp[jj][r] : (T)0;
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < TJ; ++jj) {
+                    const int p = ii * TJ + jj;
+                    T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
+                    if (tg[p]) diff[p] |= w ^ tg[p][r];
+                }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            bool mism = __ballot(diff[p] != 0) != 0ull;
+            if (mism && lane == 0) atomicOr(&A.coll_bits[idx[p] >> 5], 1u << (idx[p] & 31u));
+            if (mism && lane == 0) atomicAdd(&A.ctr->n_coll, 1u);
+        }
+    }
+}
+
+template <typename T, bool MW, bool VERIFY>
+__global__ __launch_bounds__(256) void k_level(LevelArgs<T> A) {
+    const int lane = (int)__lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t t = wave; t < A.ntiles; t += nwaves) {
+        const int bi = find_block_tile(A.blocks, (int)A.nblocks, t);
+        const Block b = A.blocks[bi];
+        uint32_t i0, j0;
+        decode_tile(b, t - b.tile_base, i0, j0);
+        switch (b.op) {
+        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane); break;
+        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane); break;
+        case LTL_U:
+            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+            else run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+            break;
+        default: break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One candidate's matrix, by canonical index (materialize, fallback)
+// ---------------------------------------------------------------------------
+template <typename T, bool MW, int OP>
+__device__ __forceinline__ T cand_word(const LevelArgs<T> &A, const T *pa, const T *pb, uint32_t r, int lane,
+                                       const RowMeta<T> &m) {
+    constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
+    return apply<T, MW, OP>(pa[r], BIN ? pb[r] : (T)0, m, A.rows, lane);
+}
+
+template <typename T>
+__device__ __forceinline__ void cand_children(const LevelArgs<T> &A, uint32_t x, int &op, const T *&pa,
+                                              const T *&pb) {
+    const int bi = find_block_cand(A.blocks, (int)A.nblocks, x);
+    const Block &b = A.blocks[bi];
+    uint32_t i, j;
+    cand_decode(b, x - b.cand_base, i, j);
+    op = (int)b.op;
+    if (op == LTL_U && A.ucarry) op = OP_UC;
+    pa = (const T *)b.a_ptr + (size_t)i * A.rows.R;
+    pb = b.nb ? (const T *)b.b_ptr + (size_t)j * A.rows.R : pa;
+    if (b.tri) pb = (const T *)b.b_ptr + (size_t)j * A.rows.R;
+}
+
+// Writes (or compares) one candidate's matrix, one row block at a time.  The
+// whole wave must call it (connectives use wave ballots and shuffles).
+template <typename T, bool MW, int OP>
+__device__ void cand_rowblock(const LevelArgs<T> &A, const T *pa, const T *pb, uint32_t blk, int lane,
+                              T *dst) {
+    const uint32_t r = blk * 64u + (uint32_t)lane;
+    RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+    dst[r] = cand_word<T, MW, OP>(A, pa, pb, r, lane, m);
+}
+
+template <typename T, bool MW>
+__device__ void cand_write_block(const LevelArgs<T> &A, int op, const T *pa, const T *pb, uint32_t blk, int lane,
+                                 T *dst) {
+    switch (op) {
+    case LTL_ATOM: cand_rowblock<T, MW, LTL_ATOM>(A, pa, pb, blk, lane, dst); break;
+    case LTL_NOT:  cand_rowblock<T, MW, LTL_NOT>(A, pa, pb, blk, lane, dst); break;
+    case LTL_X:    cand_rowblock<T, MW, LTL_X>(A, pa, pb, blk, lane, dst); break;
+    case LTL_F:    cand_rowblock<T, MW, LTL_F>(A, pa, pb, blk, lane, dst); break;
+    case LTL_G:    cand_rowblock<T, MW, LTL_G>(A, pa, pb, blk, lane, dst); break;
+    case LTL_AND:  cand_rowblock<T, MW, LTL_AND>(A, pa, pb, blk, lane, dst); break;
+    case LTL_OR:   cand_rowblock<T, MW, LTL_OR>(A, pa, pb, blk, lane, dst); break;
+    case LTL_U:    cand_rowblock<T, MW, LTL_U>(A, pa, pb, blk, lane, dst); break;
+    default:       cand_rowblock<T, MW, OP_UC>(A, pa, pb, blk, lane, dst); break;
+    }
+}
+
+// New entries of the level: entry e holds the representative recipe[base + e].
+template <typename T, bool MW>
+__global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t n_entries) {
+    const int lane = (int)__lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t e = wave; e < n_entries; e += nwaves) {
+        const uint32_t x = A.recipe[A.level_base + e];
+        int op;
+        const T *pa, *pb;
+        cand_children<T>(A, x, op, pa, pb);
+        T *dst = A.arena + (size_t)(A.level_base + e) * A.rows.R;
+        for (uint32_t blk = 0; blk < A.rows.NB; ++blk) cand_write_block<T, MW>(A, op, pa, pb, blk, lane, dst);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact fallback for fingerprint collisions (rare; forced in tests by
+// truncating fingerprints).  One workgroup handles the colliders strictly in
+// canonical order: each is compared in full with every cached matrix of equal
+// fingerprint along its probe sequence; if none is equal it becomes a new
+// representative in the first empty slot.  Sequential, hence deterministic.
+// ---------------------------------------------------------------------------
+template <typename T, bool MW>
+__device__ bool fb_equal(const LevelArgs<T> &A, const T *target, int t_op, const T *t_pa, const T *t_pb,
+                         uint32_t *s_flag, int lane, int wv, int nw) {
+    // compares A.stage with `target` (stored) or with the recomputation of (t_op, t_pa, t_pb)
+    if (threadIdx.x == 0) *s_flag = 0;
+    __syncthreads();
+    for (uint32_t blk = (uint32_t)wv; blk < A.rows.NB; blk += (uint32_t)nw) {
+        const uint32_t r = blk * 64u + (uint32_t)lane;
+        T tw;
+        if (target) {
+            tw = target[r];
+        } else {
+            RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+            switch (t_op) {
+            case LTL_ATOM: tw = cand_word<T, MW, LTL_ATOM>(A, t_pa, t_pb, r, lane, m); break;
+            case LTL_NOT:  tw = cand_word<T, MW, LTL_NOT>(A, t_pa, t_pb, r, lane, m); break;
+            case LTL_X:    tw = cand_word<T, MW, LTL_X>(A, t_pa, t_pb, r, lane, m); break;
+            case LTL_F:    tw = cand_word<T, MW, LTL_F>(A, t_pa, t_pb, r, lane, m); break;
+            case LTL_G:    tw = cand_word<T, MW, LTL_G>(A, t_pa, t_pb, r, lane, m); break;
+            case LTL_AND:  tw = cand_word<T, MW, LTL_AND>(A, t_pa, t_pb, r, lane, m); break;
+            case LTL_OR:   tw = cand_word<T, MW, LTL_OR>(A, t_pa, t_pb, r, lane, m); break;
+            case LTL_U:    tw = cand_word<T, MW, LTL_U>(A, t_pa, t_pb, r, lane, m); break;
+            default:       tw = cand_word<T, MW, OP_UC>(A, t_pa, t_pb, r, lane, m); break;
+            }
+        }
+        if (__ballot(tw != A.stage[r]) != 0ull && lane == 0) atomicOr(s_flag, 1u);
+    }
+    __syncthreads();
+    bool eq = (*s_flag == 0);
+    __syncthreads();
+    return eq;
+}
+
+template <typename T, bool MW>
+__global__ __launch_bounds__(256) void k_fallback(LevelArgs<T> A, uint32_t nwords, uint32_t ncand) {
+    __shared__ unsigned long long s_part[4];
+    __shared__ uint32_t s_flag;
+    __shared__ unsigned long long s_key;
+    __shared__ uint32_t s_val;
+    const int lane = (int)__lane_id();
+    const int wv = (int)(threadIdx.x >> 6);
+    const int nw = (int)(blockDim.x >> 6);
+    for (uint32_t wi = 0; wi < nwords; ++wi) {
+        uint32_t bits = A.coll_bits[wi];
+        while (bits) {
+            const uint32_t x = wi * 32u + (uint32_t)__ffs(bits) - 1u;
+            bits &= bits - 1u;
+            if (x >= ncand) break;
+            int op;
+            const T *pa, *pb;
+            cand_children<T>(A, x, op, pa, pb);
+            // stage the collider's matrix and its fingerprint
+            uint64_t acc = 0;
+            for (uint32_t blk = (uint32_t)wv; blk < A.rows.NB; blk += (uint32_t)nw) {
+                cand_write_block<T, MW>(A, op, pa, pb, blk, lane, A.stage);
+            }
+            __syncthreads();
+            for (uint32_t blk = (uint32_t)wv; blk < A.rows.NB; blk += (uint32_t)nw) {
+                const uint32_t r = blk * 64u + (uint32_t)lane;
+                RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+                fp_add<T>(acc, A.stage[r], m);
+            }
+            acc = wave_sum(acc);
+            if (lane == 0) s_part[wv] = acc;
+            __syncthreads();
+            uint64_t fp = 0;
+            for (int k = 0; k < nw; ++k) fp += s_part[k];
+            fp = finish_fp(fp, A.fp_mask);
+            uint32_t h = (uint32_t)(mix64(fp) >> 32) & A.slot_mask;
+            for (uint32_t n = 0; n < MAX_PROBES; ++n) {
+                // thread 0 reads the slot; everyone acts on the same copy
+                if (threadIdx.x == 0) { s_key = A.tkey[h]; s_val = A.tval[h]; }
+                __syncthreads();
+                const unsigned long long k = s_key;
+                const uint32_t v = s_val;
+                __syncthreads();
+                if (k == 0ull) {
+                    if (threadIdx.x == 0) {
+                        A.tkey[h] = fp;
+                        A.tval[h] = x;
+                        A.fb_bits[x >> 5] |= 1u << (x & 31u);
+                        const uint32_t pos = A.ctr->n_new;
+                        A.ctr->n_new = pos + 1;
+                        A.ctr->n_fallback_new += 1;
+                        if (pos < A.new_cap) A.new_slots[pos] = h;
+                        else A.ctr->overflow = 1;
+                    }
+                    __syncthreads();
+                    break;
+                }
+                if (k == (unsigned long long)fp) {
+                    const T *target = nullptr;
+                    int t_op = 0;
+                    const T *t_pa = nullptr, *t_pb = nullptr;
+                    if (v & VAL_SETTLED) {
+                        target = A.arena + (size_t)(v & ~VAL_SETTLED) * A.rows.R;
+                    } else if ((A.fb_bits[v >> 5] >> (v & 31u)) & 1u) {
+                        cand_children<T>(A, v, t_op, t_pa, t_pb);
+                    } else {
+                        target = A.arena + (size_t)(A.level_base + rank_of(A.bitmap, A.wordpre, v)) * A.rows.R;
+                    }
+                    if (fb_equal<T, MW>(A, target, t_op, t_pa, t_pb, &s_flag, lane, wv, nw)) break;
+                }
+                h = (h + 1) & A.slot_mask;
+                if (n + 1 == MAX_PROBES && threadIdx.x == 0) A.ctr->overflow = 1;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compaction of representatives: bitmap -> word prefix -> entry ids
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
+    const int lane = (int)__lane_id();
+    const int wv = (int)(threadIdx.x >> 6);
+    const int nwv = (int)(blockDim.x >> 6);
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, (unsigned)o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_tmp[wv] = inc;
+    __syncthreads();
+    uint32_t wbase = 0;
+    total = 0;
+    for (int k = 0; k < nwv; ++k) {
+        uint32_t t = s_tmp[k];
+        if (k < wv) wbase += t;
+        total += t;
+    }
+    __syncthreads();
+    return wbase + inc - v;
+}
+
+constexpr int SCAN_WPT = 8;                       // bitmap words per thread
+constexpr int SCAN_CHUNK = 256 * SCAN_WPT;        // bitmap words per block
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *bits, uint32_t nw, uint32_t *chunk_sums) {
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_WPT;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_WPT; ++k)
+        if (base + k < nw) s += (uint32_t)__popc(bits[base + k]);
+    uint32_t total;
+    block_exclusive_scan(s, s_tmp, total);
+    if (threadIdx.x == 0) chunk_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_chunks(uint32_t *chunk_sums, uint32_t nchunks) {
+    __shared__ uint32_t s_tmp[4];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nchunks; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < nchunks ? chunk_sums[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(v, s_tmp, total);
+        if (i < nchunks) chunk_sums[i] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *bits, uint32_t nw, const uint32_t *chunk_sums,
+                                                    uint32_t *wordpre) {
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_WPT;
+    uint32_t c[SCAN_WPT];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_WPT; ++k) {
+        c[k] = (base + k < nw) ? (uint32_t)__popc(bits[base + k]) : 0u;
+        s += c[k];
+    }
+    uint32_t total;
+    uint32_t run = chunk_sums[blockIdx.x] + block_exclusive_scan(s, s_tmp, total);
+#pragma unroll
+    for (int k = 0; k < SCAN_WPT; ++k) {
+        if (base + k < nw) wordpre[base + k] = run;
+        run += c[k];
+    }
+}
+
+// slot owners -> representative bits
+__global__ void k_mark(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, uint32_t *bitmap) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t x = tval[new_slots[i]];
+    atomicOr(&bitmap[x >> 5], 1u << (x & 31u));
+}
+
+__global__ void k_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) dst[i] |= src[i];
+}
+
+// representatives -> recipes (entry order = canonical order of the representative)
+__global__ void k_scatter(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, const uint32_t *bitmap,
+                          const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t x = tval[new_slots[i]];
+    recipe[level_base + rank_of(bitmap, wordpre, x)] = x;
+}
+
+// settle the level's slots: owner index -> global entry id
+__global__ void k_finalize(const uint32_t *new_slots, uint32_t n, uint32_t *tval, const uint32_t *bitmap,
+                           const uint32_t *wordpre, uint32_t level_base) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = new_slots[i];
+    const uint32_t x = tval[s];
+    tval[s] = VAL_SETTLED | (level_base + rank_of(bitmap, wordpre, x));
+}
+
+// ---------------------------------------------------------------------------
+// Specification intake
+// ---------------------------------------------------------------------------
+__global__ void k_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t nslots) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        tkey[i] = 0ull;
+        tval[i] = VAL_OPEN;
+    }
+}
+
+// Atom matrices: bit (W-1-i) of word w of trace t for proposition p is p in tr_t[w*W + i].
+template <typename T>
+__global__ void k_pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
+                       const uint32_t *row_word, uint32_t R, uint32_t nprops, T *atoms, Counters *ctr) {
+    constexpr int BITS = Word<T>::BITS;
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const uint32_t t = row_trace[r];
+    if (t == 0xFFFFFFFFu) {
+        for (uint32_t p = 0; p < nprops; ++p) atoms[(size_t)p * R + r] = 0;
+        return;
+    }
+    const uint64_t off = offsets[t];
+    const uint64_t len = offsets[t + 1] - off;
+    const uint64_t p0 = (uint64_t)row_word[r] * BITS;
+    const uint32_t n = (uint32_t)min((uint64_t)BITS, len - p0);
+    uint32_t lor = 0;
+    for (uint32_t i = 0; i < n; ++i) lor |= letters[off + p0 + i];
+    for (uint32_t p = 0; p < nprops; ++p) {
+        T w = 0;
+        for (uint32_t i = 0; i < n; ++i) w |= (T)((letters[off + p0 + i] >> p) & 1u) << (BITS - 1 - i);
+        atoms[(size_t)p * R + r] = w;
+    }
+    if (lor) atomicOr(&ctr->letter_or, lor);
+}
+
+// Per-trace fingerprint (length and letters), for the P/N disjointness check.
+__global__ void k_trace_fp(const uint32_t *letters, const uint64_t *offsets, uint32_t ntr, uint64_t *out) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntr) return;
+    const uint64_t off = offsets[t], len = offsets[t + 1] - off;
+    uint64_t h = mix64(len + 0x9e3779b97f4a7c15ull);
+    for (uint64_t i = 0; i < len; ++i) h = mix64(h ^ (uint64_t)letters[off + i]);
+    out[t] = h;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side of this translation unit)
+// ---------------------------------------------------------------------------
+// Multi-word kernels (lanes of one trace exchange bits) exist for 64-bit words only.
+template <typename T>
+hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, uint32_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            if (verify) hipLaunchKernelGGL((k_level<T, true, true>), dim3(grid), dim3(256), 0, s, A);
+            else hipLaunchKernelGGL((k_level<T, true, false>), dim3(grid), dim3(256), 0, s, A);
+            return hipGetLastError();
+        }
+    }
+    if (verify) hipLaunchKernelGGL((k_level<T, false, true>), dim3(grid), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL((k_level<T, false, false>), dim3(grid), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::materialize(const LevelArgs<T> &A, bool mw, uint32_t n, uint32_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            hipLaunchKernelGGL((k_materialize<T, true>), dim3(grid), dim3(256), 0, s, A, n);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_materialize<T, false>), dim3(grid), dim3(256), 0, s, A, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::fallback(const LevelArgs<T> &A, bool mw, uint32_t nwords, uint32_t ncand, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            hipLaunchKernelGGL((k_fallback<T, true>), dim3(1), dim3(256), 0, s, A, nwords, ncand);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_fallback<T, false>), dim3(1), dim3(256), 0, s, A, nwords, ncand);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
+                           const uint32_t *row_word, uint32_t R, uint32_t nprops, T *atoms, Counters *ctr,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((k_pack<T>), dim3((R + 255) / 256), dim3(256), 0, s, letters, offsets, row_trace,
+                       row_word, R, nprops, atoms, ctr);
+    return hipGetLastError();
+}
+
+template struct Launch<uint32_t>;
+template struct Launch<uint64_t>;
+
+hipError_t launch_scan(const uint32_t *bits, uint32_t nw, uint32_t *chunk_sums, uint32_t *wordpre, hipStream_t s) {
+    const uint32_t nchunks = (nw + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nchunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(256), 0, s, bits, nw, chunk_sums);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(256), 0, s, chunk_sums, nchunks);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nchunks), dim3(256), 0, s, bits, nw, chunk_sums, wordpre);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, uint32_t *bitmap, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_mark, dim3((n + 255) / 256), dim3(256), 0, s, new_slots, n, tval, bitmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipStream_t s) {
+    if (!nw) return hipSuccess;
+    hipLaunchKernelGGL(k_or_bits, dim3((nw + 255) / 256), dim3(256), 0, s, dst, src, nw);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, const uint32_t *bitmap,
+                          const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, new_slots, n, tval, bitmap, wordpre,
+                       recipe, level_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const uint32_t *new_slots, uint32_t n, uint32_t *tval, const uint32_t *bitmap,
+                           const uint32_t *wordpre, uint32_t level_base, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, s, new_slots, n, tval, bitmap, wordpre,
+                       level_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t nslots, hipStream_t s) {
+    uint64_t g = (nslots + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_table_init, dim3((uint32_t)g), dim3(256), 0, s, tkey, tval, nslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_fp(const uint32_t *letters, const uint64_t *offsets, uint32_t ntr, uint64_t *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_trace_fp, dim3((ntr + 255) / 256), dim3(256), 0, s, letters, offsets, ntr, out);
+    return hipGetLastError();
+}
+
+}  // namespace ltl

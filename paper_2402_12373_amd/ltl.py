@@ -1,0 +1,313 @@
+"""Python binding of the gfx950 LTL learner library (libltl.so, C-ABI in include/ltl.h).
+
+Argument marshalling only: every step of the learner runs in the library's HIP
+kernels.  PyTorch provides the device workspace and the stream.  Importing works
+without a GPU; creating a context needs the built library and a HIP device and
+raises otherwise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libltl.so")
+
+LTL_OK, LTL_NOT_FOUND = 0, 1
+LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG, LTL_E_OOM, LTL_E_DEVICE, LTL_E_STATE = -1, -2, -3, -4, -5, -6
+ATOM, NOT, AND, OR, X, F, G, U = range(8)
+CTX_U_CARRY, CTX_TIMING = 0x1, 0x2
+SPEC_DEVICE = 0x1
+MAX_LEVELS, MAX_NODES, K_KINDS = 64, 64, 6
+NO_SOLUTION = (1 << 64) - 1
+KERNEL_KINDS = ("eval", "verify", "materialize", "compact", "fallback", "intake")
+
+# every symbol include/ltl.h declares
+EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_job_create", "ltl_eval_level",
+           "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
+           "ltl_status_str")
+
+
+class LTLError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _status_str(status)
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+class CtxOpts(C.Structure):
+    _fields_ = [("device", C.c_int32), ("flags", C.c_uint32), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_uint64), ("stream", C.c_void_p), ("hash_slots_log2", C.c_uint32),
+                ("word_bits", C.c_uint32), ("fp_bits", C.c_uint32), ("reserved", C.c_uint32),
+                ("max_entries", C.c_uint64)]
+
+
+class Spec(C.Structure):
+    _fields_ = [("num_props", C.c_uint32), ("num_pos", C.c_uint32), ("num_neg", C.c_uint32),
+                ("flags", C.c_uint32), ("letters", C.c_void_p), ("offsets", C.c_void_p)]
+
+
+class OpSet(C.Structure):
+    _fields_ = [("op_mask", C.c_uint32), ("cost", C.c_uint32 * 8)]
+
+
+class Node(C.Structure):
+    _fields_ = [("op", C.c_uint32), ("a", C.c_uint32), ("b", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("cost", C.c_uint32), ("levels_done", C.c_uint32),
+                ("num_nodes", C.c_uint32), ("nodes", Node * MAX_NODES), ("solution_index", C.c_uint64),
+                ("level_new", C.c_uint64 * MAX_LEVELS), ("level_candidates", C.c_uint64 * MAX_LEVELS),
+                ("level_ms", C.c_double * MAX_LEVELS), ("colliders", C.c_uint64),
+                ("kernel_ms", C.c_double * K_KINDS), ("kernel_launches", C.c_uint32 * K_KINDS)]
+
+
+class LevelStats(C.Structure):
+    _fields_ = [("cost", C.c_uint32), ("stored", C.c_uint32), ("candidates", C.c_uint64),
+                ("new_entries", C.c_uint64), ("first_solution", C.c_uint64), ("colliders", C.c_uint64),
+                ("kernel_ms", C.c_double)]
+
+
+class JobInfo(C.Structure):
+    _fields_ = [("word_bits", C.c_uint32), ("rows", C.c_uint32), ("cm_bytes", C.c_uint64),
+                ("total_positions", C.c_uint64), ("hash_slots_log2", C.c_uint32), ("doubling_steps", C.c_uint32),
+                ("arena_bytes", C.c_uint64), ("max_entries", C.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libltl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with `python -m paper_2402_12373_amd.build`")
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.ltl_ctx_create.argtypes = [P(CtxOpts), P(C.c_void_p)]
+    L.ltl_ctx_create.restype = C.c_int
+    L.ltl_ctx_destroy.argtypes = [C.c_void_p]
+    L.ltl_ctx_destroy.restype = None
+    L.ltl_learn.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(Result)]
+    L.ltl_learn.restype = C.c_int
+    L.ltl_job_create.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(C.c_void_p)]
+    L.ltl_job_create.restype = C.c_int
+    L.ltl_eval_level.argtypes = [C.c_void_p, C.c_uint32, P(LevelStats)]
+    L.ltl_eval_level.restype = C.c_int
+    L.ltl_job_result.argtypes = [C.c_void_p, P(Result)]
+    L.ltl_job_result.restype = C.c_int
+    L.ltl_job_formula.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P(Node), C.c_uint32, P(C.c_uint32)]
+    L.ltl_job_formula.restype = C.c_int
+    L.ltl_job_dump_cm.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, C.c_void_p, C.c_uint64]
+    L.ltl_job_dump_cm.restype = C.c_int
+    L.ltl_job_get_info.argtypes = [C.c_void_p, P(JobInfo)]
+    L.ltl_job_get_info.restype = C.c_int
+    L.ltl_job_destroy.argtypes = [C.c_void_p]
+    L.ltl_job_destroy.restype = None
+    L.ltl_status_str.argtypes = [C.c_int]
+    L.ltl_status_str.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _status_str(st: int) -> str:
+    try:
+        return load_library().ltl_status_str(st).decode()
+    except Exception:
+        return f"status {st}"
+
+
+def opset(cost: Optional[Sequence[int]] = None, ops: Optional[Sequence[int]] = None) -> OpSet:
+    o = OpSet()
+    mask = 0
+    for op in (ops if ops is not None else range(8)):
+        mask |= 1 << op
+    o.op_mask = mask | 1
+    for k in range(8):
+        o.cost[k] = (cost[k] if cost is not None else 1)
+    return o
+
+
+@dataclass
+class LearnResult:
+    status: int
+    cost: int
+    levels_done: int
+    level_new: List[int]
+    level_candidates: List[int]
+    level_ms: List[float]
+    solution: Optional[list]
+    solution_index: Optional[int]
+    colliders: int
+    kernel_ms: dict = field(default_factory=dict)
+    kernel_launches: dict = field(default_factory=dict)
+
+    @property
+    def candidates(self) -> int:
+        return int(sum(self.level_candidates))
+
+
+def _convert(r: Result) -> LearnResult:
+    done = int(r.levels_done)
+    sol = [(int(r.nodes[k].op), int(r.nodes[k].a), int(r.nodes[k].b)) for k in range(r.num_nodes)] \
+        if r.status == LTL_OK else None
+    return LearnResult(int(r.status), int(r.cost), done,
+                       [int(r.level_new[c]) for c in range(done + 1)],
+                       [int(r.level_candidates[c]) for c in range(done + 1)],
+                       [float(r.level_ms[c]) for c in range(done + 1)], sol,
+                       None if r.solution_index == NO_SOLUTION else int(r.solution_index), int(r.colliders),
+                       {KERNEL_KINDS[k]: float(r.kernel_ms[k]) for k in range(K_KINDS)},
+                       {KERNEL_KINDS[k]: int(r.kernel_launches[k]) for k in range(K_KINDS)})
+
+
+class SpecBuffers:
+    """Host (numpy) or device (torch) buffers behind an ltl_spec."""
+
+    def __init__(self, inst, device_tensors=None):
+        self.inst = inst
+        self.c = Spec()
+        self.c.num_props = inst.num_props
+        self.c.num_pos = inst.num_pos
+        self.c.num_neg = inst.num_neg
+        if device_tensors is None:
+            self.letters = np.ascontiguousarray(inst.letters, dtype=np.uint32)
+            self.offsets = np.ascontiguousarray(inst.offsets, dtype=np.uint64)
+            self.c.flags = 0
+            self.c.letters = self.letters.ctypes.data
+            self.c.offsets = self.offsets.ctypes.data
+        else:
+            self.letters, self.offsets = device_tensors
+            self.c.flags = SPEC_DEVICE
+            self.c.letters = self.letters.data_ptr()
+            self.c.offsets = self.offsets.data_ptr()
+
+
+def spec_to_device(inst, device="cuda"):
+    """Copies an instance's letters/offsets to device tensors (inputs resident in HBM)."""
+    import torch
+    letters = torch.from_numpy(np.ascontiguousarray(inst.letters, dtype=np.uint32).view(np.int32)).to(device)
+    offsets = torch.from_numpy(np.ascontiguousarray(inst.offsets, dtype=np.uint64).view(np.int64)).to(device)
+    return SpecBuffers(inst, (letters, offsets))
+
+
+class Context:
+    """An ltl_ctx over a torch-allocated device workspace."""
+
+    def __init__(self, workspace_bytes: int = 1 << 30, device: int = 0, flags: int = 0, hash_slots_log2: int = 0,
+                 word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0, stream=None, workspace=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
+        L = load_library()
+        self.L = L
+        self.device = device
+        if workspace is None:
+            workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        self.workspace = workspace
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        o = CtxOpts()
+        o.device = device
+        o.flags = flags
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+        o.stream = stream.cuda_stream
+        o.hash_slots_log2 = hash_slots_log2
+        o.word_bits = word_bits
+        o.fp_bits = fp_bits
+        o.max_entries = max_entries
+        self.opts = o
+        h = C.c_void_p()
+        st = L.ltl_ctx_create(C.byref(o), C.byref(h))
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_ctx_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ltl_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def learn(self, inst_or_spec, bound: int, cost=None, ops=None) -> LearnResult:
+        spec = inst_or_spec if isinstance(inst_or_spec, SpecBuffers) else SpecBuffers(inst_or_spec)
+        r = Result()
+        self.L.ltl_learn(self.h, C.byref(spec.c), C.byref(opset(cost, ops)), bound, C.byref(r))
+        return _convert(r)
+
+    def job(self, inst_or_spec, bound: int, cost=None, ops=None) -> "Job":
+        return Job(self, inst_or_spec, bound, cost, ops)
+
+
+class Job:
+    """Level-by-level interface (ltl_job_create / ltl_eval_level / ...)."""
+
+    def __init__(self, ctx: Context, inst_or_spec, bound: int, cost=None, ops=None):
+        self.ctx = ctx
+        self.L = ctx.L
+        self.spec = inst_or_spec if isinstance(inst_or_spec, SpecBuffers) else SpecBuffers(inst_or_spec)
+        self.bound = bound
+        h = C.c_void_p()
+        st = self.L.ltl_job_create(ctx.h, C.byref(self.spec.c), C.byref(opset(cost, ops)), bound, C.byref(h))
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_job_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ltl_job_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval_level(self, cost: int) -> LevelStats:
+        s = LevelStats()
+        st = self.L.ltl_eval_level(self.h, cost, C.byref(s))
+        if st != LTL_OK:
+            raise LTLError(st, f"ltl_eval_level({cost})")
+        return s
+
+    def result(self) -> LearnResult:
+        r = Result()
+        self.L.ltl_job_result(self.h, C.byref(r))
+        return _convert(r)
+
+    def formula(self, cost: int, entry: int):
+        buf = (Node * MAX_NODES)()
+        n = C.c_uint32()
+        st = self.L.ltl_job_formula(self.h, cost, entry, buf, MAX_NODES, C.byref(n))
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_job_formula")
+        return [(int(buf[k].op), int(buf[k].a), int(buf[k].b)) for k in range(n.value)]
+
+    def dump_cm(self, cost: int, entry: int) -> np.ndarray:
+        tb = int(self.spec.inst.total_positions)
+        out = np.zeros(tb, dtype=np.uint8)
+        st = self.L.ltl_job_dump_cm(self.h, cost, entry, out.ctypes.data, tb)
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_job_dump_cm")
+        return out
+
+    def info(self) -> JobInfo:
+        i = JobInfo()
+        st = self.L.ltl_job_get_info(self.h, C.byref(i))
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_job_get_info")
+        return i

@@ -1,0 +1,223 @@
+"""GPU path vs the CPU oracle, element by element, through the C-ABI.
+
+Bar: bit-exact.  Every compared quantity is integer: status, minimal cost,
+per-level counts of new languages and of candidates, the canonical index and
+formula of the first solution, and every stored characteristic matrix.
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2402_12373_amd import synth
+from ltl_text import random_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ltl():
+    from paper_2402_12373_amd import ltl as L
+    return L
+
+
+@pytest.fixture(scope="module")
+def ctx(ltl):
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22)
+    yield c
+    c.close()
+
+
+def _same(gpu, ora, where=""):
+    assert gpu.status == ora.status, (where, gpu.status, ora.status)
+    assert gpu.levels_done == ora.levels_done, (where, gpu.levels_done, ora.levels_done)
+    for c in range(1, ora.levels_done + 1):
+        assert gpu.level_new[c] == ora.level_new[c], (where, "E", c, gpu.level_new, ora.level_new)
+        assert gpu.level_candidates[c] == ora.level_candidates[c], (where, "C", c)
+    if ora.status == O.ST_OK:
+        assert gpu.cost == ora.cost, where
+        assert gpu.solution_index == ora.first_index, (where, gpu.solution_index, ora.first_index)
+        assert gpu.solution == ora.solution, (where, gpu.solution, ora.solution)
+
+
+@pytest.mark.parametrize("chunk", range(8))
+def test_tiny_workload_parity(ctx, chunk):
+    """Tiny planted workload (2 props, 16+16 traces, length 4..8, bound 7), 256 seeds."""
+    for seed in range(chunk * 32, chunk * 32 + 32):
+        inst, cfg = synth.preset_instance("tiny", seed)
+        _say("tiny seed", seed)
+        g = ctx.learn(inst, cfg["bound"])
+        o = O.learn(inst, cfg["bound"])
+        _same(g, o, f"tiny/{seed}")
+
+
+def _level_by_level(ltl, ctx, inst, bound, check_entries=True, max_entries_per_level=None):
+    """Evaluates levels one at a time and compares every stored matrix and formula."""
+    run = O.Run(O.Spec.of(inst), bound, mode=O.MODE_EXPAND, threads=8)
+    ora = run.result()
+    job = ctx.job(inst, bound)
+    try:
+        for c in range(1, ora.levels_done + 1):
+            st = job.eval_level(c)
+            assert st.new_entries == ora.level_new[c], (c, st.new_entries, ora.level_new[c])
+            assert st.candidates == ora.level_candidates[c], c
+            if not check_entries:
+                continue
+            n = ora.level_new[c]
+            step = 1 if max_entries_per_level is None else max(1, n // max_entries_per_level)
+            for e in range(0, n, step):
+                assert job.formula(c, e) == run.entry_formula(c, e), (c, e)
+                np.testing.assert_array_equal(job.dump_cm(c, e), run.entry_cm(c, e), err_msg=f"level {c} entry {e}")
+        g = job.result()
+    finally:
+        job.close()
+    _same(g, ora)
+    return g, ora
+
+
+def test_every_stored_matrix_tiny(ltl, ctx):
+    for seed in (0, 2, 7):
+        inst, cfg = synth.preset_instance("tiny", seed)
+        _say("entries tiny", seed)
+        _level_by_level(ltl, ctx, inst, 5)
+
+
+LENGTH_SETS = [
+    (1, 2, 3),
+    (31, 32, 30),
+    (33, 40, 64),
+    (63, 64, 65),
+    (127, 128, 129),
+    (200, 511, 512),
+    (1, 64, 129, 300),
+]
+
+
+@pytest.mark.parametrize("lengths", LENGTH_SETS, ids=lambda l: "len" + "-".join(map(str, l)))
+def test_word_boundaries(ltl, ctx, lengths):
+    """Traces straddling word boundaries (single and multi-word rows), all matrices to level 4."""
+    rng = np.random.default_rng(sum(lengths))
+    pos, neg = [], []
+    for k in range(8):
+        n = lengths[k % len(lengths)]
+        tr = [int(x) for x in rng.integers(0, 4, size=n)]
+        (pos if k % 2 == 0 else neg).append(tr)
+    inst = synth.from_traces(pos, neg, 2)
+    _say("boundaries", lengths)
+    _level_by_level(ltl, ctx, inst, 4, max_entries_per_level=200)
+
+
+def test_single_word_u64_rows(ltl):
+    """Short traces in 64-bit words (one word per trace) match the 32-bit layout."""
+    c64 = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, word_bits=64)
+    try:
+        for seed in range(8):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            _same(c64.learn(inst, cfg["bound"]), O.learn(inst, cfg["bound"]), f"u64/{seed}")
+    finally:
+        c64.close()
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+def test_u_carry_variant_matches(ltl, word_bits):
+    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, flags=ltl.CTX_U_CARRY, word_bits=word_bits)
+    try:
+        for seed in range(16):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            _same(c.learn(inst, cfg["bound"]), O.learn(inst, cfg["bound"]), f"ucarry/{seed}")
+        rng = np.random.default_rng(5)
+        if word_bits == 64:
+            inst = random_instance(rng, 2, 4, 4, 60, 200)
+            _same(c.learn(inst, 4), O.learn(inst, 4, mode=O.MODE_EXPAND), "ucarry-long")
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("fp_bits", [1, 4, 12])
+def test_forced_fingerprint_collisions(ltl, fp_bits):
+    """Truncated fingerprints flood the exact compare and the fallback; results must not change."""
+    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, fp_bits=fp_bits)
+    try:
+        total = 0
+        for seed in range(6):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            _say("fp_bits", fp_bits, "seed", seed)
+            g = c.learn(inst, 6)
+            _same(g, O.learn(inst, 6), f"fp{fp_bits}/{seed}")
+            total += g.colliders
+        assert total > 0
+    finally:
+        c.close()
+
+
+def test_forced_collisions_multiword(ltl):
+    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, fp_bits=6)
+    try:
+        rng = np.random.default_rng(11)
+        inst = random_instance(rng, 2, 3, 3, 70, 140)
+        g = c.learn(inst, 4)
+        _same(g, O.learn(inst, 4, mode=O.MODE_EXPAND), "fp6-long")
+        assert g.colliders > 0
+    finally:
+        c.close()
+
+
+def test_deterministic_reruns(ltl, ctx):
+    inst, cfg = synth.preset_instance("tiny", 3)
+    a = ctx.learn(inst, 7)
+    b = ctx.learn(inst, 7)
+    assert (a.status, a.cost, a.level_new, a.level_candidates, a.solution_index, a.solution) == \
+           (b.status, b.cost, b.level_new, b.level_candidates, b.solution_index, b.solution)
+
+
+def test_oom_entry_cap_matches_oracle(ltl):
+    inst, cfg = synth.preset_instance("tiny", 0)
+    for cap in (3, 10, 30):
+        c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, max_entries=cap)
+        try:
+            g = c.learn(inst, 7)
+        finally:
+            c.close()
+        o = O.learn(inst, 7, max_entries=cap)
+        assert g.status == o.status, (cap, g.status, o.status)
+        assert g.levels_done == o.levels_done
+        assert g.level_new == o.level_new[:o.levels_done + 1]
+
+
+def test_invalid_specs(ltl, ctx):
+    bad = [
+        (synth.from_traces([[1, 2]], [[1, 2]], 2), ltl.LTL_E_INCONSISTENT),
+        (synth.from_traces([[1, 2], []], [[3]], 2), ltl.LTL_E_INVAL),
+        (synth.from_traces([[4]], [[1]], 2), ltl.LTL_E_INVAL),
+        (synth.from_traces([[1] * 5000], [[0]], 1), ltl.LTL_E_TOO_LONG),
+    ]
+    for inst, st in bad:
+        assert ctx.learn(inst, 3).status == st
+    ok = synth.from_traces([[1, 0]], [[0, 1]], 1)
+    r = ctx.learn(ok, 3)
+    assert r.status == ltl.LTL_OK and r.cost == 1
+
+
+def test_device_resident_spec(ltl, ctx):
+    inst, cfg = synth.preset_instance("tiny", 9)
+    dev = ltl.spec_to_device(inst)
+    _same(ctx.learn(dev, 7), O.learn(inst, 7), "device-spec")
+
+
+def test_level_calls_out_of_order(ltl, ctx):
+    inst, cfg = synth.preset_instance("tiny", 1)
+    job = ctx.job(inst, 7)
+    try:
+        with pytest.raises(ltl.LTLError):
+            job.eval_level(2)
+        job.eval_level(1)
+    finally:
+        job.close()
