@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: candidate formulae evaluated per second on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input: the
+learning jobs of the "scale" workload (3 propositions, 1024 + 1024 traces of
+length 16..32, Bernoulli(0.5) letters, planted formula of size 9, unit costs,
+cost bound 11, 32-bit words, 2^26 hash slots), seeds 0..7, each solved by
+ltl_learn from a device-resident specification.  The metric is the number of
+canonical candidates evaluated, over the timed wall time.
+
+Prints ONE JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, 8 TB/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T
+
+
+def parse_seeds(s: str):
+    out = []
+    for part in s.split(","):
+        if "-" in part:
+            a, b = part.split("-")
+            out += list(range(int(a), int(b) + 1))
+        elif part:
+            out.append(int(part))
+    return out
+
+
+# Algorithmic work per candidate, per 32-bit half-word of its matrix ("Roofline"):
+#   connective: NOT 2, AND/OR 1, X 1, F 2, G 5, U (doubling, k steps) 5k-2, ATOM 0
+#   fingerprint 7 (premix 4, multiply-add 3), separation 3
+OP_OPS = {"atom": 0, "not": 2, "and": 1, "or": 1, "x": 1, "f": 2, "g": 5}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long"])
+    ap.add_argument("--seeds", default="0-7")
+    ap.add_argument("--workspace-gb", type=float, default=0.0)
+    ap.add_argument("--ucarry", action="store_true", help="U by carry-chain add instead of doubling")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-levels", type=int, default=8, help="levels per job in the CPU-baseline sample")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the run, copy this many MiB device-to-device (a kernel of known traffic for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2402_12373_amd import ltl, synth
+
+    seeds = parse_seeds(args.seeds)
+    cfg = synth.PRESETS[args.workload]
+    insts = [synth.preset_instance(args.workload, s)[0] for s in seeds]
+    dev = [ltl.spec_to_device(i) for i in insts]            # inputs resident in HBM
+
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    free, total = torch.cuda.mem_get_info()
+    ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
+    slots = 26 if args.workload != "tiny" else 20
+    flags = ltl.CTX_TIMING | (ltl.CTX_U_CARRY if args.ucarry else 0)
+    ctx = ltl.Context(workspace_bytes=ws_bytes, hash_slots_log2=slots, flags=flags)
+
+    def step():
+        return [ctx.learn(d, cfg["bound"]) for d in dev]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    job_ms = []
+    for _ in range(args.steps):
+        for d in dev:
+            tj = time.perf_counter()
+            results.append(ctx.learn(d, cfg["bound"]))
+            job_ms.append((time.perf_counter() - tj) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+
+    cands = sum(r.candidates for r in results)
+    value = cands / wall
+    tb = [int(i.total_positions) for i in insts]
+    tb_mean = sum(tb) / len(tb)
+
+    # per-kernel GPU time, measured with HIP events on the library's stream
+    kern_ms = {k: sum(r.kernel_ms[k] for r in results) for k in ltl.KERNEL_KINDS}
+    kern_n = {k: sum(r.kernel_launches[k] for r in results) for k in ltl.KERNEL_KINDS}
+    dominant = max(kern_ms, key=kern_ms.get)
+
+    # algorithmic work of the evaluation / verify kernels
+    job = ctx.job(dev[0], 1)
+    info = job.info()
+    job.close()
+    R = int(info.rows)
+    halves = R * (int(info.word_bits) // 32)
+    k = int(info.doubling_steps)
+    cm_bytes = int(info.cm_bytes)
+
+    # candidate mix: the canonical blocks per level follow from the level sizes
+    ops_total = 0.0
+    bytes_verify = 0.0
+    n_eval_cands = 0
+    for r in results:
+        E = r.level_new
+        for c in range(1, r.levels_done + 1):
+            C = r.level_candidates[c]
+            if C == 0:
+                continue
+            n_eval_cands += C
+            if c == 1:
+                per = OP_OPS["atom"]
+                ops_total += C * halves * (per + 10)
+            else:
+                x = c - 1
+                un = E[x] if x >= 1 else 0
+                u_pairs = sum(E[a] * E[x - a] for a in range(1, x))
+                ao = 0
+                for a in range(1, x // 2 + 1):
+                    b = x - a
+                    ao += E[a] * E[b] if a < b else E[a] * (E[a] - 1) // 2
+                uop = 5 if args.ucarry else 5 * k - 2
+                per_level_ops = un * (OP_OPS["f"] + OP_OPS["g"] + OP_OPS["x"] + OP_OPS["not"] + 4 * 10) \
+                    + u_pairs * (uop + 10) + ao * (OP_OPS["and"] + OP_OPS["or"] + 2 * 10)
+                ops_total += per_level_ops * halves
+            # verify: every non-representative reads its owner's matrix once; new entries are written once
+            bytes_verify += (C - r.level_new[c]) * cm_bytes
+    eval_ms = kern_ms["eval"]
+    verify_ms = kern_ms["verify"]
+    eval_tops = ops_total / (eval_ms * 1e-3) / 1e12 if eval_ms else 0.0
+    verify_gbs = bytes_verify / (verify_ms * 1e-3) / 1e9 if verify_ms else 0.0
+    if dominant == "verify":
+        roof = {"bound": "hbm", "kernel": "k_level<verify>", "achieved": round(verify_gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(verify_gbs / HBM_PEAK_GBS, 4),
+                "traffic": None}
+    else:
+        roof = {"bound": "alu", "kernel": "k_level<eval>", "achieved": round(eval_tops, 3),
+                "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
+                "frac": round(eval_tops / VALU_PEAK_TOPS, 4), "traffic": None}
+    roof["avg_launch_ms"] = round(kern_ms[dominant] / max(1, kern_n[dominant]), 4)
+    roof["launches"] = kern_n[dominant]
+
+    out = {
+        "metric": "candidate formulae evaluated/s",
+        "value": round(value, 1),
+        "unit": "candidates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32" if cfg["word_bits"] == 32 else "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {cfg['num_props']} props, {cfg['k']}+{cfg['k']} traces, "
+                               f"len {cfg['lo']}..{cfg['hi']}, p={cfg['p']}, planted size {cfg['size']}, "
+                               f"cost bound {cfg['bound']}, seeds {args.seeds}",
+                   "jobs_per_step": len(dev), "hash_slots_log2": slots,
+                   "u_operator": "carry" if args.ucarry else "doubling"},
+        "trace_bits_per_s": round(value * tb_mean, 1),
+        "jobs_per_s": round(len(results) / wall, 3),
+        "job_ms_p50": round(statistics.median(job_ms), 3),
+        "job_ms_p99": round(float(np.percentile(job_ms, 99)), 3),
+        "minimal_costs": [r.cost if r.status == 0 else None for r in results[:len(dev)]],
+        "statuses": [r.status for r in results[:len(dev)]],
+        "candidates_per_step": cands // args.steps,
+        "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in kern_ms.items()},
+        "verify_GBps": round(verify_gbs, 1),
+        "eval_Tops": round(eval_tops, 3),
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_levels)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(insts, levels):
+    """The CPU oracle, unchanged, on a bounded sample: the first `levels` cost levels of every job."""
+    from oracle import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    cands = 0
+    for inst in insts:
+        r = O.learn(inst, levels, mode=O.MODE_EXPAND, threads=threads)
+        cands += sum(r.level_candidates[:r.levels_done + 1])
+    dt = time.perf_counter() - t0
+    return {"value": round(cands / dt, 1), "unit": "candidates/s", "cores": threads, "kind": "oracle",
+            "sample": f"levels 1..{levels} of each of the {len(insts)} jobs ({cands} candidates, {dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

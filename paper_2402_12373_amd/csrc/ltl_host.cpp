@@ -86,7 +86,8 @@ struct ltl_job {
     void *valid = nullptr, *sepm = nullptr, *sepw = nullptr, *atoms = nullptr;
     uint64_t *nxt = nullptr, *key = nullptr, *tfp = nullptr, *offsets_d = nullptr;
     uint32_t *row_trace = nullptr, *row_word = nullptr, *letters_d = nullptr;
-    Block *blocks_d = nullptr;
+    Block *blocks_d = nullptr;       // canonical order (candidate decode)
+    Block *blocks_cls_d = nullptr;   // grouped by connective class, class-local tiles
     unsigned long long *tkey = nullptr;
     uint32_t *tval = nullptr;
     uint32_t slots_log2 = 0;
@@ -105,6 +106,7 @@ struct ltl_job {
     uint64_t colliders = 0;
     bool timing = false;
     std::vector<TimedLaunch> pending;
+    std::vector<Block> grouped;
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[LTL_K_KINDS] = {0};
     uint32_t kernel_launches[LTL_K_KINDS] = {0};
@@ -327,6 +329,7 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     j->atoms = ws_take(j, (uint64_t)j->A * R * j->wbytes);
     j->tfp = (uint64_t *)ws_take(j, (uint64_t)T * 8);
     j->blocks_d = (Block *)ws_take(j, sizeof(Block) * MAX_BLOCKS);
+    j->blocks_cls_d = (Block *)ws_take(j, sizeof(Block) * MAX_BLOCKS);
     if (!(spec->flags & LTL_SPEC_DEVICE)) {
         j->letters_d = (uint32_t *)ws_take(j, j->TB * 4);
         j->offsets_d = (uint64_t *)ws_take(j, ((uint64_t)T + 1) * 8);
@@ -335,7 +338,7 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
         j->offsets_d = (uint64_t *)spec->offsets;
     }
     if (!j->ctr || !j->valid || !j->sepm || !j->sepw || !j->nxt || !j->key || !j->row_trace || !j->row_word ||
-        !j->atoms || !j->tfp || !j->blocks_d || !j->letters_d || !j->offsets_d)
+        !j->atoms || !j->tfp || !j->blocks_d || !j->blocks_cls_d || !j->letters_d || !j->offsets_d)
         return LTL_E_OOM;
 
     // language-cache hash table: 12 bytes per slot
@@ -612,6 +615,31 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
 
     HIP_TRY(hipMemcpyAsync(j->blocks_d, lv.blocks.data(), sizeof(Block) * lv.blocks.size(), hipMemcpyHostToDevice,
                            j->s));
+    // the same blocks grouped by connective class, each class with its own tile numbering
+    const bool ucarry = (j->ctx->o.flags & LTL_CTX_U_CARRY) != 0;
+    auto cls_of = [&](uint32_t op) {
+        if (op == LTL_AND || op == LTL_OR) return 1;
+        if (op == LTL_U) return ucarry ? 3 : 2;
+        return 0;
+    };
+    std::vector<Block> &grouped = j->grouped;
+    grouped.clear();
+    uint32_t cls_first[5] = {0}, cls_tiles[4] = {0};
+    for (int k = 0; k < 4; ++k) {
+        cls_first[k] = (uint32_t)grouped.size();
+        uint32_t tb = 0;
+        for (const Block &b : lv.blocks) {
+            if (cls_of(b.op) != k) continue;
+            Block g = b;
+            g.tile_base = tb;
+            tb += b.ntile;
+            grouped.push_back(g);
+        }
+        cls_tiles[k] = tb;
+    }
+    cls_first[4] = (uint32_t)grouped.size();
+    HIP_TRY(hipMemcpyAsync(j->blocks_cls_d, grouped.data(), sizeof(Block) * grouped.size(), hipMemcpyHostToDevice,
+                           j->s));
     Counters init{};
     init.first_sol = ~0ull;
     HIP_TRY(hipMemcpyAsync(j->ctr, &init, sizeof(Counters), hipMemcpyHostToDevice, j->s));
@@ -623,7 +651,6 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.rows = make_rows<T>(j);
     A.blocks = j->blocks_d;
     A.nblocks = (uint32_t)lv.blocks.size();
-    A.ntiles = (uint32_t)ntiles;
     A.tkey = j->tkey;
     A.tval = j->tval;
     A.slot_mask = (uint32_t)(nslots - 1);
@@ -642,11 +669,20 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.recipe = j->recipe;
     A.stage = stage;
     A.ucarry = (j->ctx->o.flags & LTL_CTX_U_CARRY) ? 1 : 0;
+    auto launch_level = [&](bool verify) -> hipError_t {
+        for (int k = 0; k < 4; ++k) {
+            if (!cls_tiles[k]) continue;
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] + 3) / 4, MAX_GRID);
+            hipError_t e = Launch<T>::level(A, j->mw, verify, k, j->blocks_cls_d + cls_first[k],
+                                            cls_first[k + 1] - cls_first[k], cls_tiles[k], grid, j->s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
 
-    const uint32_t grid_tiles = (uint32_t)std::min<uint64_t>((ntiles + 3) / 4, MAX_GRID);
     {
         Timer tm(j, LTL_K_EVAL);
-        HIP_TRY(Launch<T>::level(A, j->mw, false, grid_tiles, j->s));
+        HIP_TRY(launch_level(false));
     }
     Counters hc;
     if (int e = sync_read_counters(j, &hc)) return e;
@@ -671,7 +707,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     {
         Timer tm(j, LTL_K_VERIFY);
-        HIP_TRY(Launch<T>::level(A, j->mw, true, grid_tiles, j->s));
+        HIP_TRY(launch_level(true));
     }
     if (int e = sync_read_counters(j, &hc)) return e;
     lv.colliders = hc.n_coll;

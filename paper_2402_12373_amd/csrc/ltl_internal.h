@@ -56,8 +56,8 @@ struct Rows {
 template <typename T>
 struct LevelArgs {
     Rows<T> rows;
-    const Block *blocks;
-    uint32_t nblocks, ntiles;
+    const Block *blocks;     // canonical order (for decoding a candidate index)
+    uint32_t nblocks;
     unsigned long long *tkey;
     uint32_t *tval;
     uint32_t slot_mask;
@@ -80,7 +80,9 @@ struct LevelArgs {
 
 template <typename T>
 struct Launch {
-    static hipError_t level(const LevelArgs<T> &A, bool mw, bool verify, uint32_t grid, hipStream_t s);
+    // cls: 0 unary, 1 and/or, 2 until (doubling), 3 until (carry adder)
+    static hipError_t level(const LevelArgs<T> &A, bool mw, bool verify, int cls, const Block *blocks,
+                            uint32_t nblocks, uint32_t ntiles, uint32_t grid, hipStream_t s);
     static hipError_t materialize(const LevelArgs<T> &A, bool mw, uint32_t n, uint32_t grid, hipStream_t s);
     static hipError_t fallback(const LevelArgs<T> &A, bool mw, uint32_t nwords, uint32_t ncand, hipStream_t s);
     static hipError_t pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,

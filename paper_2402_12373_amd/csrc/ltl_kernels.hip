@@ -315,40 +315,32 @@ __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx
 // EVAL   : fingerprint + separation, probe/claim in the language cache.
 // VERIFY : recompute, compare in full with the presumed owner.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY>
 __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane) {
     constexpr int NP = TI * TJ;
     constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
     const uint32_t R = A.rows.R;
     const uint32_t nbj = b.tri ? b.na : b.nb;
+    // child matrices of the tile (clamped; results of out-of-range pairs are dropped)
     const T *ap[TI];
     const T *bp[TJ];
 #pragma unroll
-    for (int ii = 0; ii < TI; ++ii) {
-        uint32_t i = min(i0 + ii, b.na - 1);
-        ap[ii] = (const T *)b.a_ptr + (size_t)i * R;
-    }
+    for (int ii = 0; ii < TI; ++ii) ap[ii] = (const T *)b.a_ptr + (size_t)min(i0 + ii, b.na - 1) * R;
 #pragma unroll
-    for (int jj = 0; jj < TJ; ++jj) {
-        if constexpr (BIN) {
-            uint32_t j = min(j0 + jj, nbj - 1);
-            bp[jj] = (const T *)b.b_ptr + (size_t)j * R;
-        } else {
-            bp[jj] = nullptr;
-        }
-    }
-    bool ok[NP];
+    for (int jj = 0; jj < TJ; ++jj)
+        bp[jj] = BIN ? (const T *)b.b_ptr + (size_t)min(j0 + jj, nbj - 1) * R : (const T *)nullptr;
+    // canonical index of each pair, 0xFFFFFFFF if the pair is outside the block
     uint32_t idx[NP];
 #pragma unroll
     for (int ii = 0; ii < TI; ++ii)
 #pragma unroll
         for (int jj = 0; jj < TJ; ++jj) {
-            const int p = ii * TJ + jj;
-            uint32_t i = i0 + ii, j = j0 + jj;
+            const uint32_t i = i0 + ii, j = j0 + jj;
             bool v = i < b.na;
             if constexpr (BIN) v = v && (b.tri ? (j < b.na && j > i) : (j < b.nb));
-            ok[p] = v;
-            idx[p] = v ? cand_index(b, i, j) : 0u;
+            idx[ii * TJ + jj] = v ? cand_index(b, i, j) : 0xFFFFFFFFu;
         }
 
     if constexpr (!VERIFY) {
@@ -358,7 +350,7 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
         for (int p = 0; p < NP; ++p) { acc[p] = 0; viol[p] = 0; }
         for (uint32_t blk = 0; blk < A.rows.NB; ++blk) {
             const uint32_t r = blk * 64u + (uint32_t)lane;
-            RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+            const RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
             T av[TI], bv[TJ];
 #pragma unroll
             for (int ii = 0; ii < TI; ++ii) av[ii] = ap[ii][r];
@@ -369,45 +361,44 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
 #pragma unroll
                 for (int jj = 0; jj < TJ; ++jj) {
                     const int p = ii * TJ + jj;
-                    T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
+                    const T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
                     viol[p] |= (w ^ m.sw) & m.sm;
                     fp_add<T>(acc[p], w, m);
                 }
         }
         uint64_t my_fp = 0;
-        uint32_t my_idx = 0;
-        bool my_ok = false;
+        uint32_t my_idx = 0xFFFFFFFFu;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            uint64_t s = wave_sum(acc[p]);
-            bool bad = __ballot(viol[p] != 0) != 0ull;
-            if (ok[p] && !bad && lane == 0) atomicMin(&A.ctr->first_sol, (unsigned long long)idx[p]);
-            if (lane == p) { my_fp = s; my_idx = idx[p]; my_ok = ok[p]; }
+            const uint64_t s = wave_sum(acc[p]);
+            const bool bad = __ballot(viol[p] != 0) != 0ull;
+            if (idx[p] != 0xFFFFFFFFu && !bad && lane == 0)
+                atomicMin(&A.ctr->first_sol, (unsigned long long)idx[p]);
+            if (lane == p) { my_fp = s; my_idx = idx[p]; }
         }
-        if (my_ok) {
-            uint64_t fp = finish_fp(my_fp, A.fp_mask);
-            A.cand_slot[my_idx] = probe_claim<T>(A, fp, my_idx);
-        }
+        if (my_idx != 0xFFFFFFFFu) A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx);
     } else {
-        const T *tg[NP];
+        // presumed owner of each pair: a stored entry (global id), or none (representative / no slot)
+        uint32_t tgt[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            uint32_t g = 0xFFFFFFFFu;
+            if (idx[p] != 0xFFFFFFFFu) {
+                const uint32_t h = uniform(A.cand_slot[idx[p]]);
+                if (h != NO_SLOT) {
+                    const uint32_t v = uniform(A.tval[h]);
+                    if (v & VAL_SETTLED) g = v & ~VAL_SETTLED;
+                    else if (v != idx[p]) g = A.level_base + uniform(rank_of(A.bitmap, A.wordpre, v));
+                }
+            }
+            tgt[p] = g;
+        }
         T diff[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            diff[p] = 0;
-            tg[p] = nullptr;
-            if (!ok[p]) continue;
-            uint32_t h = A.cand_slot[idx[p]];
-            if (h == NO_SLOT) continue;
-            uint32_t v = A.tval[h];
-            uint32_t g;
-            if (v & VAL_SETTLED) g = v & ~VAL_SETTLED;
-            else if (v == idx[p]) continue;                       // the representative itself
-            else g = A.level_base + rank_of(A.bitmap, A.wordpre, v);
-            tg[p] = A.arena + (size_t)g * R;
-        }
+        for (int p = 0; p < NP; ++p) diff[p] = 0;
         for (uint32_t blk = 0; blk < A.rows.NB; ++blk) {
             const uint32_t r = blk * 64u + (uint32_t)lane;
-            RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+            const RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
             T av[TI], bv[TJ];
 #pragma unroll
             for (int ii = 0; ii < TI; ++ii) av[ii] = ap[ii][r];
@@ -418,42 +409,58 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
 #pragma unroll
                 for (int jj = 0; jj < TJ; ++jj) {
                     const int p = ii * TJ + jj;
-                    T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
-                    if (tg[p]) diff[p] |= w ^ tg[p][r];
+                    if (tgt[p] != 0xFFFFFFFFu) {
+                        const T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
+                        diff[p] |= w ^ A.arena[(size_t)tgt[p] * R + r];
+                    }
                 }
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            bool mism = __ballot(diff[p] != 0) != 0ull;
-            if (mism && lane == 0) atomicOr(&A.coll_bits[idx[p] >> 5], 1u << (idx[p] & 31u));
-            if (mism && lane == 0) atomicAdd(&A.ctr->n_coll, 1u);
+            const bool mism = __ballot(diff[p] != 0) != 0ull;
+            if (mism && lane == 0) {
+                atomicOr(&A.coll_bits[idx[p] >> 5], 1u << (idx[p] & 31u));
+                atomicAdd(&A.ctr->n_coll, 1u);
+            }
         }
     }
 }
 
-template <typename T, bool MW, bool VERIFY>
-__global__ __launch_bounds__(256) void k_level(LevelArgs<T> A) {
+// Connective classes get kernels of their own, so that each is register-
+// allocated for its own tile loop: CLS_UNARY (ATOM, NOT, X, F, G; 4 children
+// per tile), CLS_ANDOR (4 x 4 pairs), CLS_U (4 x 4 pairs, doubling) and
+// CLS_UC (4 x 4 pairs, carry adder).  Blocks of a class are listed in
+// A.cls_blocks with class-local tile numbering.
+enum { CLS_UNARY = 0, CLS_ANDOR = 1, CLS_U = 2, CLS_UC = 3 };
+
+template <typename T, bool MW, bool VERIFY, int CLS>
+__global__ __launch_bounds__(256) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
+                                               uint32_t ntiles) {
     const int lane = (int)__lane_id();
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t t = wave; t < A.ntiles; t += nwaves) {
-        const int bi = find_block_tile(A.blocks, (int)A.nblocks, t);
-        const Block b = A.blocks[bi];
+    for (uint32_t t = wave; t < ntiles; t += nwaves) {
+        const int bi = find_block_tile(blocks, (int)nblocks, t);
+        const Block b = blocks[bi];
         uint32_t i0, j0;
         decode_tile(b, t - b.tile_base, i0, j0);
-        switch (b.op) {
-        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane); break;
-        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane); break;
-        case LTL_U:
-            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
-            else run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
-            break;
-        default: break;
+        i0 = uniform(i0);
+        j0 = uniform(j0);
+        if constexpr (CLS == CLS_UNARY) {
+            switch (b.op) {
+            case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+            case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+            case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+            case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+            default:       run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+            }
+        } else if constexpr (CLS == CLS_ANDOR) {
+            if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+            else run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+        } else if constexpr (CLS == CLS_U) {
+            run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+        } else {
+            run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
         }
     }
 }
@@ -512,10 +519,10 @@ __device__ void cand_write_block(const LevelArgs<T> &A, int op, const T *pa, con
 template <typename T, bool MW>
 __global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t n_entries) {
     const int lane = (int)__lane_id();
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     for (uint32_t e = wave; e < n_entries; e += nwaves) {
-        const uint32_t x = A.recipe[A.level_base + e];
+        const uint32_t x = uniform(A.recipe[A.level_base + e]);
         int op;
         const T *pa, *pb;
         cand_children<T>(A, x, op, pa, pb);
@@ -800,17 +807,30 @@ __global__ void k_trace_fp(const uint32_t *letters, const uint64_t *offsets, uin
 // Launchers (host side of this translation unit)
 // ---------------------------------------------------------------------------
 // Multi-word kernels (lanes of one trace exchange bits) exist for 64-bit words only.
+template <typename T, bool MW, bool V>
+static void launch_cls(const LevelArgs<T> &A, int cls, const Block *blocks, uint32_t nb, uint32_t nt, uint32_t grid,
+                       hipStream_t s) {
+    switch (cls) {
+    case CLS_UNARY: hipLaunchKernelGGL((k_level<T, MW, V, CLS_UNARY>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
+    case CLS_ANDOR: hipLaunchKernelGGL((k_level<T, MW, V, CLS_ANDOR>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
+    case CLS_U:     hipLaunchKernelGGL((k_level<T, MW, V, CLS_U>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
+    default:        hipLaunchKernelGGL((k_level<T, MW, V, CLS_UC>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
+    }
+}
+
+// Multi-word kernels (lanes of one trace exchange bits) exist for 64-bit words only.
 template <typename T>
-hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, uint32_t grid, hipStream_t s) {
+hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls, const Block *blocks,
+                            uint32_t nblocks, uint32_t ntiles, uint32_t grid, hipStream_t s) {
     if constexpr (sizeof(T) == 8) {
         if (mw) {
-            if (verify) hipLaunchKernelGGL((k_level<T, true, true>), dim3(grid), dim3(256), 0, s, A);
-            else hipLaunchKernelGGL((k_level<T, true, false>), dim3(grid), dim3(256), 0, s, A);
+            if (verify) launch_cls<T, true, true>(A, cls, blocks, nblocks, ntiles, grid, s);
+            else launch_cls<T, true, false>(A, cls, blocks, nblocks, ntiles, grid, s);
             return hipGetLastError();
         }
     }
-    if (verify) hipLaunchKernelGGL((k_level<T, false, true>), dim3(grid), dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((k_level<T, false, false>), dim3(grid), dim3(256), 0, s, A);
+    if (verify) launch_cls<T, false, true>(A, cls, blocks, nblocks, ntiles, grid, s);
+    else launch_cls<T, false, false>(A, cls, blocks, nblocks, ntiles, grid, s);
     return hipGetLastError();
 }
 
