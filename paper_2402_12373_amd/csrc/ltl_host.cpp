@@ -28,6 +28,14 @@ namespace {
 
 constexpr int ORDER[7] = {LTL_F, LTL_U, LTL_G, LTL_X, LTL_AND, LTL_OR, LTL_NOT};   // Sec. 3 listing
 constexpr uint32_t MAX_GRID = 8192;
+// A level whose tiles give fewer waves than this is evaluated row-split: waves
+// take chunks of row blocks, so that small levels are not one long chain of
+// dependent row-block loads.
+constexpr uint64_t TARGET_WAVES = 8192;
+constexpr uint64_t MIN_CHUNK = 4;        // row blocks per work item at least (per-item fixed cost)
+// pinned staging: [blocks canonical | blocks by class | counters in | counters out]
+constexpr uint64_t PINNED_BLOCKS = sizeof(Block) * MAX_BLOCKS;
+constexpr uint64_t PINNED_BYTES = 2 * PINNED_BLOCKS + 2 * 256;
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -46,6 +54,8 @@ struct ltl_ctx {
     ltl_ctx_opts o;
     hipStream_t s = nullptr;
     bool busy = false;
+    char *pinned = nullptr;          // page-locked host staging: two block tables + counters
+    uint32_t table_clean_log2 = 0;   // the hash table at the start of the workspace is empty (this size)
 };
 
 struct LevelInfo {
@@ -92,7 +102,9 @@ struct ltl_job {
     uint32_t *tval = nullptr;
     uint32_t slots_log2 = 0;
     uint32_t *recipe = nullptr;
+    uint32_t *entry_slot = nullptr;  // per global entry: its hash slot (to empty the table afterwards)
     uint64_t recipe_cap = 0, max_entries = 0;
+    bool table_consistent = true;    // every claimed slot belongs to a finalized entry
     char *arena = nullptr;
     uint64_t arena_region = 0;     // bytes from arena to the end of the workspace
     uint64_t total_entries = 0;    // entries in the arena
@@ -107,6 +119,7 @@ struct ltl_job {
     bool timing = false;
     std::vector<TimedLaunch> pending;
     std::vector<Block> grouped;
+    Counters ctr_init{};
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[LTL_K_KINDS] = {0};
     uint32_t kernel_launches[LTL_K_KINDS] = {0};
@@ -180,8 +193,10 @@ static double collect_times(ltl_job *j) {
 }
 
 static int sync_read_counters(ltl_job *j, Counters *host) {
-    HIP_TRY(hipMemcpyAsync(host, j->ctr, sizeof(Counters), hipMemcpyDeviceToHost, j->s));
+    Counters *pin = (Counters *)(j->ctx->pinned + 2 * PINNED_BLOCKS + 256);
+    HIP_TRY(hipMemcpyAsync(pin, j->ctr, sizeof(Counters), hipMemcpyDeviceToHost, j->s));
     HIP_TRY(hipStreamSynchronize(j->s));
+    *host = *pin;
     return LTL_OK;
 }
 
@@ -214,11 +229,19 @@ extern "C" int ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out) {
     if (!c) return LTL_E_INVAL;
     c->o = *opts;
     c->s = (hipStream_t)opts->stream;
+    if (hipHostMalloc((void **)&c->pinned, PINNED_BYTES, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return LTL_E_DEVICE;
+    }
     *out = c;
     return LTL_OK;
 }
 
-extern "C" void ltl_ctx_destroy(ltl_ctx *ctx) { delete ctx; }
+extern "C" void ltl_ctx_destroy(ltl_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
 
 extern "C" const char *ltl_status_str(int st) {
     switch (st) {
@@ -317,7 +340,23 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     uint64_t seed = 0x5eed1e55c0ffee11ull;
     for (auto &kk : keys) kk = splitmix64(seed) | 1ull;
 
-    // workspace carve: fixed tables
+    // workspace carve: the language-cache hash table first (12 bytes per slot), at
+    // a fixed place so that a context can hand an emptied table to its next job
+    uint32_t sl = c->o.hash_slots_log2;
+    if (!sl) {
+        sl = 26;
+        while (sl > 10 && (24ull << sl) > j->wsb / 4) --sl;
+    }
+    j->slots_log2 = sl;
+    const uint64_t nslots = 1ull << sl;
+    j->tkey = (unsigned long long *)ws_take(j, nslots * 8);
+    j->tval = (uint32_t *)ws_take(j, nslots * 4);
+    j->max_entries = c->o.max_entries ? c->o.max_entries : nslots / 2;
+    j->recipe_cap = nslots;
+    j->recipe = (uint32_t *)ws_take(j, nslots * 4);
+    j->entry_slot = (uint32_t *)ws_take(j, nslots * 4);
+    if (!j->tkey || !j->tval || !j->recipe || !j->entry_slot) return LTL_E_OOM;
+
     j->ctr = (Counters *)ws_take(j, sizeof(Counters));
     j->valid = ws_take(j, R * j->wbytes);
     j->sepm = ws_take(j, R * j->wbytes);
@@ -340,21 +379,6 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     if (!j->ctr || !j->valid || !j->sepm || !j->sepw || !j->nxt || !j->key || !j->row_trace || !j->row_word ||
         !j->atoms || !j->tfp || !j->blocks_d || !j->blocks_cls_d || !j->letters_d || !j->offsets_d)
         return LTL_E_OOM;
-
-    // language-cache hash table: 12 bytes per slot
-    uint32_t sl = c->o.hash_slots_log2;
-    if (!sl) {
-        sl = 26;
-        while (sl > 10 && (16ull << sl) > (j->wsb - j->used) / 4) --sl;
-    }
-    j->slots_log2 = sl;
-    const uint64_t nslots = 1ull << sl;
-    j->tkey = (unsigned long long *)ws_take(j, nslots * 8);
-    j->tval = (uint32_t *)ws_take(j, nslots * 4);
-    j->max_entries = c->o.max_entries ? c->o.max_entries : nslots / 2;
-    j->recipe_cap = nslots;
-    j->recipe = (uint32_t *)ws_take(j, nslots * 4);
-    if (!j->tkey || !j->tval || !j->recipe) return LTL_E_OOM;
     j->arena = j->ws + align_up(j->used, 256);
     if ((uint64_t)(j->arena - j->ws) >= j->wsb) return LTL_E_OOM;
     j->arena_region = j->wsb - (uint64_t)(j->arena - j->ws);
@@ -381,7 +405,8 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     HIP_TRY(hipMemsetAsync(j->ctr, 0, sizeof(Counters), j->s));
     {
         Timer tm(j, LTL_K_INTAKE);
-        HIP_TRY(launch_table_init(j->tkey, j->tval, nslots, j->s));
+        if (c->table_clean_log2 != sl) HIP_TRY(launch_table_init(j->tkey, j->tval, nslots, j->s));
+        c->table_clean_log2 = 0;   // dirty until the job empties its slots again
         if (wb == 64)
             HIP_TRY(Launch<uint64_t>::pack(j->letters_d, j->offsets_d, j->row_trace, j->row_word, j->R, j->A,
                                            (uint64_t *)j->atoms, j->ctr, j->s));
@@ -458,6 +483,9 @@ extern "C" int ltl_job_create(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opse
 
 extern "C" void ltl_job_destroy(ltl_job *j) {
     if (!j) return;
+    if (j->ctx && j->table_consistent && j->tkey &&
+        launch_clear_slots(j->entry_slot, (uint32_t)j->total_entries, j->tkey, j->tval, j->s) == hipSuccess)
+        j->ctx->table_clean_log2 = j->slots_log2;
     if (j->s) (void)hipStreamSynchronize(j->s); else (void)hipDeviceSynchronize();
     for (auto &t : j->pending) { (void)hipEventDestroy(t.e0); (void)hipEventDestroy(t.e1); }
     for (auto e : j->event_pool) (void)hipEventDestroy(e);
@@ -598,23 +626,31 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         top = (top - bytes) & ~255ull;
         return j->ws + top;
     };
+    const uint64_t nwa = align_up(nw, 64);                 // words, so the bitmaps stay aligned
+    const bool split = ntiles < TARGET_WAVES;
+    // bitmap | coll_bits | fb_bits | cand_viol | cand_fp (split levels), cleared at once
+    const uint64_t clear_bytes = nwa * 4 * 4 + (split ? (uint64_t)nc * 8 : 0);
+    uint32_t *bits3 = (uint32_t *)take_top(align_up(nwa * 4 * 4 + (uint64_t)nc * 8, 256));
     uint32_t *cand_slot = (uint32_t *)take_top((uint64_t)nc * 4);
-    uint32_t *bitmap = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
-    uint32_t *coll_bits = (uint32_t *)take_top((uint64_t)nw * 4);
-    uint32_t *fb_bits = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
     uint32_t *new_slots = (uint32_t *)take_top((uint64_t)new_cap * 4);
     T *stage = (T *)take_top((uint64_t)j->R * sizeof(T));
     const uint64_t arena_off = (uint64_t)(j->arena - j->ws);
     const uint64_t arena_used = j->total_entries * j->cm_bytes;
-    if (!cand_slot || !bitmap || !wordpre || !coll_bits || !fb_bits || !chunks || !new_slots || !stage ||
-        arena_off + arena_used > top)
+    if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !stage || arena_off + arena_used > top)
         return LTL_E_OOM;
+    uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
+    unsigned long long *cand_fp = (unsigned long long *)(bits3 + 4 * nwa);
     const uint64_t arena_free = top - (arena_off + arena_used);
+    const uint32_t arena_cap = (uint32_t)std::min<uint64_t>(
+        {arena_free / j->cm_bytes, j->recipe_cap - j->total_entries, (uint64_t)new_cap});
 
-    HIP_TRY(hipMemcpyAsync(j->blocks_d, lv.blocks.data(), sizeof(Block) * lv.blocks.size(), hipMemcpyHostToDevice,
-                           j->s));
+    Block *pin_blocks = (Block *)j->ctx->pinned;
+    Block *pin_grouped = (Block *)(j->ctx->pinned + PINNED_BLOCKS);
+    Counters *pin_ctr = (Counters *)(j->ctx->pinned + 2 * PINNED_BLOCKS);
+    memcpy(pin_blocks, lv.blocks.data(), sizeof(Block) * lv.blocks.size());
+    HIP_TRY(hipMemcpyAsync(j->blocks_d, pin_blocks, sizeof(Block) * lv.blocks.size(), hipMemcpyHostToDevice, j->s));
     // the same blocks grouped by connective class, each class with its own tile numbering
     const bool ucarry = (j->ctx->o.flags & LTL_CTX_U_CARRY) != 0;
     auto cls_of = [&](uint32_t op) {
@@ -638,14 +674,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         cls_tiles[k] = tb;
     }
     cls_first[4] = (uint32_t)grouped.size();
-    HIP_TRY(hipMemcpyAsync(j->blocks_cls_d, grouped.data(), sizeof(Block) * grouped.size(), hipMemcpyHostToDevice,
-                           j->s));
-    Counters init{};
-    init.first_sol = ~0ull;
-    HIP_TRY(hipMemcpyAsync(j->ctr, &init, sizeof(Counters), hipMemcpyHostToDevice, j->s));
-    HIP_TRY(hipMemsetAsync(bitmap, 0, (uint64_t)nw * 4, j->s));
-    HIP_TRY(hipMemsetAsync(coll_bits, 0, (uint64_t)nw * 4, j->s));
-    HIP_TRY(hipMemsetAsync(fb_bits, 0, (uint64_t)nw * 4, j->s));
+    memcpy(pin_grouped, grouped.data(), sizeof(Block) * grouped.size());
+    HIP_TRY(hipMemcpyAsync(j->blocks_cls_d, pin_grouped, sizeof(Block) * grouped.size(), hipMemcpyHostToDevice, j->s));
+    *pin_ctr = Counters{};
+    pin_ctr->first_sol = ~0ull;
+    HIP_TRY(hipMemcpyAsync(j->ctr, pin_ctr, sizeof(Counters), hipMemcpyHostToDevice, j->s));
+    HIP_TRY(hipMemsetAsync(bits3, 0, clear_bytes, j->s));
 
     LevelArgs<T> A{};
     A.rows = make_rows<T>(j);
@@ -668,48 +702,68 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.level_base = lv.gid_base;
     A.recipe = j->recipe;
     A.stage = stage;
-    A.ucarry = (j->ctx->o.flags & LTL_CTX_U_CARRY) ? 1 : 0;
+    A.arena_cap = arena_cap;
+    A.ucarry = ucarry ? 1 : 0;
+    A.split_mode = split ? 1u : 0u;
+    A.cand_fp = cand_fp;
+    A.cand_viol = cand_viol;
+    {   // materialize work items: entries x row chunks (sized on the candidate count, an upper bound)
+        const uint64_t per = std::max<uint64_t>(
+            1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max<uint64_t>(1, new_cap)));
+        A.mat_chunk = (uint32_t)((j->NB + per - 1) / per);
+    }
     auto launch_level = [&](bool verify) -> hipError_t {
         for (int k = 0; k < 4; ++k) {
             if (!cls_tiles[k]) continue;
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] + 3) / 4, MAX_GRID);
+            uint64_t per = 1;          // row chunks per tile
+            if (split)
+                per = std::max<uint64_t>(1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK,
+                                                              TARGET_WAVES / cls_tiles[k]));
+            const uint32_t chunk = (uint32_t)((j->NB + per - 1) / per);
+            const uint64_t nchunk = (j->NB + chunk - 1) / chunk;
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] * nchunk + 3) / 4, MAX_GRID);
             hipError_t e = Launch<T>::level(A, j->mw, verify, k, j->blocks_cls_d + cls_first[k],
-                                            cls_first[k + 1] - cls_first[k], cls_tiles[k], grid, j->s);
+                                            cls_first[k + 1] - cls_first[k], cls_tiles[k], chunk, grid, j->s);
             if (e != hipSuccess) return e;
         }
+        if (!verify && split) return Launch<T>::probe(A, nc, j->s);
         return hipSuccess;
     };
-
+    // kernels after the evaluation read the level's new-entry count on the device
+    const uint32_t grid_new = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((new_cap + 255) / 256, 2048));
+    const uint64_t mat_items = (uint64_t)new_cap * ((j->NB + A.mat_chunk - 1) / A.mat_chunk);
+    const uint32_t grid_mat = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((mat_items + 3) / 4, MAX_GRID));
+    j->table_consistent = false;
     {
         Timer tm(j, LTL_K_EVAL);
         HIP_TRY(launch_level(false));
     }
-    Counters hc;
-    if (int e = sync_read_counters(j, &hc)) return e;
-    if (hc.overflow) return LTL_E_OOM;
-    lv.first = (hc.first_sol == ~0ull) ? LTL_NO_SOLUTION : (uint64_t)hc.first_sol;
-    uint32_t n_new = hc.n_new;
-    const bool found = lv.first != LTL_NO_SOLUTION;
-    lv.stored = !found && c < j->bound;
-
-    // the level's new entries go to the arena (they serve as owners for the verify pass)
-    if ((uint64_t)n_new * j->cm_bytes > arena_free || j->total_entries + n_new > j->recipe_cap) return LTL_E_OOM;
     {
         Timer tm(j, LTL_K_COMPACT);
-        HIP_TRY(launch_mark(new_slots, n_new, j->tval, bitmap, j->s));
-        HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
-        HIP_TRY(launch_scatter(new_slots, n_new, j->tval, bitmap, wordpre, j->recipe, lv.gid_base, j->s));
+        if (nw <= SMALL_COMPACT_WORDS) {
+            HIP_TRY(launch_compact_small(new_slots, j->ctr, arena_cap, j->tval, bitmap, nw, wordpre, j->recipe,
+                                         lv.gid_base, j->s));
+        } else {
+            HIP_TRY(launch_mark(new_slots, j->ctr, arena_cap, j->tval, bitmap, grid_new, j->s));
+            HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
+            HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
+                                   grid_new, j->s));
+        }
     }
-    const uint32_t grid_mat = std::max<uint32_t>(1, std::min<uint32_t>((n_new + 3) / 4, MAX_GRID));
-    if (n_new) {
+    {
         Timer tm(j, LTL_K_MATERIALIZE);
-        HIP_TRY(Launch<T>::materialize(A, j->mw, n_new, grid_mat, j->s));
+        HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
     }
     {
         Timer tm(j, LTL_K_VERIFY);
         HIP_TRY(launch_level(true));
     }
+    Counters hc;
     if (int e = sync_read_counters(j, &hc)) return e;
+    if (hc.overflow || hc.n_new > arena_cap) return LTL_E_OOM;
+    lv.first = (hc.first_sol == ~0ull) ? LTL_NO_SOLUTION : (uint64_t)hc.first_sol;
+    lv.stored = lv.first == LTL_NO_SOLUTION && c < j->bound;
+    uint32_t n_new = hc.n_new;
     lv.colliders = hc.n_coll;
     if (hc.n_coll) {
         // exact resolution of fingerprint collisions, in canonical order
@@ -718,27 +772,26 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             HIP_TRY(Launch<T>::fallback(A, j->mw, nw, nc, j->s));
         }
         if (int e = sync_read_counters(j, &hc)) return e;
-        if (hc.overflow) return LTL_E_OOM;
+        if (hc.overflow || hc.n_new > arena_cap) return LTL_E_OOM;
         n_new = hc.n_new;
-        if ((uint64_t)n_new * j->cm_bytes > arena_free || j->total_entries + n_new > j->recipe_cap) return LTL_E_OOM;
         {
             Timer tm(j, LTL_K_COMPACT);
             HIP_TRY(launch_or_bits(bitmap, fb_bits, nw, j->s));
             HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
-            HIP_TRY(launch_scatter(new_slots, n_new, j->tval, bitmap, wordpre, j->recipe, lv.gid_base, j->s));
+            HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
+                                   grid_new, j->s));
         }
         {
             Timer tm(j, LTL_K_MATERIALIZE);
-            HIP_TRY(Launch<T>::materialize(A, j->mw, n_new,
-                                           std::max<uint32_t>(1, std::min<uint32_t>((n_new + 3) / 4, MAX_GRID)),
-                                           j->s));
+            HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
         }
     }
     {
         Timer tm(j, LTL_K_COMPACT);
-        HIP_TRY(launch_finalize(new_slots, n_new, j->tval, bitmap, wordpre, lv.gid_base, j->s));
+        HIP_TRY(launch_finalize(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, lv.gid_base, j->entry_slot,
+                                grid_new, j->s));
     }
-    HIP_TRY(hipStreamSynchronize(j->s));
+    j->table_consistent = true;
     lv.n = n_new;
     j->total_entries += n_new;
     return LTL_OK;

@@ -74,7 +74,15 @@ struct LevelArgs {
     uint32_t level_base;     // global id of the level's first entry
     uint32_t *recipe;        // per global entry: canonical candidate index in its level
     T *stage;                // R words of scratch for the fallback
+    uint32_t arena_cap;      // new entries the arena can take this level
     int ucarry;
+    // Row-split evaluation of small levels: a wave takes one chunk of row blocks of
+    // a tile; fingerprint sums (order-free, mod 2^64) and separation violations are
+    // combined per candidate, and k_probe claims the cache slots afterwards.
+    uint32_t split_mode;
+    unsigned long long *cand_fp;   // per candidate: sum of partial fingerprints
+    uint32_t *cand_viol;           // per candidate: separation violated (bit)
+    uint32_t mat_chunk;            // row blocks per materialize work item
 };
 
 
@@ -82,7 +90,8 @@ template <typename T>
 struct Launch {
     // cls: 0 unary, 1 and/or, 2 until (doubling), 3 until (carry adder)
     static hipError_t level(const LevelArgs<T> &A, bool mw, bool verify, int cls, const Block *blocks,
-                            uint32_t nblocks, uint32_t ntiles, uint32_t grid, hipStream_t s);
+                            uint32_t nblocks, uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
+    static hipError_t probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
     static hipError_t materialize(const LevelArgs<T> &A, bool mw, uint32_t n, uint32_t grid, hipStream_t s);
     static hipError_t fallback(const LevelArgs<T> &A, bool mw, uint32_t nwords, uint32_t ncand, hipStream_t s);
     static hipError_t pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
@@ -91,12 +100,22 @@ struct Launch {
 };
 
 hipError_t launch_scan(const uint32_t *bits, uint32_t nw, uint32_t *chunk_sums, uint32_t *wordpre, hipStream_t s);
-hipError_t launch_mark(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, uint32_t *bitmap, hipStream_t s);
+hipError_t launch_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                       uint32_t *bitmap, uint32_t grid, hipStream_t s);
 hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipStream_t s);
-hipError_t launch_scatter(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, const uint32_t *bitmap,
-                          const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base, hipStream_t s);
-hipError_t launch_finalize(const uint32_t *new_slots, uint32_t n, uint32_t *tval, const uint32_t *bitmap,
-                           const uint32_t *wordpre, uint32_t level_base, hipStream_t s);
+// mark + scan + scatter in one workgroup, for levels with at most SMALL_COMPACT_WORDS bitmap words
+constexpr uint32_t SMALL_COMPACT_WORDS = 8192;
+hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                                uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
+                                uint32_t level_base, hipStream_t s);
+hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                          const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
+                          uint32_t grid, hipStream_t s);
+hipError_t launch_finalize(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
+                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t level_base,
+                           uint32_t *entry_slot, uint32_t grid, hipStream_t s);
+hipError_t launch_clear_slots(const uint32_t *entry_slot, uint32_t n, unsigned long long *tkey, uint32_t *tval,
+                              hipStream_t s);
 hipError_t launch_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t nslots, hipStream_t s);
 hipError_t launch_trace_fp(const uint32_t *letters, const uint64_t *offsets, uint32_t ntr, uint64_t *out,
                            hipStream_t s);

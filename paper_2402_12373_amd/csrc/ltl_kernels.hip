@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ltl.h"
 #include "ltl_internal.h"
 
@@ -50,27 +52,59 @@ struct RowMeta {
     uint64_t nx, hn, k0, k1;
 };
 
-template <typename T, bool MW>
+// Global-address-space views: loads through them become global_load with a
+// scalar base and a 32-bit lane offset (no flat addressing).
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)(uintptr_t)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(uint64_t p) {
+    return (gptr<T>)(uintptr_t)p;
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+
+// FULL: everything the evaluation pass needs (separation bits, fingerprint keys);
+// LIGHT: valid bits and the trace-continuation mask only (verify, materialize).
+template <typename T, bool MW, bool FULL>
 __device__ __forceinline__ RowMeta<T> load_meta(const Rows<T> &rw, uint32_t r, int lane) {
     RowMeta<T> m;
-    m.v = rw.valid[r];
-    m.sm = rw.sepm[r];
-    m.sw = rw.sepw[r];
+    m.v = as_global(rw.valid)[r];
+    if constexpr (FULL) {
+        m.sw = as_global(rw.sepw)[r];
+        if constexpr (MW || sizeof(T) == 8) m.sm = as_global(rw.sepm)[r];
+        else m.sm = m.v & (T)0x80000000u;     // one word per trace: every live row is a first word
+        if constexpr (sizeof(T) == 8) {       // two 32-bit halves, two keys per row
+            m.k0 = as_global(rw.key)[2 * (size_t)r];
+            m.k1 = as_global(rw.key)[2 * (size_t)r + 1];
+        } else {
+            m.k0 = as_global(rw.key)[r];
+            m.k1 = 0;
+        }
+    } else {
+        m.sm = m.sw = 0;
+        m.k0 = m.k1 = 0;
+    }
     if constexpr (MW) {
-        m.nx = rw.nxt[r];
-        m.hn = __ballot((m.nx & (2ull << lane)) != 0ull);
+        m.nx = as_global(rw.nxt)[r];
     } else {
         m.nx = 0;
-        m.hn = 0;
     }
-    if constexpr (sizeof(T) == 8) {       // two 32-bit halves, two keys per row
-        m.k0 = rw.key[2 * (size_t)r];
-        m.k1 = rw.key[2 * (size_t)r + 1];
-    } else {
-        m.k0 = rw.key[r];
-        m.k1 = 0;
-    }
+    m.hn = 0;
     return m;
+}
+
+// Wave-uniform part of the metadata, computed once the loads have landed.
+template <typename T, bool MW>
+__device__ __forceinline__ void finish_meta(RowMeta<T> &m, int lane) {
+    if constexpr (MW) m.hn = __ballot((m.nx & (2ull << lane)) != 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,22 +349,23 @@ __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx
 // EVAL   : fingerprint + separation, probe/claim in the language cache.
 // VERIFY : recompute, compare in full with the presumed owner.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
 template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY>
-__device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane) {
+__device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane, uint32_t rb0,
+                         uint32_t rb1) {
     constexpr int NP = TI * TJ;
     constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
     const uint32_t R = A.rows.R;
     const uint32_t nbj = b.tri ? b.na : b.nb;
     // child matrices of the tile (clamped; results of out-of-range pairs are dropped)
-    const T *ap[TI];
-    const T *bp[TJ];
+    gptr<T> ap[TI];
+    gptr<T> bp[TJ];
 #pragma unroll
-    for (int ii = 0; ii < TI; ++ii) ap[ii] = (const T *)b.a_ptr + (size_t)min(i0 + ii, b.na - 1) * R;
+    for (int ii = 0; ii < TI; ++ii)
+        ap[ii] = as_global<T>(uniform64(b.a_ptr + (uint64_t)min(i0 + ii, b.na - 1) * R * sizeof(T)));
 #pragma unroll
     for (int jj = 0; jj < TJ; ++jj)
-        bp[jj] = BIN ? (const T *)b.b_ptr + (size_t)min(j0 + jj, nbj - 1) * R : (const T *)nullptr;
+        bp[jj] = BIN ? as_global<T>(uniform64(b.b_ptr + (uint64_t)min(j0 + jj, nbj - 1) * R * sizeof(T)))
+                     : (gptr<T>)nullptr;
     // canonical index of each pair, 0xFFFFFFFF if the pair is outside the block
     uint32_t idx[NP];
 #pragma unroll
@@ -340,46 +375,18 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
             const uint32_t i = i0 + ii, j = j0 + jj;
             bool v = i < b.na;
             if constexpr (BIN) v = v && (b.tri ? (j < b.na && j > i) : (j < b.nb));
-            idx[ii * TJ + jj] = v ? cand_index(b, i, j) : 0xFFFFFFFFu;
+            idx[ii * TJ + jj] = uniform(v ? cand_index(b, i, j) : 0xFFFFFFFFu);
         }
 
-    if constexpr (!VERIFY) {
-        uint64_t acc[NP];
-        T viol[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) { acc[p] = 0; viol[p] = 0; }
-        for (uint32_t blk = 0; blk < A.rows.NB; ++blk) {
-            const uint32_t r = blk * 64u + (uint32_t)lane;
-            const RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
-            T av[TI], bv[TJ];
-#pragma unroll
-            for (int ii = 0; ii < TI; ++ii) av[ii] = ap[ii][r];
-#pragma unroll
-            for (int jj = 0; jj < TJ; ++jj) bv[jj] = BIN ? bp[jj][r] : (T)0;
-#pragma unroll
-            for (int ii = 0; ii < TI; ++ii)
-#pragma unroll
-                for (int jj = 0; jj < TJ; ++jj) {
-                    const int p = ii * TJ + jj;
-                    const T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
-                    viol[p] |= (w ^ m.sw) & m.sm;
-                    fp_add<T>(acc[p], w, m);
-                }
-        }
-        uint64_t my_fp = 0;
-        uint32_t my_idx = 0xFFFFFFFFu;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const uint64_t s = wave_sum(acc[p]);
-            const bool bad = __ballot(viol[p] != 0) != 0ull;
-            if (idx[p] != 0xFFFFFFFFu && !bad && lane == 0)
-                atomicMin(&A.ctr->first_sol, (unsigned long long)idx[p]);
-            if (lane == p) { my_fp = s; my_idx = idx[p]; }
-        }
-        if (my_idx != 0xFFFFFFFFu) A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx);
-    } else {
+    // one row block of operands (and, for VERIFY, of the owners), loaded one block ahead
+    struct Rowset {
+        RowMeta<T> m;
+        T av[TI], bv[TJ];
+        T tv[VERIFY ? NP : 1];
+    };
+    uint32_t tgt[VERIFY ? NP : 1];
+    if constexpr (VERIFY) {
         // presumed owner of each pair: a stored entry (global id), or none (representative / no slot)
-        uint32_t tgt[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             uint32_t g = 0xFFFFFFFFu;
@@ -393,37 +400,100 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
             }
             tgt[p] = g;
         }
+    }
+    gptr<T> arena = as_global<T>((const T *)A.arena);
+    auto load = [&](uint32_t blk, Rowset &L) {
+        const uint32_t r = blk * 64u + (uint32_t)lane;
+        L.m = load_meta<T, MW, !VERIFY>(A.rows, r, lane);
+#pragma unroll
+        for (int ii = 0; ii < TI; ++ii) L.av[ii] = ap[ii][r];
+#pragma unroll
+        for (int jj = 0; jj < TJ; ++jj) L.bv[jj] = BIN ? bp[jj][r] : (T)0;
+        if constexpr (VERIFY) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                L.tv[p] = (tgt[p] != 0xFFFFFFFFu) ? arena[(size_t)tgt[p] * R + r] : (T)0;
+        }
+    };
+
+    if constexpr (!VERIFY) {
+        uint64_t acc[NP];
+        T viol[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) { acc[p] = 0; viol[p] = 0; }
+        Rowset cur, nxt;
+        load(rb0, cur);
+        for (uint32_t blk = rb0; blk < rb1; ++blk) {
+            if (blk + 1 < rb1) load(blk + 1, nxt);
+            finish_meta<T, MW>(cur.m, lane);
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < TJ; ++jj) {
+                    const int p = ii * TJ + jj;
+                    const T w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
+                    viol[p] |= (w ^ cur.m.sw) & cur.m.sm;
+                    fp_add<T>(acc[p], w, cur.m);
+                }
+            cur = nxt;
+        }
+        uint64_t my_fp = 0;
+        uint32_t my_idx = 0xFFFFFFFFu;
+        bool my_bad = false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const uint64_t sum = wave_sum(acc[p]);
+            const bool bad = __ballot(viol[p] != 0) != 0ull;
+            if (lane == p) { my_fp = sum; my_idx = idx[p]; my_bad = bad; }
+        }
+        if (my_idx != 0xFFFFFFFFu) {
+            if (A.split_mode) {        // partial result of one row chunk
+                atomicAdd(&A.cand_fp[my_idx], (unsigned long long)my_fp);
+                if (my_bad) atomicOr(&A.cand_viol[my_idx >> 5], 1u << (my_idx & 31u));
+            } else {
+                if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
+                A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx);
+            }
+        }
+    } else {
         T diff[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) diff[p] = 0;
-        for (uint32_t blk = 0; blk < A.rows.NB; ++blk) {
-            const uint32_t r = blk * 64u + (uint32_t)lane;
-            const RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
-            T av[TI], bv[TJ];
-#pragma unroll
-            for (int ii = 0; ii < TI; ++ii) av[ii] = ap[ii][r];
-#pragma unroll
-            for (int jj = 0; jj < TJ; ++jj) bv[jj] = BIN ? bp[jj][r] : (T)0;
+        Rowset cur, nxt;
+        load(rb0, cur);
+        for (uint32_t blk = rb0; blk < rb1; ++blk) {
+            if (blk + 1 < rb1) load(blk + 1, nxt);
+            finish_meta<T, MW>(cur.m, lane);
 #pragma unroll
             for (int ii = 0; ii < TI; ++ii)
 #pragma unroll
                 for (int jj = 0; jj < TJ; ++jj) {
                     const int p = ii * TJ + jj;
                     if (tgt[p] != 0xFFFFFFFFu) {
-                        const T w = apply<T, MW, OP>(av[ii], bv[jj], m, A.rows, lane);
-                        diff[p] |= w ^ A.arena[(size_t)tgt[p] * R + r];
+                        const T w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
+                        diff[p] |= w ^ cur.tv[p];
                     }
                 }
+            cur = nxt;
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const bool mism = __ballot(diff[p] != 0) != 0ull;
             if (mism && lane == 0) {
-                atomicOr(&A.coll_bits[idx[p] >> 5], 1u << (idx[p] & 31u));
-                atomicAdd(&A.ctr->n_coll, 1u);
+                const uint32_t bit = 1u << (idx[p] & 31u);
+                if (!(atomicOr(&A.coll_bits[idx[p] >> 5], bit) & bit)) atomicAdd(&A.ctr->n_coll, 1u);
             }
         }
     }
+}
+
+__device__ __forceinline__ Block uniform_block(const Block &in) {
+    Block b;
+    const uint32_t *src = (const uint32_t *)&in;
+    uint32_t *dst = (uint32_t *)&b;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(Block) / 4); ++k) dst[k] = uniform(src[k]);
+    return b;
 }
 
 // Connective classes get kernels of their own, so that each is register-
@@ -435,33 +505,51 @@ enum { CLS_UNARY = 0, CLS_ANDOR = 1, CLS_U = 2, CLS_UC = 3 };
 
 template <typename T, bool MW, bool VERIFY, int CLS>
 __global__ __launch_bounds__(256) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
-                                               uint32_t ntiles) {
+                                               uint32_t ntiles, uint32_t chunk) {
     const int lane = (int)__lane_id();
+    if constexpr (VERIFY) {
+        if (uniform(A.ctr->overflow) || uniform(A.ctr->n_new) > A.arena_cap) return;
+    }
+    const uint32_t NB = A.rows.NB;
+    const uint32_t nchunk = (NB + chunk - 1) / chunk;          // row chunks per tile
+    const uint32_t nwork = ntiles * nchunk;
     const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t t = wave; t < ntiles; t += nwaves) {
-        const int bi = find_block_tile(blocks, (int)nblocks, t);
-        const Block b = blocks[bi];
+    for (uint32_t w = wave; w < nwork; w += nwaves) {
+        const uint32_t t = w / nchunk, q = w - t * nchunk;
+        const uint32_t rb0 = q * chunk, rb1 = min(NB, rb0 + chunk);
+        const int bi = (int)uniform((uint32_t)find_block_tile(blocks, (int)nblocks, t));
+        const Block b = uniform_block(blocks[bi]);
         uint32_t i0, j0;
         decode_tile(b, t - b.tile_base, i0, j0);
         i0 = uniform(i0);
         j0 = uniform(j0);
         if constexpr (CLS == CLS_UNARY) {
             switch (b.op) {
-            case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-            case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-            case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-            case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
-            default:       run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane); break;
+            case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+            default:       run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
             }
         } else if constexpr (CLS == CLS_ANDOR) {
-            if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
-            else run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+            if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+            else run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
         } else if constexpr (CLS == CLS_U) {
-            run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+            run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
         } else {
-            run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane);
+            run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
         }
+    }
+}
+
+// Row-split levels: combine the partial results and claim cache slots.
+template <typename T>
+__global__ __launch_bounds__(256) void k_probe(LevelArgs<T> A, uint32_t ncand) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ncand; x += gridDim.x * blockDim.x) {
+        const bool bad = (A.cand_viol[x >> 5] >> (x & 31u)) & 1u;
+        if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)x);
+        A.cand_slot[x] = probe_claim<T>(A, finish_fp(A.cand_fp[x], A.fp_mask), x);
     }
 }
 
@@ -495,7 +583,8 @@ template <typename T, bool MW, int OP>
 __device__ void cand_rowblock(const LevelArgs<T> &A, const T *pa, const T *pb, uint32_t blk, int lane,
                               T *dst) {
     const uint32_t r = blk * 64u + (uint32_t)lane;
-    RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+    RowMeta<T> m = load_meta<T, MW, false>(A.rows, r, lane);
+    finish_meta<T, MW>(m, lane);
     dst[r] = cand_word<T, MW, OP>(A, pa, pb, r, lane, m);
 }
 
@@ -515,19 +604,73 @@ __device__ void cand_write_block(const LevelArgs<T> &A, int op, const T *pa, con
     }
 }
 
+// One candidate's whole matrix into dst, four row blocks per iteration so that
+// every wave keeps several loads in flight.
+template <typename T, bool MW, int OP>
+__device__ void write_matrix(const LevelArgs<T> &A, const T *pa, const T *pb, T *dst, int lane, uint32_t rb0,
+                             uint32_t NB) {
+    constexpr int UNR = 4;
+    constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
+    gptr<T> a = as_global<T>(pa);
+    gptr<T> b = as_global<T>(pb);
+    __attribute__((address_space(1))) T *d = (__attribute__((address_space(1))) T *)(uintptr_t)dst;
+    for (uint32_t blk = rb0; blk < NB; blk += UNR) {
+        RowMeta<T> m[UNR];
+        T av[UNR], bv[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (blk + u < NB) {
+                const uint32_t r = (blk + u) * 64u + (uint32_t)lane;
+                m[u] = load_meta<T, MW, false>(A.rows, r, lane);
+                av[u] = a[r];
+                bv[u] = BIN ? b[r] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (blk + u < NB) {
+                const uint32_t r = (blk + u) * 64u + (uint32_t)lane;
+                finish_meta<T, MW>(m[u], lane);
+                d[r] = apply<T, MW, OP>(av[u], bv[u], m[u], A.rows, lane);
+            }
+        }
+    }
+}
+
 // New entries of the level: entry e holds the representative recipe[base + e].
+// A work item is one chunk of A.mat_chunk row blocks of one entry.
 template <typename T, bool MW>
-__global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t n_entries) {
+__global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t n_fixed) {
     const int lane = (int)__lane_id();
+    const uint32_t n_entries = n_fixed ? n_fixed : uniform(level_new_count(A.ctr, A.arena_cap));
+    const uint32_t NB = A.rows.NB;
+    const uint32_t chunk = A.mat_chunk;
+    const uint32_t nchunk = (NB + chunk - 1) / chunk;
+    const uint32_t nwork = n_entries * nchunk;
     const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t e = wave; e < n_entries; e += nwaves) {
+    for (uint32_t w = wave; w < nwork; w += nwaves) {
+        const uint32_t e = w / nchunk, q = w - e * nchunk;
+        const uint32_t rb0 = q * chunk, rb1 = min(NB, rb0 + chunk);
         const uint32_t x = uniform(A.recipe[A.level_base + e]);
         int op;
         const T *pa, *pb;
         cand_children<T>(A, x, op, pa, pb);
+        op = (int)uniform((uint32_t)op);
+        pa = (const T *)uniform64((uint64_t)(uintptr_t)pa);
+        pb = (const T *)uniform64((uint64_t)(uintptr_t)pb);
         T *dst = A.arena + (size_t)(A.level_base + e) * A.rows.R;
-        for (uint32_t blk = 0; blk < A.rows.NB; ++blk) cand_write_block<T, MW>(A, op, pa, pb, blk, lane, dst);
+        switch (op) {
+        case LTL_ATOM: write_matrix<T, MW, LTL_ATOM>(A, pa, pb, dst, lane, rb0, rb1); break;
+        case LTL_NOT:  write_matrix<T, MW, LTL_NOT>(A, pa, pb, dst, lane, rb0, rb1); break;
+        case LTL_X:    write_matrix<T, MW, LTL_X>(A, pa, pb, dst, lane, rb0, rb1); break;
+        case LTL_F:    write_matrix<T, MW, LTL_F>(A, pa, pb, dst, lane, rb0, rb1); break;
+        case LTL_G:    write_matrix<T, MW, LTL_G>(A, pa, pb, dst, lane, rb0, rb1); break;
+        case LTL_AND:  write_matrix<T, MW, LTL_AND>(A, pa, pb, dst, lane, rb0, rb1); break;
+        case LTL_OR:   write_matrix<T, MW, LTL_OR>(A, pa, pb, dst, lane, rb0, rb1); break;
+        case LTL_U:    write_matrix<T, MW, LTL_U>(A, pa, pb, dst, lane, rb0, rb1); break;
+        default:       write_matrix<T, MW, OP_UC>(A, pa, pb, dst, lane, rb0, rb1); break;
+        }
     }
 }
 
@@ -550,7 +693,8 @@ __device__ bool fb_equal(const LevelArgs<T> &A, const T *target, int t_op, const
         if (target) {
             tw = target[r];
         } else {
-            RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+            RowMeta<T> m = load_meta<T, MW, false>(A.rows, r, lane);
+            finish_meta<T, MW>(m, lane);
             switch (t_op) {
             case LTL_ATOM: tw = cand_word<T, MW, LTL_ATOM>(A, t_pa, t_pb, r, lane, m); break;
             case LTL_NOT:  tw = cand_word<T, MW, LTL_NOT>(A, t_pa, t_pb, r, lane, m); break;
@@ -597,7 +741,7 @@ __global__ __launch_bounds__(256) void k_fallback(LevelArgs<T> A, uint32_t nword
             __syncthreads();
             for (uint32_t blk = (uint32_t)wv; blk < A.rows.NB; blk += (uint32_t)nw) {
                 const uint32_t r = blk * 64u + (uint32_t)lane;
-                RowMeta<T> m = load_meta<T, MW>(A.rows, r, lane);
+                RowMeta<T> m = load_meta<T, MW, true>(A.rows, r, lane);
                 fp_add<T>(acc, A.stage[r], m);
             }
             acc = wave_sum(acc);
@@ -724,12 +868,60 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *bits, uint32
     }
 }
 
+// The number of new groups of the level is read on the device (no host round
+// trip between the level's kernels); a level whose new entries would not fit
+// the arena (or the slot list) is marked in ctr->overflow and left alone.
+__device__ __forceinline__ uint32_t level_new_count(const Counters *ctr, uint32_t cap) {
+    const uint32_t n = ctr->n_new;
+    return (n <= cap && !ctr->overflow) ? n : 0u;
+}
+
+// Small levels (at most SMALL_WORDS bitmap words): representative bits, their
+// ordered prefix and the recipes in one workgroup of 1024 threads.
+constexpr uint32_t SMALL_WPT = 8;
+constexpr uint32_t SMALL_WORDS = 1024 * SMALL_WPT;
+
+__global__ __launch_bounds__(1024) void k_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap,
+                                                        const uint32_t *tval, uint32_t *bitmap, uint32_t nw,
+                                                        uint32_t *wordpre, uint32_t *recipe, uint32_t level_base) {
+    __shared__ uint32_t s_tmp[16];
+    const uint32_t n = level_new_count(ctr, cap);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t x = tval[new_slots[i]];
+        atomicOr(&bitmap[x >> 5], 1u << (x & 31u));
+    }
+    __syncthreads();
+    const uint32_t base = threadIdx.x * SMALL_WPT;
+    uint32_t c[SMALL_WPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SMALL_WPT; ++k) {
+        c[k] = (base + k < nw) ? (uint32_t)__popc(__hip_atomic_load(&bitmap[base + k], __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT)) : 0u;
+        sum += c[k];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, s_tmp, total);
+#pragma unroll
+    for (uint32_t k = 0; k < SMALL_WPT; ++k) {
+        if (base + k < nw) wordpre[base + k] = run;
+        run += c[k];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t x = tval[new_slots[i]];
+        recipe[level_base + rank_of(bitmap, wordpre, x)] = x;
+    }
+}
+
 // slot owners -> representative bits
-__global__ void k_mark(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, uint32_t *bitmap) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t x = tval[new_slots[i]];
-    atomicOr(&bitmap[x >> 5], 1u << (x & 31u));
+__global__ void k_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                       uint32_t *bitmap) {
+    const uint32_t n = level_new_count(ctr, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t x = tval[new_slots[i]];
+        atomicOr(&bitmap[x >> 5], 1u << (x & 31u));
+    }
 }
 
 __global__ void k_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw) {
@@ -738,22 +930,35 @@ __global__ void k_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw) {
 }
 
 // representatives -> recipes (entry order = canonical order of the representative)
-__global__ void k_scatter(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, const uint32_t *bitmap,
-                          const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t x = tval[new_slots[i]];
-    recipe[level_base + rank_of(bitmap, wordpre, x)] = x;
+__global__ void k_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                          const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base) {
+    const uint32_t n = level_new_count(ctr, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t x = tval[new_slots[i]];
+        recipe[level_base + rank_of(bitmap, wordpre, x)] = x;
+    }
 }
 
-// settle the level's slots: owner index -> global entry id
-__global__ void k_finalize(const uint32_t *new_slots, uint32_t n, uint32_t *tval, const uint32_t *bitmap,
-                           const uint32_t *wordpre, uint32_t level_base) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t s = new_slots[i];
-    const uint32_t x = tval[s];
-    tval[s] = VAL_SETTLED | (level_base + rank_of(bitmap, wordpre, x));
+// settle the level's slots: owner index -> global entry id; remember each entry's slot
+__global__ void k_finalize(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
+                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t level_base,
+                           uint32_t *entry_slot) {
+    const uint32_t n = level_new_count(ctr, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t s = new_slots[i];
+        const uint32_t g = level_base + rank_of(bitmap, wordpre, tval[s]);
+        tval[s] = VAL_SETTLED | g;
+        entry_slot[g] = s;
+    }
+}
+
+// return the slots of a finished job to the empty state
+__global__ void k_clear_slots(const uint32_t *entry_slot, uint32_t n, unsigned long long *tkey, uint32_t *tval) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t s = entry_slot[i];
+        tkey[s] = 0ull;
+        tval[s] = VAL_OPEN;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -808,29 +1013,36 @@ __global__ void k_trace_fp(const uint32_t *letters, const uint64_t *offsets, uin
 // ---------------------------------------------------------------------------
 // Multi-word kernels (lanes of one trace exchange bits) exist for 64-bit words only.
 template <typename T, bool MW, bool V>
-static void launch_cls(const LevelArgs<T> &A, int cls, const Block *blocks, uint32_t nb, uint32_t nt, uint32_t grid,
-                       hipStream_t s) {
+static void launch_cls(const LevelArgs<T> &A, int cls, const Block *blocks, uint32_t nb, uint32_t nt, uint32_t ch,
+                       uint32_t grid, hipStream_t s) {
     switch (cls) {
-    case CLS_UNARY: hipLaunchKernelGGL((k_level<T, MW, V, CLS_UNARY>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
-    case CLS_ANDOR: hipLaunchKernelGGL((k_level<T, MW, V, CLS_ANDOR>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
-    case CLS_U:     hipLaunchKernelGGL((k_level<T, MW, V, CLS_U>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
-    default:        hipLaunchKernelGGL((k_level<T, MW, V, CLS_UC>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt); break;
+    case CLS_UNARY: hipLaunchKernelGGL((k_level<T, MW, V, CLS_UNARY>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    case CLS_ANDOR: hipLaunchKernelGGL((k_level<T, MW, V, CLS_ANDOR>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    case CLS_U:     hipLaunchKernelGGL((k_level<T, MW, V, CLS_U>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    default:        hipLaunchKernelGGL((k_level<T, MW, V, CLS_UC>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
     }
 }
 
 // Multi-word kernels (lanes of one trace exchange bits) exist for 64-bit words only.
 template <typename T>
 hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls, const Block *blocks,
-                            uint32_t nblocks, uint32_t ntiles, uint32_t grid, hipStream_t s) {
+                            uint32_t nblocks, uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s) {
     if constexpr (sizeof(T) == 8) {
         if (mw) {
-            if (verify) launch_cls<T, true, true>(A, cls, blocks, nblocks, ntiles, grid, s);
-            else launch_cls<T, true, false>(A, cls, blocks, nblocks, ntiles, grid, s);
+            if (verify) launch_cls<T, true, true>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
+            else launch_cls<T, true, false>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
             return hipGetLastError();
         }
     }
-    if (verify) launch_cls<T, false, true>(A, cls, blocks, nblocks, ntiles, grid, s);
-    else launch_cls<T, false, false>(A, cls, blocks, nblocks, ntiles, grid, s);
+    if (verify) launch_cls<T, false, true>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
+    else launch_cls<T, false, false>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((ncand + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_probe<T>), dim3(grid), dim3(256), 0, s, A, ncand);
     return hipGetLastError();
 }
 
@@ -879,9 +1091,17 @@ hipError_t launch_scan(const uint32_t *bits, uint32_t nw, uint32_t *chunk_sums, 
     return hipGetLastError();
 }
 
-hipError_t launch_mark(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, uint32_t *bitmap, hipStream_t s) {
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_mark, dim3((n + 255) / 256), dim3(256), 0, s, new_slots, n, tval, bitmap);
+hipError_t launch_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                       uint32_t *bitmap, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark, dim3(grid), dim3(256), 0, s, new_slots, ctr, cap, tval, bitmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                                uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
+                                uint32_t level_base, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(1024), 0, s, new_slots, ctr, cap, tval, bitmap, nw, wordpre,
+                       recipe, level_base);
     return hipGetLastError();
 }
 
@@ -891,19 +1111,27 @@ hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const uint32_t *new_slots, uint32_t n, const uint32_t *tval, const uint32_t *bitmap,
-                          const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base, hipStream_t s) {
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, new_slots, n, tval, bitmap, wordpre,
-                       recipe, level_base);
+hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                          const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
+                          uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(256), 0, s, new_slots, ctr, cap, tval, bitmap, wordpre, recipe,
+                       level_base);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const uint32_t *new_slots, uint32_t n, uint32_t *tval, const uint32_t *bitmap,
-                           const uint32_t *wordpre, uint32_t level_base, hipStream_t s) {
+hipError_t launch_finalize(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
+                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t level_base,
+                           uint32_t *entry_slot, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, s, new_slots, ctr, cap, tval, bitmap, wordpre,
+                       level_base, entry_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_slots(const uint32_t *entry_slot, uint32_t n, unsigned long long *tkey, uint32_t *tval,
+                              hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, s, new_slots, n, tval, bitmap, wordpre,
-                       level_base);
+    const uint32_t g = std::min<uint32_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_clear_slots, dim3(g), dim3(256), 0, s, entry_slot, n, tkey, tval);
     return hipGetLastError();
 }
 

@@ -218,8 +218,15 @@ def from_traces(pos: Sequence[Sequence[int]], neg: Sequence[Sequence[int]], num_
 def planted_instance(seed: int, num_props: int, k: int, lo: int, hi: int, p: float,
                      size: int, max_draws: int = 10 ** 6, batch: int = 4096,
                      name: str = "") -> Instance:
-    """Planted-formula specification with k positive and k negative distinct traces."""
+    """Planted-formula specification with k positive and k negative distinct traces.
+
+    Traces are drawn in batches; a trace already drawn (in either class) is rejected.
+    The planted formula is redrawn from the next sub-seed as soon as the class that
+    fills slower cannot reach k within max_draws draws at its observed rate (checked
+    after every batch once 16 384 traces were drawn), or when max_draws is reached.
+    """
     attempt = 0
+    weights = (1 << np.arange(num_props, dtype=np.uint32))
     while True:
         rng = np.random.default_rng([seed, attempt])
         phi = draw_formula(rng, size, num_props)
@@ -227,14 +234,15 @@ def planted_instance(seed: int, num_props: int, k: int, lo: int, hi: int, p: flo
         neg: list = []
         seen = set()
         draws = 0
+        n_pos_seen = n_neg_seen = 0
+        feasible = True
         while (len(pos) < k or len(neg) < k) and draws < max_draws:
             nb = min(batch, max_draws - draws)
             lens = rng.integers(lo, hi + 1, size=nb)
-            bits = rng.random((nb, hi, num_props)) < p
+            bits = rng.random((nb, hi, num_props), dtype=np.float32) < np.float32(p)
             live = np.arange(hi)[None, :] < lens[:, None]
             bits &= live[:, :, None]
             lab = _label_positions(phi, bits, lens)[:, 0]
-            weights = (1 << np.arange(num_props, dtype=np.uint32))
             lets = (bits.astype(np.uint32) * weights[None, None, :]).sum(axis=2).astype(np.uint32)
             for i in range(nb):
                 draws += 1
@@ -249,7 +257,14 @@ def planted_instance(seed: int, num_props: int, k: int, lo: int, hi: int, p: flo
                 cls.append(tr.copy())
                 if len(pos) >= k and len(neg) >= k:
                     break
-        if len(pos) >= k and len(neg) >= k:
+            n_pos_seen += int(lab.sum())
+            n_neg_seen += int(nb - lab.sum())
+            if draws >= 16384:
+                rate = min(n_pos_seen, n_neg_seen) / draws
+                if rate * max_draws < k:
+                    feasible = False
+                    break
+        if feasible and len(pos) >= k and len(neg) >= k:
             break
         attempt += 1
     traces = pos + neg

@@ -221,3 +221,17 @@ def test_level_calls_out_of_order(ltl, ctx):
         job.eval_level(1)
     finally:
         job.close()
+
+
+def test_table_reuse_across_jobs_after_oom(ltl):
+    """A context hands its emptied hash table to the next job, also after an OOM stop."""
+    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=16, max_entries=30)
+    try:
+        inst0, _ = synth.preset_instance("tiny", 0)
+        g0 = c.learn(inst0, 7)
+        assert g0.status == ltl.LTL_E_OOM
+        for seed in (1, 2, 3, 4):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            _same(c.learn(inst, 7), O.learn(inst, 7, max_entries=30), f"reuse/{seed}")
+    finally:
+        c.close()
