@@ -23,6 +23,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, 8 TB/s
+KERNEL_SRC = os.path.join(ROOT, "paper_2402_12373_amd", "csrc", "ltl_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_scale.json")
+
+
+def measured_traffic(kind: str):
+    """Calibrated HBM bytes per launch of a kernel kind, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary -- only if the kernel source is unchanged since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != src:
+        return None
+    k = rec.get("per_launch_bytes", {}).get(kind)
+    return None if k is None else float(k)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T
 
 
@@ -50,6 +67,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long"])
     ap.add_argument("--seeds", default="0-7")
+    ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
     ap.add_argument("--ucarry", action="store_true", help="U by carry-chain add instead of doubling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -70,7 +88,9 @@ def main():
     from paper_2402_12373_amd import ltl, synth
 
     seeds = parse_seeds(args.seeds)
-    cfg = synth.PRESETS[args.workload]
+    cfg = dict(synth.PRESETS[args.workload])
+    if args.bound:
+        cfg["bound"] = args.bound
     insts = [synth.preset_instance(args.workload, s)[0] for s in seeds]
     dev = [ltl.spec_to_device(i) for i in insts]            # inputs resident in HBM
 
@@ -166,6 +186,9 @@ def main():
         roof = {"bound": "alu", "kernel": "k_level<eval>", "achieved": round(eval_tops, 3),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
                 "frac": round(eval_tops / VALU_PEAK_TOPS, 4), "traffic": None}
+    t = measured_traffic(dominant)
+    roof["traffic"] = None if t is None else round(t / 1e6, 3)
+    roof["traffic_unit"] = "MB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
     roof["avg_launch_ms"] = round(kern_ms[dominant] / max(1, kern_n[dominant]), 4)
     roof["launches"] = kern_n[dominant]
 

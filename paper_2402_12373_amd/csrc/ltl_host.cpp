@@ -157,8 +157,9 @@ struct Timer {
     ltl_job *j;
     TimedLaunch t{};
     bool on = false;
-    Timer(ltl_job *job, int kind) : j(job) {
-        j->kernel_launches[kind]++;
+    // counts `dispatches` kernel launches for the kind (rocprofv3 counts dispatches too)
+    Timer(ltl_job *job, int kind, uint32_t dispatches = 1) : j(job) {
+        j->kernel_launches[kind] += dispatches;
         if (!j->timing) return;
         t.kind = kind;
         t.e0 = pool_event(j);
@@ -404,7 +405,7 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     }
     HIP_TRY(hipMemsetAsync(j->ctr, 0, sizeof(Counters), j->s));
     {
-        Timer tm(j, LTL_K_INTAKE);
+        Timer tm(j, LTL_K_INTAKE, c->table_clean_log2 != sl ? 3u : 2u);
         if (c->table_clean_log2 != sl) HIP_TRY(launch_table_init(j->tkey, j->tval, nslots, j->s));
         c->table_clean_log2 = 0;   // dirty until the job empties its slots again
         if (wb == 64)
@@ -661,14 +662,34 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     std::vector<Block> &grouped = j->grouped;
     grouped.clear();
     uint32_t cls_first[5] = {0}, cls_tiles[4] = {0};
+    // F, G, X and NOT over the same child level are evaluated as one fused block
+    int fuse_idx[4] = {-1, -1, -1, -1};
+    {
+        const uint32_t fops[4] = {LTL_F, LTL_G, LTL_X, LTL_NOT};
+        for (size_t bi = 0; bi < lv.blocks.size(); ++bi)
+            for (int q = 0; q < 4; ++q)
+                if (lv.blocks[bi].op == fops[q]) fuse_idx[q] = (int)bi;
+        for (int q = 0; q < 4; ++q)
+            if (fuse_idx[q] < 0 || lv.blocks[fuse_idx[q]].a_ptr != lv.blocks[fuse_idx[0] < 0 ? 0 : fuse_idx[0]].a_ptr)
+                fuse_idx[0] = -1;
+    }
+    const bool fuse = fuse_idx[0] >= 0;
     for (int k = 0; k < 4; ++k) {
         cls_first[k] = (uint32_t)grouped.size();
         uint32_t tb = 0;
-        for (const Block &b : lv.blocks) {
+        for (size_t bi = 0; bi < lv.blocks.size(); ++bi) {
+            const Block &b = lv.blocks[bi];
             if (cls_of(b.op) != k) continue;
+            if (fuse && (int)bi == fuse_idx[1]) continue;      // folded into the fused block
+            if (fuse && (int)bi == fuse_idx[2]) continue;
+            if (fuse && (int)bi == fuse_idx[3]) continue;
             Block g = b;
+            if (fuse && (int)bi == fuse_idx[0]) {
+                g.op = OP_FUSED4;
+                for (int q = 0; q < 4; ++q) g.fcb[q] = lv.blocks[fuse_idx[q]].cand_base;
+            }
             g.tile_base = tb;
-            tb += b.ntile;
+            tb += g.ntile;
             grouped.push_back(g);
         }
         cls_tiles[k] = tb;
@@ -734,12 +755,14 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     const uint64_t mat_items = (uint64_t)new_cap * ((j->NB + A.mat_chunk - 1) / A.mat_chunk);
     const uint32_t grid_mat = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((mat_items + 3) / 4, MAX_GRID));
     j->table_consistent = false;
+    uint32_t ncls = 0;
+    for (int k = 0; k < 4; ++k) ncls += cls_tiles[k] ? 1u : 0u;
     {
-        Timer tm(j, LTL_K_EVAL);
+        Timer tm(j, LTL_K_EVAL, ncls + (split ? 1u : 0u));
         HIP_TRY(launch_level(false));
     }
     {
-        Timer tm(j, LTL_K_COMPACT);
+        Timer tm(j, LTL_K_COMPACT, nw <= SMALL_COMPACT_WORDS ? 1u : 5u);
         if (nw <= SMALL_COMPACT_WORDS) {
             HIP_TRY(launch_compact_small(new_slots, j->ctr, arena_cap, j->tval, bitmap, nw, wordpre, j->recipe,
                                          lv.gid_base, j->s));
@@ -755,7 +778,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
     }
     {
-        Timer tm(j, LTL_K_VERIFY);
+        Timer tm(j, LTL_K_VERIFY, ncls);
         HIP_TRY(launch_level(true));
     }
     Counters hc;
@@ -775,7 +798,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         if (hc.overflow || hc.n_new > arena_cap) return LTL_E_OOM;
         n_new = hc.n_new;
         {
-            Timer tm(j, LTL_K_COMPACT);
+            Timer tm(j, LTL_K_COMPACT, 6);
             HIP_TRY(launch_or_bits(bitmap, fb_bits, nw, j->s));
             HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
             HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,

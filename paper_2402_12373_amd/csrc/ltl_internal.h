@@ -29,7 +29,12 @@ struct Block {
     uint32_t a_gid, b_gid;   // global entry id of the first a / b entry (ATOM: prop 0)
     uint64_t a_ptr;       // device address of the first a matrix
     uint64_t b_ptr;       // device address of the first b matrix (0 for unary)
+    uint32_t fcb[4];      // OP_FUSED4 blocks: canonical base of F, G, X, NOT over the same children
 };
+
+// Evaluation-only block: F, G, X and NOT over the same child level in one tile
+// (each child is read once for its four candidates).
+constexpr uint32_t OP_FUSED4 = 16;
 
 struct Counters {
     unsigned long long first_sol;   // smallest separating canonical index (atomicMin)
@@ -104,7 +109,7 @@ hipError_t launch_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t 
                        uint32_t *bitmap, uint32_t grid, hipStream_t s);
 hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipStream_t s);
 // mark + scan + scatter in one workgroup, for levels with at most SMALL_COMPACT_WORDS bitmap words
-constexpr uint32_t SMALL_COMPACT_WORDS = 8192;
+constexpr uint32_t SMALL_COMPACT_WORDS = 512;
 hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
                                 uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
                                 uint32_t level_base, hipStream_t s);

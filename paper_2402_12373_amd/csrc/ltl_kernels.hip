@@ -349,11 +349,21 @@ __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx
 // EVAL   : fingerprint + separation, probe/claim in the language cache.
 // VERIFY : recompute, compare in full with the presumed owner.
 // ---------------------------------------------------------------------------
+// F, G, X, NOT of one child, selected by a compile-time index (fused unary tiles)
+template <typename T, bool MW>
+__device__ __forceinline__ T apply_fused(int k, T a, const RowMeta<T> &m, const Rows<T> &rw, int lane) {
+    if (k == 0) return apply<T, MW, LTL_F>(a, (T)0, m, rw, lane);
+    if (k == 1) return apply<T, MW, LTL_G>(a, (T)0, m, rw, lane);
+    if (k == 2) return apply<T, MW, LTL_X>(a, (T)0, m, rw, lane);
+    return apply<T, MW, LTL_NOT>(a, (T)0, m, rw, lane);
+}
+
 template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY>
 __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane, uint32_t rb0,
                          uint32_t rb1) {
     constexpr int NP = TI * TJ;
     constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
+    constexpr bool FUSED = (OP == (int)OP_FUSED4);
     const uint32_t R = A.rows.R;
     const uint32_t nbj = b.tri ? b.na : b.nb;
     // child matrices of the tile (clamped; results of out-of-range pairs are dropped)
@@ -375,7 +385,8 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
             const uint32_t i = i0 + ii, j = j0 + jj;
             bool v = i < b.na;
             if constexpr (BIN) v = v && (b.tri ? (j < b.na && j > i) : (j < b.nb));
-            idx[ii * TJ + jj] = uniform(v ? cand_index(b, i, j) : 0xFFFFFFFFu);
+            if constexpr (FUSED) idx[ii * TJ + jj] = uniform(v ? b.fcb[jj] + i : 0xFFFFFFFFu);
+            else idx[ii * TJ + jj] = uniform(v ? cand_index(b, i, j) : 0xFFFFFFFFu);
         }
 
     // one row block of operands (and, for VERIFY, of the owners), loaded one block ahead
@@ -431,7 +442,9 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
 #pragma unroll
                 for (int jj = 0; jj < TJ; ++jj) {
                     const int p = ii * TJ + jj;
-                    const T w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
+                    T w;
+                    if constexpr (FUSED) w = apply_fused<T, MW>(jj, cur.av[ii], cur.m, A.rows, lane);
+                    else w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
                     viol[p] |= (w ^ cur.m.sw) & cur.m.sm;
                     fp_add<T>(acc[p], w, cur.m);
                 }
@@ -470,7 +483,9 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
                 for (int jj = 0; jj < TJ; ++jj) {
                     const int p = ii * TJ + jj;
                     if (tgt[p] != 0xFFFFFFFFu) {
-                        const T w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
+                        T w;
+                        if constexpr (FUSED) w = apply_fused<T, MW>(jj, cur.av[ii], cur.m, A.rows, lane);
+                        else w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
                         diff[p] |= w ^ cur.tv[p];
                     }
                 }
@@ -530,7 +545,8 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs<T> A, const Block *bloc
             case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
             case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
             case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-            default:       run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+            default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
             }
         } else if constexpr (CLS == CLS_ANDOR) {
             if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);

@@ -1,0 +1,69 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times.
+
+* scale workload (3 props, 1024+1024 traces, len 16..32, bound 11, 2^26 hash
+  slots), the eight benchmark seeds: status, minimal cost, every level's counts
+  and the first solution equal the oracle's (the oracle runs every level);
+* long workload (5 props, 4096+4096 traces, len 64..512, multi-word 64-bit rows):
+  levels 1..4 complete (counts, every entry's formula, sampled matrices).
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2402_12373_amd import synth
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def ltl():
+    from paper_2402_12373_amd import ltl as L
+    return L
+
+
+@pytest.fixture(scope="module")
+def big_ctx(ltl):
+    c = ltl.Context(workspace_bytes=24 << 30, hash_slots_log2=26)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_scale_workload_full_parity(ltl, big_ctx, seed):
+    inst, cfg = synth.preset_instance("scale", seed)
+    print("scale seed", seed, flush=True)
+    g = big_ctx.learn(ltl.spec_to_device(inst), cfg["bound"])
+    o = O.learn(inst, cfg["bound"], mode=O.MODE_EXPAND, threads=THREADS)
+    assert (g.status, g.levels_done) == (o.status, o.levels_done)
+    assert g.level_new == o.level_new[:o.levels_done + 1]
+    assert g.level_candidates == o.level_candidates[:o.levels_done + 1]
+    if o.status == O.ST_OK:
+        assert g.cost == o.cost and g.solution_index == o.first_index and g.solution == o.solution
+        assert g.cost <= cfg["size"]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_long_workload_levels(ltl, big_ctx, seed):
+    inst, cfg = synth.preset_instance("long", seed)
+    print("long seed", seed, flush=True)
+    run = O.Run(O.Spec.of(inst), 4, mode=O.MODE_EXPAND, threads=THREADS)
+    ora = run.result()
+    job = big_ctx.job(ltl.spec_to_device(inst), cfg["bound"])
+    try:
+        info = job.info()
+        assert info.word_bits == 64
+        for c in range(1, 5):
+            st = job.eval_level(c)
+            assert st.candidates == ora.level_candidates[c] and st.new_entries == ora.level_new[c], c
+            n = ora.level_new[c]
+            for e in range(n):
+                assert job.formula(c, e) == run.entry_formula(c, e), (c, e)
+            for e in sorted(set([0, n - 1] + list(range(0, n, max(1, n // 12))))):
+                np.testing.assert_array_equal(job.dump_cm(c, e), run.entry_cm(c, e), err_msg=f"{c}/{e}")
+    finally:
+        job.close()
