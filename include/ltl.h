@@ -160,6 +160,40 @@ typedef struct {
 int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
               ltl_result *out);
 
+/* ---------------------------------------------------------------- batched learning */
+
+/* Many independent learning jobs of uneven sizes, run `lanes` at a time.  Each
+ * lane has its own HIP stream, its own slice of the workspace (workspace_bytes /
+ * lanes, 256-byte aligned) and its own context, so the levels of different jobs
+ * overlap on the device; every job's result equals that of ltl_learn on a
+ * context with the same options and a workspace of the slice's size. */
+typedef struct {
+    int32_t  device;
+    uint32_t flags;              /* LTL_CTX_* for every job                                  */
+    void    *workspace;          /* device pointer, caller-owned, split evenly among lanes   */
+    uint64_t workspace_bytes;
+    uint32_t lanes;              /* jobs in flight at once, 1..64                            */
+    uint32_t hash_slots_log2;    /* per lane; 0 = automatic                                  */
+    uint32_t word_bits;          /* as in ltl_ctx_opts                                       */
+    uint32_t fp_bits;
+    uint64_t max_entries;        /* per job; 0 = derived from the lane's hash table          */
+} ltl_batch_opts;
+
+typedef struct {
+    ltl_spec  spec;              /* host or device buffers (LTL_SPEC_DEVICE)                 */
+    ltl_opset ops;
+    uint32_t  cost_bound;
+    uint32_t  reserved;
+} ltl_batch_job;
+
+/* Runs jobs[0..njobs-1] (taken in order by free lanes).  results[i] receives job
+ * i's result; if job_ms is not NULL, job_ms[2*i] is its duration and
+ * job_ms[2*i+1] its completion time since the call began (milliseconds, host
+ * clock).  Returns LTL_OK if every job ran (each job's own status is in its
+ * result), LTL_E_INVAL for bad options, LTL_E_DEVICE if a lane could not start. */
+int ltl_learn_batch(const ltl_batch_opts *opts, const ltl_batch_job *jobs, uint32_t njobs, ltl_result *results,
+                    double *job_ms);
+
 /* ---------------------------------------------------------------- level-by-level interface */
 
 /* Validate and pack the specification (atom matrices, row layout) into the

@@ -11,12 +11,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <unordered_map>
+#include <thread>
 #include <vector>
 
 #include "ltl.h"
@@ -34,8 +37,11 @@ constexpr uint32_t MAX_GRID = 8192;
 constexpr uint64_t TARGET_WAVES = 8192;
 constexpr uint64_t MIN_CHUNK = 4;        // row blocks per work item at least (per-item fixed cost)
 // pinned staging: [blocks canonical | blocks by class | counters in | counters out]
-constexpr uint64_t PINNED_BLOCKS = sizeof(Block) * MAX_BLOCKS;
-constexpr uint64_t PINNED_BYTES = 2 * PINNED_BLOCKS + 2 * 256;
+// per-level upload, one copy: [counters init (256 B) | canonical blocks | blocks by class]
+// [counters init | canonical blocks | blocks by class | all blocks, one tile numbering]
+constexpr uint64_t UPLOAD_BYTES = 256 + 3 * sizeof(Block) * MAX_BLOCKS;
+// pinned staging: the upload image, then 256 B for the counters read back
+constexpr uint64_t PINNED_BYTES = UPLOAD_BYTES + 256;
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -194,7 +200,7 @@ static double collect_times(ltl_job *j) {
 }
 
 static int sync_read_counters(ltl_job *j, Counters *host) {
-    Counters *pin = (Counters *)(j->ctx->pinned + 2 * PINNED_BLOCKS + 256);
+    Counters *pin = (Counters *)(j->ctx->pinned + UPLOAD_BYTES);
     HIP_TRY(hipMemcpyAsync(pin, j->ctr, sizeof(Counters), hipMemcpyDeviceToHost, j->s));
     HIP_TRY(hipStreamSynchronize(j->s));
     *host = *pin;
@@ -358,7 +364,8 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     j->entry_slot = (uint32_t *)ws_take(j, nslots * 4);
     if (!j->tkey || !j->tval || !j->recipe || !j->entry_slot) return LTL_E_OOM;
 
-    j->ctr = (Counters *)ws_take(j, sizeof(Counters));
+    char *upload = (char *)ws_take(j, UPLOAD_BYTES);   // counters, then the level's block tables
+    j->ctr = (Counters *)upload;
     j->valid = ws_take(j, R * j->wbytes);
     j->sepm = ws_take(j, R * j->wbytes);
     j->sepw = ws_take(j, R * j->wbytes);
@@ -368,8 +375,8 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     j->row_word = (uint32_t *)ws_take(j, R * 4);
     j->atoms = ws_take(j, (uint64_t)j->A * R * j->wbytes);
     j->tfp = (uint64_t *)ws_take(j, (uint64_t)T * 8);
-    j->blocks_d = (Block *)ws_take(j, sizeof(Block) * MAX_BLOCKS);
-    j->blocks_cls_d = (Block *)ws_take(j, sizeof(Block) * MAX_BLOCKS);
+    j->blocks_d = upload ? (Block *)(upload + 256) : nullptr;
+    j->blocks_cls_d = j->blocks_d;   // placed after the canonical blocks of each level
     if (!(spec->flags & LTL_SPEC_DEVICE)) {
         j->letters_d = (uint32_t *)ws_take(j, j->TB * 4);
         j->offsets_d = (uint64_t *)ws_take(j, ((uint64_t)T + 1) * 8);
@@ -636,10 +643,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
     uint32_t *new_slots = (uint32_t *)take_top((uint64_t)new_cap * 4);
+    uint32_t *new_owner = (uint32_t *)take_top((uint64_t)new_cap * 4);
     T *stage = (T *)take_top((uint64_t)j->R * sizeof(T));
     const uint64_t arena_off = (uint64_t)(j->arena - j->ws);
     const uint64_t arena_used = j->total_entries * j->cm_bytes;
-    if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !stage || arena_off + arena_used > top)
+    if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !new_owner || !stage ||
+        arena_off + arena_used > top)
         return LTL_E_OOM;
     uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
     unsigned long long *cand_fp = (unsigned long long *)(bits3 + 4 * nwa);
@@ -647,11 +656,10 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     const uint32_t arena_cap = (uint32_t)std::min<uint64_t>(
         {arena_free / j->cm_bytes, j->recipe_cap - j->total_entries, (uint64_t)new_cap});
 
-    Block *pin_blocks = (Block *)j->ctx->pinned;
-    Block *pin_grouped = (Block *)(j->ctx->pinned + PINNED_BLOCKS);
-    Counters *pin_ctr = (Counters *)(j->ctx->pinned + 2 * PINNED_BLOCKS);
+    Counters *pin_ctr = (Counters *)j->ctx->pinned;
+    Block *pin_blocks = (Block *)(j->ctx->pinned + 256);
+    Block *pin_grouped = pin_blocks + lv.blocks.size();
     memcpy(pin_blocks, lv.blocks.data(), sizeof(Block) * lv.blocks.size());
-    HIP_TRY(hipMemcpyAsync(j->blocks_d, pin_blocks, sizeof(Block) * lv.blocks.size(), hipMemcpyHostToDevice, j->s));
     // the same blocks grouped by connective class, each class with its own tile numbering
     const bool ucarry = (j->ctx->o.flags & LTL_CTX_U_CARRY) != 0;
     auto cls_of = [&](uint32_t op) {
@@ -696,10 +704,24 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     cls_first[4] = (uint32_t)grouped.size();
     memcpy(pin_grouped, grouped.data(), sizeof(Block) * grouped.size());
-    HIP_TRY(hipMemcpyAsync(j->blocks_cls_d, pin_grouped, sizeof(Block) * grouped.size(), hipMemcpyHostToDevice, j->s));
+    // small levels evaluate every class in one dispatch: one tile numbering over the grouped blocks
+    const bool merged_eval = split && !j->mw;
+    Block *pin_all = pin_grouped + grouped.size();
+    uint32_t all_tiles = 0;
+    if (merged_eval) {
+        for (size_t k = 0; k < grouped.size(); ++k) {
+            pin_all[k] = grouped[k];
+            pin_all[k].tile_base = all_tiles;
+            all_tiles += grouped[k].ntile;
+        }
+    }
     *pin_ctr = Counters{};
     pin_ctr->first_sol = ~0ull;
-    HIP_TRY(hipMemcpyAsync(j->ctr, pin_ctr, sizeof(Counters), hipMemcpyHostToDevice, j->s));
+    Block *grouped_d = j->blocks_d + lv.blocks.size();
+    Block *all_d = grouped_d + grouped.size();
+    HIP_TRY(hipMemcpyAsync(j->ctr, j->ctx->pinned,
+                           256 + sizeof(Block) * (lv.blocks.size() + grouped.size() * (merged_eval ? 2 : 1)),
+                           hipMemcpyHostToDevice, j->s));
     HIP_TRY(hipMemsetAsync(bits3, 0, clear_bytes, j->s));
 
     LevelArgs<T> A{};
@@ -714,6 +736,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.ctr = j->ctr;
     A.cand_slot = cand_slot;
     A.new_slots = new_slots;
+    A.new_owner = new_owner;
     A.new_cap = new_cap;
     A.bitmap = bitmap;
     A.wordpre = wordpre;
@@ -734,6 +757,17 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         A.mat_chunk = (uint32_t)((j->NB + per - 1) / per);
     }
     auto launch_level = [&](bool verify) -> hipError_t {
+        if (!verify && merged_eval) {
+            const uint64_t per = std::max<uint64_t>(
+                1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max(1u, all_tiles)));
+            const uint32_t chunk = (uint32_t)((j->NB + per - 1) / per);
+            const uint64_t nchunk = (j->NB + chunk - 1) / chunk;
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)all_tiles * nchunk + 3) / 4, MAX_GRID);
+            hipError_t e = Launch<T>::level_all(A, j->mw, false, all_d, (uint32_t)grouped.size(), all_tiles, chunk,
+                                                grid, j->s);
+            if (e != hipSuccess) return e;
+            return Launch<T>::probe(A, nc, j->s);
+        }
         for (int k = 0; k < 4; ++k) {
             if (!cls_tiles[k]) continue;
             uint64_t per = 1;          // row chunks per tile
@@ -743,7 +777,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             const uint32_t chunk = (uint32_t)((j->NB + per - 1) / per);
             const uint64_t nchunk = (j->NB + chunk - 1) / chunk;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] * nchunk + 3) / 4, MAX_GRID);
-            hipError_t e = Launch<T>::level(A, j->mw, verify, k, j->blocks_cls_d + cls_first[k],
+            hipError_t e = Launch<T>::level(A, j->mw, verify, k, grouped_d + cls_first[k],
                                             cls_first[k + 1] - cls_first[k], cls_tiles[k], chunk, grid, j->s);
             if (e != hipSuccess) return e;
         }
@@ -758,19 +792,19 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t ncls = 0;
     for (int k = 0; k < 4; ++k) ncls += cls_tiles[k] ? 1u : 0u;
     {
-        Timer tm(j, LTL_K_EVAL, ncls + (split ? 1u : 0u));
+        Timer tm(j, LTL_K_EVAL, merged_eval ? 2u : ncls + (split ? 1u : 0u));
         HIP_TRY(launch_level(false));
     }
     {
         Timer tm(j, LTL_K_COMPACT, nw <= SMALL_COMPACT_WORDS ? 1u : 5u);
         if (nw <= SMALL_COMPACT_WORDS) {
             HIP_TRY(launch_compact_small(new_slots, j->ctr, arena_cap, j->tval, bitmap, nw, wordpre, j->recipe,
-                                         lv.gid_base, j->s));
+                                         lv.gid_base, j->entry_slot, new_owner, j->s));
         } else {
             HIP_TRY(launch_mark(new_slots, j->ctr, arena_cap, j->tval, bitmap, grid_new, j->s));
             HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
             HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
-                                   grid_new, j->s));
+                                   j->entry_slot, new_owner, false, grid_new, j->s));
         }
     }
     {
@@ -798,21 +832,16 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         if (hc.overflow || hc.n_new > arena_cap) return LTL_E_OOM;
         n_new = hc.n_new;
         {
-            Timer tm(j, LTL_K_COMPACT, 6);
+            Timer tm(j, LTL_K_COMPACT, 5);
             HIP_TRY(launch_or_bits(bitmap, fb_bits, nw, j->s));
             HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
             HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
-                                   grid_new, j->s));
+                                   j->entry_slot, new_owner, true, grid_new, j->s));
         }
         {
             Timer tm(j, LTL_K_MATERIALIZE);
             HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
         }
-    }
-    {
-        Timer tm(j, LTL_K_COMPACT);
-        HIP_TRY(launch_finalize(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, lv.gid_base, j->entry_slot,
-                                grid_new, j->s));
     }
     j->table_consistent = true;
     lv.n = n_new;
@@ -1026,5 +1055,62 @@ extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *op
     }
     st = ltl_job_result(j, out);
     ltl_job_destroy(j);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// Batched learning: lanes of (stream, workspace slice, context), jobs taken in order
+// ---------------------------------------------------------------------------
+extern "C" int ltl_learn_batch(const ltl_batch_opts *o, const ltl_batch_job *jobs, uint32_t njobs,
+                               ltl_result *results, double *job_ms) {
+    if (!o || (!jobs && njobs) || (!results && njobs) || !o->workspace) return LTL_E_INVAL;
+    if (o->lanes < 1 || o->lanes > 64) return LTL_E_INVAL;
+    const uint64_t slice = (o->workspace_bytes / o->lanes) & ~255ull;
+    if (slice < LTL_MIN_WORKSPACE) return LTL_E_INVAL;
+    if (hipSetDevice(o->device) != hipSuccess) return LTL_E_DEVICE;
+    const uint32_t lanes = std::min<uint32_t>(o->lanes, std::max<uint32_t>(njobs, 1u));
+    std::vector<hipStream_t> streams(lanes, nullptr);
+    std::vector<ltl_ctx *> ctxs(lanes, nullptr);
+    int st = LTL_OK;
+    for (uint32_t l = 0; l < lanes && st == LTL_OK; ++l) {
+        if (hipStreamCreateWithFlags(&streams[l], hipStreamNonBlocking) != hipSuccess) { st = LTL_E_DEVICE; break; }
+        ltl_ctx_opts co{};
+        co.device = o->device;
+        co.flags = o->flags;
+        co.workspace = (char *)o->workspace + (uint64_t)l * slice;
+        co.workspace_bytes = slice;
+        co.stream = streams[l];
+        co.hash_slots_log2 = o->hash_slots_log2;
+        co.word_bits = o->word_bits;
+        co.fp_bits = o->fp_bits;
+        co.max_entries = o->max_entries;
+        st = ltl_ctx_create(&co, &ctxs[l]);
+    }
+    if (st == LTL_OK) {
+        std::atomic<uint32_t> next{0};
+        const auto t0 = std::chrono::steady_clock::now();
+        auto worker = [&](uint32_t l) {
+            (void)hipSetDevice(o->device);
+            for (;;) {
+                const uint32_t i = next.fetch_add(1);
+                if (i >= njobs) break;
+                const auto a = std::chrono::steady_clock::now();
+                ltl_learn(ctxs[l], &jobs[i].spec, &jobs[i].ops, jobs[i].cost_bound, &results[i]);
+                const auto b = std::chrono::steady_clock::now();
+                if (job_ms) {
+                    job_ms[2 * (size_t)i] = std::chrono::duration<double, std::milli>(b - a).count();
+                    job_ms[2 * (size_t)i + 1] = std::chrono::duration<double, std::milli>(b - t0).count();
+                }
+            }
+        };
+        std::vector<std::thread> th;
+        for (uint32_t l = 1; l < lanes; ++l) th.emplace_back(worker, l);
+        worker(0);
+        for (auto &t : th) t.join();
+    }
+    for (uint32_t l = 0; l < lanes; ++l) {
+        if (ctxs[l]) ltl_ctx_destroy(ctxs[l]);
+        if (streams[l]) (void)hipStreamDestroy(streams[l]);
+    }
     return st;
 }

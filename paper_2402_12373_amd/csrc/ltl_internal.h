@@ -70,6 +70,7 @@ struct LevelArgs {
     Counters *ctr;
     uint32_t *cand_slot;     // per candidate: its hash slot (or NO_SLOT)
     uint32_t *new_slots;     // slots claimed this level
+    uint32_t *new_owner;     // owner (canonical index) of each claimed slot, recorded at settlement
     uint32_t new_cap;
     uint32_t *bitmap;        // per candidate: group representative bit
     uint32_t *wordpre;       // exclusive prefix of popcounts of bitmap words
@@ -97,6 +98,9 @@ struct Launch {
     static hipError_t level(const LevelArgs<T> &A, bool mw, bool verify, int cls, const Block *blocks,
                             uint32_t nblocks, uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
     static hipError_t probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
+    // every connective class in one dispatch (small row-split levels)
+    static hipError_t level_all(const LevelArgs<T> &A, bool mw, bool verify, const Block *blocks, uint32_t nblocks,
+                                uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
     static hipError_t materialize(const LevelArgs<T> &A, bool mw, uint32_t n, uint32_t grid, hipStream_t s);
     static hipError_t fallback(const LevelArgs<T> &A, bool mw, uint32_t nwords, uint32_t ncand, hipStream_t s);
     static hipError_t pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
@@ -110,15 +114,13 @@ hipError_t launch_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t 
 hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipStream_t s);
 // mark + scan + scatter in one workgroup, for levels with at most SMALL_COMPACT_WORDS bitmap words
 constexpr uint32_t SMALL_COMPACT_WORDS = 512;
-hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                                 uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
-                                uint32_t level_base, hipStream_t s);
-hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+                                uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner, hipStream_t s);
+// recipes + slot settlement (+ entry -> slot); repass re-reads the recorded owners
+hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
-                          uint32_t grid, hipStream_t s);
-hipError_t launch_finalize(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
-                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t level_base,
-                           uint32_t *entry_slot, uint32_t grid, hipStream_t s);
+                          uint32_t *entry_slot, uint32_t *new_owner, bool repass, uint32_t grid, hipStream_t s);
 hipError_t launch_clear_slots(const uint32_t *entry_slot, uint32_t n, unsigned long long *tkey, uint32_t *tval,
                               hipStream_t s);
 hipError_t launch_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t nslots, hipStream_t s);

@@ -405,8 +405,13 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
                 const uint32_t h = uniform(A.cand_slot[idx[p]]);
                 if (h != NO_SLOT) {
                     const uint32_t v = uniform(A.tval[h]);
-                    if (v & VAL_SETTLED) g = v & ~VAL_SETTLED;
-                    else if (v != idx[p]) g = A.level_base + uniform(rank_of(A.bitmap, A.wordpre, v));
+                    if (v & VAL_SETTLED) {
+                        g = v & ~VAL_SETTLED;
+                        // a representative of this level is not compared with itself
+                        if (g >= A.level_base && uniform(A.recipe[g]) == idx[p]) g = 0xFFFFFFFFu;
+                    } else if (v != idx[p]) {
+                        g = A.level_base + uniform(rank_of(A.bitmap, A.wordpre, v));
+                    }
                 }
             }
             tgt[p] = g;
@@ -445,7 +450,10 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
                     T w;
                     if constexpr (FUSED) w = apply_fused<T, MW>(jj, cur.av[ii], cur.m, A.rows, lane);
                     else w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
-                    viol[p] |= (w ^ cur.m.sw) & cur.m.sm;
+                    // one word per trace (32-bit layout): every live row is a first word and dead
+                    // rows are zero, so the position-0 bit is masked once, after the loop
+                    if constexpr (!MW && sizeof(T) == 4) viol[p] |= w ^ cur.m.sw;
+                    else viol[p] |= (w ^ cur.m.sw) & cur.m.sm;
                     fp_add<T>(acc[p], w, cur.m);
                 }
             cur = nxt;
@@ -456,6 +464,7 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const uint64_t sum = wave_sum(acc[p]);
+            if constexpr (!MW && sizeof(T) == 4) viol[p] &= (T)0x80000000u;
             const bool bad = __ballot(viol[p] != 0) != 0ull;
             if (lane == p) { my_fp = sum; my_idx = idx[p]; my_bad = bad; }
         }
@@ -555,6 +564,47 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs<T> A, const Block *bloc
             run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
         } else {
             run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+        }
+    }
+}
+
+// All connective classes in one dispatch (row-split small levels, where the
+// number of dispatches, not occupancy, bounds the level): blocks of every
+// class, one tile numbering, one chunk size.
+template <typename T, bool MW, bool VERIFY>
+__global__ __launch_bounds__(256) void k_level_all(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
+                                                   uint32_t ntiles, uint32_t chunk) {
+    const int lane = (int)__lane_id();
+    if constexpr (VERIFY) {
+        if (uniform(A.ctr->overflow) || uniform(A.ctr->n_new) > A.arena_cap) return;
+    }
+    const uint32_t NB = A.rows.NB;
+    const uint32_t nchunk = (NB + chunk - 1) / chunk;
+    const uint32_t nwork = ntiles * nchunk;
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t w = wave; w < nwork; w += nwaves) {
+        const uint32_t t = w / nchunk, q = w - t * nchunk;
+        const uint32_t rb0 = q * chunk, rb1 = min(NB, rb0 + chunk);
+        const int bi = (int)uniform((uint32_t)find_block_tile(blocks, (int)nblocks, t));
+        const Block b = uniform_block(blocks[bi]);
+        uint32_t i0, j0;
+        decode_tile(b, t - b.tile_base, i0, j0);
+        i0 = uniform(i0);
+        j0 = uniform(j0);
+        switch (b.op) {
+        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_U:
+            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+            else run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+            break;
+        default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
         }
     }
 }
@@ -782,8 +832,12 @@ __global__ __launch_bounds__(256) void k_fallback(LevelArgs<T> A, uint32_t nword
                         const uint32_t pos = A.ctr->n_new;
                         A.ctr->n_new = pos + 1;
                         A.ctr->n_fallback_new += 1;
-                        if (pos < A.new_cap) A.new_slots[pos] = h;
-                        else A.ctr->overflow = 1;
+                        if (pos < A.new_cap) {
+                            A.new_slots[pos] = h;
+                            A.new_owner[pos] = x;
+                        } else {
+                            A.ctr->overflow = 1;
+                        }
                     }
                     __syncthreads();
                     break;
@@ -892,14 +946,31 @@ __device__ __forceinline__ uint32_t level_new_count(const Counters *ctr, uint32_
     return (n <= cap && !ctr->overflow) ? n : 0u;
 }
 
+// representatives -> recipes (entry order = canonical order of the representative),
+// and settlement of the level's slots: owner index -> global entry id.  The owner
+// of each new slot is recorded (new_owner) for a re-pass after the exact fallback.
+__device__ __forceinline__ void settle_slot(uint32_t i, const uint32_t *new_slots, uint32_t *tval,
+                                            const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe,
+                                            uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner,
+                                            bool repass) {
+    const uint32_t s = new_slots[i];
+    const uint32_t x = repass ? new_owner[i] : tval[s];
+    if (!repass) new_owner[i] = x;
+    const uint32_t g = level_base + rank_of(bitmap, wordpre, x);
+    recipe[g] = x;
+    entry_slot[g] = s;
+    tval[s] = VAL_SETTLED | g;
+}
+
 // Small levels (at most SMALL_WORDS bitmap words): representative bits, their
 // ordered prefix and the recipes in one workgroup of 1024 threads.
 constexpr uint32_t SMALL_WPT = 8;
 constexpr uint32_t SMALL_WORDS = 1024 * SMALL_WPT;
 
 __global__ __launch_bounds__(1024) void k_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap,
-                                                        const uint32_t *tval, uint32_t *bitmap, uint32_t nw,
-                                                        uint32_t *wordpre, uint32_t *recipe, uint32_t level_base) {
+                                                        uint32_t *tval, uint32_t *bitmap, uint32_t nw,
+                                                        uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
+                                                        uint32_t *entry_slot, uint32_t *new_owner) {
     __shared__ uint32_t s_tmp[16];
     const uint32_t n = level_new_count(ctr, cap);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -924,10 +995,8 @@ __global__ __launch_bounds__(1024) void k_compact_small(const uint32_t *new_slot
         run += c[k];
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t x = tval[new_slots[i]];
-        recipe[level_base + rank_of(bitmap, wordpre, x)] = x;
-    }
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        settle_slot(i, new_slots, tval, bitmap, wordpre, recipe, level_base, entry_slot, new_owner, false);
 }
 
 // slot owners -> representative bits
@@ -945,27 +1014,12 @@ __global__ void k_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw) {
     if (i < nw) dst[i] |= src[i];
 }
 
-// representatives -> recipes (entry order = canonical order of the representative)
-__global__ void k_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
-                          const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base) {
+__global__ void k_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
+                          const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
+                          uint32_t *entry_slot, uint32_t *new_owner, uint32_t repass) {
     const uint32_t n = level_new_count(ctr, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t x = tval[new_slots[i]];
-        recipe[level_base + rank_of(bitmap, wordpre, x)] = x;
-    }
-}
-
-// settle the level's slots: owner index -> global entry id; remember each entry's slot
-__global__ void k_finalize(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
-                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t level_base,
-                           uint32_t *entry_slot) {
-    const uint32_t n = level_new_count(ctr, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t s = new_slots[i];
-        const uint32_t g = level_base + rank_of(bitmap, wordpre, tval[s]);
-        tval[s] = VAL_SETTLED | g;
-        entry_slot[g] = s;
-    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        settle_slot(i, new_slots, tval, bitmap, wordpre, recipe, level_base, entry_slot, new_owner, repass != 0);
 }
 
 // return the slots of a finished job to the empty state
@@ -1056,6 +1110,21 @@ hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls
 }
 
 template <typename T>
+hipError_t Launch<T>::level_all(const LevelArgs<T> &A, bool mw, bool verify, const Block *blocks, uint32_t nblocks,
+                                uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            if (verify) hipLaunchKernelGGL((k_level_all<T, true, true>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
+            else hipLaunchKernelGGL((k_level_all<T, true, false>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
+            return hipGetLastError();
+        }
+    }
+    if (verify) hipLaunchKernelGGL((k_level_all<T, false, true>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
+    else hipLaunchKernelGGL((k_level_all<T, false, false>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t Launch<T>::probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((ncand + 255) / 256, 4096));
     hipLaunchKernelGGL((k_probe<T>), dim3(grid), dim3(256), 0, s, A, ncand);
@@ -1113,11 +1182,11 @@ hipError_t launch_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                                 uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
-                                uint32_t level_base, hipStream_t s) {
+                                uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner, hipStream_t s) {
     hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(1024), 0, s, new_slots, ctr, cap, tval, bitmap, nw, wordpre,
-                       recipe, level_base);
+                       recipe, level_base, entry_slot, new_owner);
     return hipGetLastError();
 }
 
@@ -1127,19 +1196,11 @@ hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, const uint32_t *tval,
+hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
-                          uint32_t grid, hipStream_t s) {
+                          uint32_t *entry_slot, uint32_t *new_owner, bool repass, uint32_t grid, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(256), 0, s, new_slots, ctr, cap, tval, bitmap, wordpre, recipe,
-                       level_base);
-    return hipGetLastError();
-}
-
-hipError_t launch_finalize(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
-                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t level_base,
-                           uint32_t *entry_slot, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, s, new_slots, ctr, cap, tval, bitmap, wordpre,
-                       level_base, entry_slot);
+                       level_base, entry_slot, new_owner, repass ? 1u : 0u);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ NO_SOLUTION = (1 << 64) - 1
 KERNEL_KINDS = ("eval", "verify", "materialize", "compact", "fallback", "intake")
 
 # every symbol include/ltl.h declares
-EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_job_create", "ltl_eval_level",
+EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
            "ltl_status_str")
 
@@ -57,6 +57,16 @@ class OpSet(C.Structure):
 
 class Node(C.Structure):
     _fields_ = [("op", C.c_uint32), ("a", C.c_uint32), ("b", C.c_uint32)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("device", C.c_int32), ("flags", C.c_uint32), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_uint64), ("lanes", C.c_uint32), ("hash_slots_log2", C.c_uint32),
+                ("word_bits", C.c_uint32), ("fp_bits", C.c_uint32), ("max_entries", C.c_uint64)]
+
+
+class BatchJob(C.Structure):
+    _fields_ = [("spec", Spec), ("ops", OpSet), ("cost_bound", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Result(C.Structure):
@@ -97,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     L.ltl_ctx_destroy.restype = None
     L.ltl_learn.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(Result)]
     L.ltl_learn.restype = C.c_int
+    L.ltl_learn_batch.argtypes = [P(BatchOpts), P(BatchJob), C.c_uint32, P(Result), P(C.c_double)]
+    L.ltl_learn_batch.restype = C.c_int
     L.ltl_job_create.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(C.c_void_p)]
     L.ltl_job_create.restype = C.c_int
     L.ltl_eval_level.argtypes = [C.c_void_p, C.c_uint32, P(LevelStats)]
@@ -311,3 +323,34 @@ class Job:
         if st != LTL_OK:
             raise LTLError(st, "ltl_job_get_info")
         return i
+
+
+def learn_batch(specs, bounds, lanes: int = 8, workspace_bytes: int = 8 << 30, device: int = 0, flags: int = 0,
+                hash_slots_log2: int = 0, word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0,
+                cost=None, ops=None, workspace=None):
+    """Runs many jobs, `lanes` at a time (ltl_learn_batch).  Returns (results, durations_ms, completion_ms)."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
+    L = load_library()
+    bufs = [s if isinstance(s, SpecBuffers) else SpecBuffers(s) for s in specs]
+    n = len(bufs)
+    if workspace is None:
+        workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+    o = BatchOpts()
+    o.device, o.flags, o.workspace = device, flags, workspace.data_ptr()
+    o.workspace_bytes = workspace.numel()
+    o.lanes, o.hash_slots_log2, o.word_bits, o.fp_bits, o.max_entries = lanes, hash_slots_log2, word_bits, \
+        fp_bits, max_entries
+    jobs = (BatchJob * n)()
+    for i, b in enumerate(bufs):
+        jobs[i].spec = b.c
+        jobs[i].ops = opset(cost, ops)
+        jobs[i].cost_bound = int(bounds[i])
+    res = (Result * n)()
+    ms = (C.c_double * (2 * n))()
+    torch.cuda.synchronize()
+    st = L.ltl_learn_batch(C.byref(o), jobs, n, res, ms)
+    if st != LTL_OK:
+        raise LTLError(st, "ltl_learn_batch")
+    return [_convert(res[i]) for i in range(n)], [ms[2 * i] for i in range(n)], [ms[2 * i + 1] for i in range(n)]

@@ -305,3 +305,20 @@ def hamming_instance(seed: int, length: int, delta: int) -> Instance:
             t[f // 2] ^= np.uint32(1 << (f % 2))
         negs.append(t)
     return from_traces([tr.tolist()], [t.tolist() for t in negs], 2, name=f"hamming/{length}/{delta}/{seed}")
+
+
+def batched_jobs(master_seed: int = 0, njobs: int = 256):
+    """The batched workload: independent jobs of uneven size.  Job j: propositions
+    uniform in {2..5}, traces per class log-uniform in [16, 2048], lengths uniform in
+    [8, 128], planted size uniform in [5, 10], Bernoulli(0.5) letters, cost bound =
+    planted size + 2.  Returns a list of (Instance, bound)."""
+    out = []
+    for j in range(njobs):
+        rng = np.random.default_rng([master_seed, 0xBA7C, j])
+        A = int(rng.integers(2, 6))
+        k = int(round(float(np.exp(rng.uniform(np.log(16), np.log(2048))))))
+        size = int(rng.integers(5, 11))
+        inst = planted_instance(1_000_003 * (master_seed + 1) + j, A, k, 8, 128, 0.5, size,
+                                name=f"batched/{master_seed}/{j}")
+        out.append((inst, size + 2))
+    return out

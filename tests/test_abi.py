@@ -56,6 +56,8 @@ int main(void) {
   O(ltl_result, colliders); O(ltl_result, kernel_ms); O(ltl_result, kernel_launches);
   S(ltl_level_stats); O(ltl_level_stats, kernel_ms);
   S(ltl_job_info); O(ltl_job_info, arena_bytes);
+  S(ltl_batch_opts); O(ltl_batch_opts, workspace); O(ltl_batch_opts, lanes); O(ltl_batch_opts, max_entries);
+  S(ltl_batch_job); O(ltl_batch_job, ops); O(ltl_batch_job, cost_bound);
   return 0;
 }
 ''')
@@ -63,7 +65,8 @@ int main(void) {
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
     m = {"ltl_ctx_opts": ltl.CtxOpts, "ltl_spec": ltl.Spec, "ltl_opset": ltl.OpSet, "ltl_node": ltl.Node,
-         "ltl_result": ltl.Result, "ltl_level_stats": ltl.LevelStats, "ltl_job_info": ltl.JobInfo}
+         "ltl_result": ltl.Result, "ltl_level_stats": ltl.LevelStats, "ltl_job_info": ltl.JobInfo,
+         "ltl_batch_opts": ltl.BatchOpts, "ltl_batch_job": ltl.BatchJob}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")

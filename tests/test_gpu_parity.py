@@ -235,3 +235,24 @@ def test_table_reuse_across_jobs_after_oom(ltl):
             _same(c.learn(inst, 7), O.learn(inst, 7, max_entries=30), f"reuse/{seed}")
     finally:
         c.close()
+
+
+def test_batched_lanes_match_plain_runs(ltl):
+    """ltl_learn_batch: every job's result equals its plain ltl_learn run (same slice size)."""
+    jobs = [synth.preset_instance("tiny", s) for s in range(24)]
+    insts = [j[0] for j in jobs]
+    bounds = [j[1]["bound"] for j in jobs]
+    lanes = 4
+    ws = 1 << 30
+    res, dur, done = ltl.learn_batch(insts, bounds, lanes=lanes, workspace_bytes=ws, hash_slots_log2=18)
+    plain = ltl.Context(workspace_bytes=ws // lanes, hash_slots_log2=18)
+    try:
+        for inst, b, g in zip(insts, bounds, res):
+            p = plain.learn(inst, b)
+            assert (g.status, g.cost, g.level_new, g.level_candidates, g.solution_index, g.solution) == \
+                   (p.status, p.cost, p.level_new, p.level_candidates, p.solution_index, p.solution)
+            o = O.learn(inst, b)
+            _same(g, o, "batched")
+    finally:
+        plain.close()
+    assert all(d > 0 for d in dur) and max(done) >= max(dur)
