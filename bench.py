@@ -65,7 +65,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long"])
+    ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long", "batched"])
+    ap.add_argument("--jobs", type=int, default=256, help="batched workload: number of jobs")
+    ap.add_argument("--lanes", type=int, default=8, help="batched workload: jobs in flight")
     ap.add_argument("--seeds", default="0-7")
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
@@ -87,6 +89,8 @@ def main():
     import torch
     from paper_2402_12373_amd import ltl, synth
 
+    if args.workload == "batched":
+        return bench_batched(args)
     seeds = parse_seeds(args.seeds)
     cfg = dict(synth.PRESETS[args.workload])
     if args.bound:
@@ -227,6 +231,72 @@ def main():
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_levels)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def bench_batched(args):
+    """Batched learning: many uneven jobs, `lanes` in flight (ltl_learn_batch), against the
+    plain path (the same jobs one at a time, same per-job workspace)."""
+    import numpy as np
+    import torch
+    from paper_2402_12373_amd import ltl, synth
+    jobs = synth.batched_jobs(0, args.jobs)
+    insts = [j[0] for j in jobs]
+    bounds = [j[1] for j in jobs]
+    dev = [ltl.spec_to_device(i) for i in insts]
+    free, _ = torch.cuda.mem_get_info()
+    ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    slice_bytes = (ws_bytes // args.lanes) & ~255
+    slots = 22
+    # plain path: one job per call, one at a time, in a workspace of one lane's size
+    ctx = ltl.Context(workspace=ws[:slice_bytes], hash_slots_log2=slots)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain, plain_ms = [], []
+    for d, b in zip(dev, bounds):
+        a = time.perf_counter()
+        plain.append(ctx.learn(d, b))
+        plain_ms.append((time.perf_counter() - a) * 1e3)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ctx.close()
+    # batched
+    t0 = time.perf_counter()
+    res, dur, done = ltl.learn_batch(dev, bounds, lanes=args.lanes, workspace=ws, hash_slots_log2=slots)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = sum(1 for g, p in zip(res, plain) if (g.status, g.cost, g.level_new, g.level_candidates,
+                                                 g.solution_index, g.solution) ==
+               (p.status, p.cost, p.level_new, p.level_candidates, p.solution_index, p.solution))
+    cands = sum(r.candidates for r in res)
+    statuses = {}
+    for r in res:
+        statuses[str(r.status)] = statuses.get(str(r.status), 0) + 1
+    out = {
+        "metric": "learn jobs/s",
+        "value": round(len(res) / t_batch, 3),
+        "unit": "jobs/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"batched: {len(res)} jobs, props U{{2..5}}, traces/class log-U[16,2048], "
+                               f"len U[8,128], planted size U[5,10], bound size+2; lanes {args.lanes}",
+                   "lanes": args.lanes, "slice_gb": round(slice_bytes / 2 ** 30, 2)},
+        "job_latency_ms_p50": round(float(np.percentile(done, 50)), 3),
+        "job_latency_ms_p99": round(float(np.percentile(done, 99)), 3),
+        "job_duration_ms_p50": round(float(np.percentile(dur, 50)), 3),
+        "job_duration_ms_p99": round(float(np.percentile(dur, 99)), 3),
+        "candidates_per_s": round(cands / t_batch, 1),
+        "plain": {"jobs_per_s": round(len(res) / t_plain, 3), "wall_s": round(t_plain, 3),
+                  "job_latency_ms_p50": round(float(np.percentile(np.cumsum(plain_ms), 50)), 3),
+                  "job_latency_ms_p99": round(float(np.percentile(np.cumsum(plain_ms), 99)), 3),
+                  "job_duration_ms_p50": round(float(np.percentile(plain_ms, 50)), 3),
+                  "job_duration_ms_p99": round(float(np.percentile(plain_ms, 99)), 3)},
+        "speedup_vs_plain": round(t_plain / t_batch, 3),
+        "identical_to_plain": f"{same}/{len(res)}",
+        "statuses": statuses,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(insts, levels):
