@@ -67,7 +67,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long", "batched"])
     ap.add_argument("--jobs", type=int, default=256, help="batched workload: number of jobs")
-    ap.add_argument("--lanes", type=int, default=8, help="batched workload: jobs in flight")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="jobs in flight (lanes of a batch executor: own stream, workspace slice, hash table); "
+                         "default 4 for the fixed workloads, 8 for batched; 1 = one job after another")
     ap.add_argument("--seeds", default="0-7")
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
@@ -111,22 +113,36 @@ def main():
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     slots = 26 if args.workload != "tiny" else 20
     flags = ltl.CTX_TIMING | (ltl.CTX_U_CARRY if args.ucarry else 0)
-    ctx = ltl.Context(workspace_bytes=ws_bytes, hash_slots_log2=slots, flags=flags)
+    lanes = args.lanes or 4
+    lanes = max(1, min(lanes, len(dev)))
+    # lanes > 1: the batch executor takes the workspace; the one-stream comparison run gets a
+    # workspace of one lane's size, so both see the same capacity per job
+    ctx_bytes = ws_bytes if lanes == 1 else (ws_bytes // (lanes + 1)) & ~255
+    ctx = ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots, flags=flags)
+    if lanes > 1:
+        ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots, flags=flags)
 
-    def step():
-        return [ctx.learn(d, cfg["bound"]) for d in dev]
+        def step():
+            res, dur, _ = ex.run(dev, [cfg["bound"]] * len(dev))
+            return res, dur
+    else:
+        def step():
+            res, dur = [], []
+            for d in dev:
+                a = time.perf_counter()
+                res.append(ctx.learn(d, cfg["bound"]))
+                dur.append((time.perf_counter() - a) * 1e3)
+            return res, dur
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = []
-    job_ms = []
+    results, job_ms = [], []
     for _ in range(args.steps):
-        for d in dev:
-            tj = time.perf_counter()
-            results.append(ctx.learn(d, cfg["bound"]))
-            job_ms.append((time.perf_counter() - tj) * 1e3)
+        res, dur = step()
+        results += res
+        job_ms += dur
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
@@ -136,65 +152,31 @@ def main():
     tb = [int(i.total_positions) for i in insts]
     tb_mean = sum(tb) / len(tb)
 
-    # per-kernel GPU time, measured with HIP events on the library's stream
-    kern_ms = {k: sum(r.kernel_ms[k] for r in results) for k in ltl.KERNEL_KINDS}
-    kern_n = {k: sum(r.kernel_launches[k] for r in results) for k in ltl.KERNEL_KINDS}
-    dominant = max(kern_ms, key=kern_ms.get)
-
     # algorithmic work of the evaluation / verify kernels
     job = ctx.job(dev[0], 1)
     info = job.info()
     job.close()
-    R = int(info.rows)
-    halves = R * (int(info.word_bits) // 32)
-    k = int(info.doubling_steps)
-    cm_bytes = int(info.cm_bytes)
-
-    # candidate mix: the canonical blocks per level follow from the level sizes
-    ops_total = 0.0
-    bytes_verify = 0.0
-    n_eval_cands = 0
-    for r in results:
-        E = r.level_new
-        for c in range(1, r.levels_done + 1):
-            C = r.level_candidates[c]
-            if C == 0:
-                continue
-            n_eval_cands += C
-            if c == 1:
-                per = OP_OPS["atom"]
-                ops_total += C * halves * (per + 10)
-            else:
-                x = c - 1
-                un = E[x] if x >= 1 else 0
-                u_pairs = sum(E[a] * E[x - a] for a in range(1, x))
-                ao = 0
-                for a in range(1, x // 2 + 1):
-                    b = x - a
-                    ao += E[a] * E[b] if a < b else E[a] * (E[a] - 1) // 2
-                uop = 5 if args.ucarry else 5 * k - 2
-                per_level_ops = un * (OP_OPS["f"] + OP_OPS["g"] + OP_OPS["x"] + OP_OPS["not"] + 4 * 10) \
-                    + u_pairs * (uop + 10) + ao * (OP_OPS["and"] + OP_OPS["or"] + 2 * 10)
-                ops_total += per_level_ops * halves
-            # verify: every non-representative reads its owner's matrix once; new entries are written once
-            bytes_verify += (C - r.level_new[c]) * cm_bytes
-    eval_ms = kern_ms["eval"]
-    verify_ms = kern_ms["verify"]
-    eval_tops = ops_total / (eval_ms * 1e-3) / 1e12 if eval_ms else 0.0
-    verify_gbs = bytes_verify / (verify_ms * 1e-3) / 1e9 if verify_ms else 0.0
-    if dominant == "verify":
-        roof = {"bound": "hbm", "kernel": "k_level<verify>", "achieved": round(verify_gbs, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(verify_gbs / HBM_PEAK_GBS, 4),
-                "traffic": None}
-    else:
-        roof = {"bound": "alu", "kernel": "k_level<eval>", "achieved": round(eval_tops, 3),
-                "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
-                "frac": round(eval_tops / VALU_PEAK_TOPS, 4), "traffic": None}
-    t = measured_traffic(dominant)
+    geom = dict(R=int(info.rows), halves=int(info.rows) * (int(info.word_bits) // 32), k=int(info.doubling_steps),
+                cm_bytes=int(info.cm_bytes))
+    roof, kern_ms, eval_tops, verify_gbs = roofline(ltl, results, geom, args.ucarry)
+    t = measured_traffic(roof["kind"])
     roof["traffic"] = None if t is None else round(t / 1e6, 3)
     roof["traffic_unit"] = "MB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
-    roof["avg_launch_ms"] = round(kern_ms[dominant] / max(1, kern_n[dominant]), 4)
-    roof["launches"] = kern_n[dominant]
+
+    # the same jobs one after another on one stream (context for the concurrent figure)
+    seq = None
+    if lanes > 1:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sres = [ctx.learn(d, cfg["bound"]) for d in dev]
+        torch.cuda.synchronize()
+        sw = time.perf_counter() - a
+        same = all((x.status, x.cost, x.level_new, x.solution_index) == (y.status, y.cost, y.level_new, y.solution_index)
+                   for x, y in zip(sres, results[:len(dev)]))
+        sroof = roofline(ltl, sres, geom, args.ucarry)[0]
+        seq = {"candidates_per_s": round(sum(r.candidates for r in sres) / sw, 1), "ms_per_step": round(sw * 1e3, 3),
+               "roofline_frac": sroof["frac"], "avg_launch_ms": sroof["avg_launch_ms"],
+               "identical_results": same}
 
     out = {
         "metric": "candidate formulae evaluated/s",
@@ -212,7 +194,7 @@ def main():
         "config": {"workload": f"{args.workload}: {cfg['num_props']} props, {cfg['k']}+{cfg['k']} traces, "
                                f"len {cfg['lo']}..{cfg['hi']}, p={cfg['p']}, planted size {cfg['size']}, "
                                f"cost bound {cfg['bound']}, seeds {args.seeds}",
-                   "jobs_per_step": len(dev), "hash_slots_log2": slots,
+                   "jobs_per_step": len(dev), "lanes": lanes, "hash_slots_log2": slots,
                    "u_operator": "carry" if args.ucarry else "doubling"},
         "trace_bits_per_s": round(value * tb_mean, 1),
         "jobs_per_s": round(len(results) / wall, 3),
@@ -226,10 +208,14 @@ def main():
         "eval_Tops": round(eval_tops, 3),
         "roofline": roof,
     }
+    if seq is not None:
+        out["sequential"] = seq
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_levels)
     print(json.dumps(out), flush=True)
+    if lanes > 1:
+        ex.close()
     ctx.close()
 
 
@@ -246,10 +232,13 @@ def bench_batched(args):
     free, _ = torch.cuda.mem_get_info()
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    slice_bytes = (ws_bytes // args.lanes) & ~255
+    lanes = args.lanes or 8
+    slice_bytes = (ws_bytes // lanes) & ~255
     slots = 22
     # plain path: one job per call, one at a time, in a workspace of one lane's size
     ctx = ltl.Context(workspace=ws[:slice_bytes], hash_slots_log2=slots)
+    for d, b in zip(dev[:lanes], bounds[:lanes]):           # warm-up
+        ctx.learn(d, b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain, plain_ms = [], []
@@ -260,11 +249,16 @@ def bench_batched(args):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     ctx.close()
-    # batched
+    print(f"plain path: {len(plain)} jobs in {t_plain:.2f} s", file=sys.stderr, flush=True)
+    # batched: a batch executor (lanes created once, outside the timed region)
+    ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots)
+    ex.run(dev[:lanes], bounds[:lanes])                     # warm-up: one job per lane
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res, dur, done = ltl.learn_batch(dev, bounds, lanes=args.lanes, workspace=ws, hash_slots_log2=slots)
+    res, dur, done = ex.run(dev, bounds)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    ex.close()
     same = sum(1 for g, p in zip(res, plain) if (g.status, g.cost, g.level_new, g.level_candidates,
                                                  g.solution_index, g.solution) ==
                (p.status, p.cost, p.level_new, p.level_candidates, p.solution_index, p.solution))
@@ -280,8 +274,8 @@ def bench_batched(args):
         "ms_per_step": round(t_batch * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"batched: {len(res)} jobs, props U{{2..5}}, traces/class log-U[16,2048], "
-                               f"len U[8,128], planted size U[5,10], bound size+2; lanes {args.lanes}",
-                   "lanes": args.lanes, "slice_gb": round(slice_bytes / 2 ** 30, 2)},
+                               f"len U[8,128], planted size U[5,10], bound size+2; lanes {lanes}",
+                   "lanes": lanes, "slice_gb": round(slice_bytes / 2 ** 30, 2)},
         "job_latency_ms_p50": round(float(np.percentile(done, 50)), 3),
         "job_latency_ms_p99": round(float(np.percentile(done, 99)), 3),
         "job_duration_ms_p50": round(float(np.percentile(dur, 50)), 3),
@@ -297,6 +291,53 @@ def bench_batched(args):
         "statuses": statuses,
     }
     print(json.dumps(out), flush=True)
+
+
+def roofline(ltl, results, geom, ucarry):
+    """Roofline of the dominant kernel kind over `results` (HIP-event times summed per kind)."""
+    kern_ms = {k: sum(r.kernel_ms[k] for r in results) for k in ltl.KERNEL_KINDS}
+    kern_n = {k: sum(r.kernel_launches[k] for r in results) for k in ltl.KERNEL_KINDS}
+    dominant = max(kern_ms, key=kern_ms.get)
+    halves, k, cm_bytes = geom["halves"], geom["k"], geom["cm_bytes"]
+    # candidate mix: the canonical blocks per level follow from the level sizes
+    ops_total = 0.0
+    bytes_verify = 0.0
+    for r in results:
+        E = r.level_new
+        for c in range(1, r.levels_done + 1):
+            C = r.level_candidates[c]
+            if C == 0:
+                continue
+            if c == 1:
+                ops_total += C * halves * (OP_OPS["atom"] + 10)
+            else:
+                x = c - 1
+                un = E[x] if x >= 1 else 0
+                u_pairs = sum(E[a] * E[x - a] for a in range(1, x))
+                ao = 0
+                for a in range(1, x // 2 + 1):
+                    b = x - a
+                    ao += E[a] * E[b] if a < b else E[a] * (E[a] - 1) // 2
+                uop = 5 if ucarry else 5 * k - 2
+                per_level_ops = un * (OP_OPS["f"] + OP_OPS["g"] + OP_OPS["x"] + OP_OPS["not"] + 4 * 10) \
+                    + u_pairs * (uop + 10) + ao * (OP_OPS["and"] + OP_OPS["or"] + 2 * 10)
+                ops_total += per_level_ops * halves
+            # verify: every non-representative reads its owner's matrix once
+            bytes_verify += (C - r.level_new[c]) * cm_bytes
+    eval_ms, verify_ms = kern_ms["eval"], kern_ms["verify"]
+    eval_tops = ops_total / (eval_ms * 1e-3) / 1e12 if eval_ms else 0.0
+    verify_gbs = bytes_verify / (verify_ms * 1e-3) / 1e9 if verify_ms else 0.0
+    if dominant == "verify":
+        roof = {"bound": "hbm", "kernel": "k_level<verify>", "achieved": round(verify_gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(verify_gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "alu", "kernel": "k_level<eval>", "achieved": round(eval_tops, 3),
+                "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
+                "frac": round(eval_tops / VALU_PEAK_TOPS, 4)}
+    roof["kind"] = dominant
+    roof["avg_launch_ms"] = round(kern_ms[dominant] / max(1, kern_n[dominant]), 4)
+    roof["launches"] = kern_n[dominant]
+    return roof, kern_ms, eval_tops, verify_gbs
 
 
 def cpu_baseline(insts, levels):

@@ -194,6 +194,20 @@ typedef struct {
 int ltl_learn_batch(const ltl_batch_opts *opts, const ltl_batch_job *jobs, uint32_t njobs, ltl_result *results,
                     double *job_ms);
 
+/* The same lanes kept for many calls: a batch executor owns `lanes` contexts
+ * (each with its stream, its workspace slice and its hash table, initialised
+ * once) and lanes-1 host worker threads.  ltl_batch_run has the semantics of
+ * ltl_learn_batch with the executor's options; consecutive runs reuse the
+ * tables (each job empties the slots it used).  One run at a time per executor
+ * (LTL_E_STATE if a run is already in progress).  The caller keeps the
+ * workspace alive until ltl_batch_destroy, which waits for the lanes' streams.
+ * Errors of ltl_batch_create: LTL_E_INVAL (options), LTL_E_DEVICE. */
+typedef struct ltl_batch ltl_batch;
+int ltl_batch_create(const ltl_batch_opts *opts, ltl_batch **out);
+int ltl_batch_run(ltl_batch *batch, const ltl_batch_job *jobs, uint32_t njobs, ltl_result *results,
+                  double *job_ms);
+void ltl_batch_destroy(ltl_batch *batch);
+
 /* ---------------------------------------------------------------- level-by-level interface */
 
 /* Validate and pack the specification (atom matrices, row layout) into the

@@ -12,11 +12,13 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <thread>
@@ -1061,56 +1063,160 @@ extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *op
 // ---------------------------------------------------------------------------
 // Batched learning: lanes of (stream, workspace slice, context), jobs taken in order
 // ---------------------------------------------------------------------------
-extern "C" int ltl_learn_batch(const ltl_batch_opts *o, const ltl_batch_job *jobs, uint32_t njobs,
-                               ltl_result *results, double *job_ms) {
-    if (!o || (!jobs && njobs) || (!results && njobs) || !o->workspace) return LTL_E_INVAL;
+// A batch executor: `lanes` contexts (stream, workspace slice, hash table) and
+// lanes-1 worker threads that sleep between runs.  The calling thread works as
+// lane 0 of each run.
+struct ltl_batch {
+    ltl_batch_opts o{};
+    std::vector<hipStream_t> streams;
+    std::vector<ltl_ctx *> ctxs;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv_start, cv_done;
+    uint64_t generation = 0;      // bumped once per run
+    uint32_t lanes_busy = 0;      // worker lanes still in the current run
+    bool quit = false;
+    std::atomic<bool> running{false};
+    // the current run
+    const ltl_batch_job *jobs = nullptr;
+    uint32_t njobs = 0;
+    ltl_result *results = nullptr;
+    double *job_ms = nullptr;
+    std::atomic<uint32_t> next{0};
+    std::chrono::steady_clock::time_point t0;
+};
+
+static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
+    for (;;) {
+        const uint32_t i = b->next.fetch_add(1);
+        if (i >= b->njobs) break;
+        const auto a = std::chrono::steady_clock::now();
+        ltl_learn(b->ctxs[lane], &b->jobs[i].spec, &b->jobs[i].ops, b->jobs[i].cost_bound, &b->results[i]);
+        const auto e = std::chrono::steady_clock::now();
+        if (b->job_ms) {
+            b->job_ms[2 * (size_t)i] = std::chrono::duration<double, std::milli>(e - a).count();
+            b->job_ms[2 * (size_t)i + 1] = std::chrono::duration<double, std::milli>(e - b->t0).count();
+        }
+    }
+}
+
+static void batch_worker(ltl_batch *b, uint32_t lane) {
+    (void)hipSetDevice(b->o.device);
+    uint64_t seen = 0;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(b->mu);
+            b->cv_start.wait(lk, [&] { return b->quit || b->generation != seen; });
+            if (b->quit) return;
+            seen = b->generation;
+        }
+        batch_lane_jobs(b, lane);
+        {
+            std::lock_guard<std::mutex> lk(b->mu);
+            if (--b->lanes_busy == 0) b->cv_done.notify_all();
+        }
+    }
+}
+
+extern "C" void ltl_batch_destroy(ltl_batch *b) {
+    if (!b) return;
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        b->quit = true;
+    }
+    b->cv_start.notify_all();
+    for (auto &t : b->workers) t.join();
+    for (size_t l = 0; l < b->ctxs.size(); ++l)
+        if (b->ctxs[l]) ltl_ctx_destroy(b->ctxs[l]);
+    for (size_t l = 0; l < b->streams.size(); ++l)
+        if (b->streams[l]) {
+            (void)hipStreamSynchronize(b->streams[l]);
+            (void)hipStreamDestroy(b->streams[l]);
+        }
+    delete b;
+}
+
+extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
+    if (!out) return LTL_E_INVAL;
+    *out = nullptr;
+    if (!o || !o->workspace) return LTL_E_INVAL;
     if (o->lanes < 1 || o->lanes > 64) return LTL_E_INVAL;
     const uint64_t slice = (o->workspace_bytes / o->lanes) & ~255ull;
     if (slice < LTL_MIN_WORKSPACE) return LTL_E_INVAL;
     if (hipSetDevice(o->device) != hipSuccess) return LTL_E_DEVICE;
-    const uint32_t lanes = std::min<uint32_t>(o->lanes, std::max<uint32_t>(njobs, 1u));
-    std::vector<hipStream_t> streams(lanes, nullptr);
-    std::vector<ltl_ctx *> ctxs(lanes, nullptr);
+    ltl_batch *b = new (std::nothrow) ltl_batch();
+    if (!b) return LTL_E_INVAL;
+    b->o = *o;
+    const uint32_t lanes = o->lanes;
+    b->streams.assign(lanes, nullptr);
+    b->ctxs.assign(lanes, nullptr);
     int st = LTL_OK;
     for (uint32_t l = 0; l < lanes && st == LTL_OK; ++l) {
-        if (hipStreamCreateWithFlags(&streams[l], hipStreamNonBlocking) != hipSuccess) { st = LTL_E_DEVICE; break; }
+        if (hipStreamCreateWithFlags(&b->streams[l], hipStreamNonBlocking) != hipSuccess) {
+            st = LTL_E_DEVICE;
+            break;
+        }
         ltl_ctx_opts co{};
         co.device = o->device;
         co.flags = o->flags;
         co.workspace = (char *)o->workspace + (uint64_t)l * slice;
         co.workspace_bytes = slice;
-        co.stream = streams[l];
+        co.stream = b->streams[l];
         co.hash_slots_log2 = o->hash_slots_log2;
         co.word_bits = o->word_bits;
         co.fp_bits = o->fp_bits;
         co.max_entries = o->max_entries;
-        st = ltl_ctx_create(&co, &ctxs[l]);
+        st = ltl_ctx_create(&co, &b->ctxs[l]);
     }
-    if (st == LTL_OK) {
-        std::atomic<uint32_t> next{0};
-        const auto t0 = std::chrono::steady_clock::now();
-        auto worker = [&](uint32_t l) {
-            (void)hipSetDevice(o->device);
-            for (;;) {
-                const uint32_t i = next.fetch_add(1);
-                if (i >= njobs) break;
-                const auto a = std::chrono::steady_clock::now();
-                ltl_learn(ctxs[l], &jobs[i].spec, &jobs[i].ops, jobs[i].cost_bound, &results[i]);
-                const auto b = std::chrono::steady_clock::now();
-                if (job_ms) {
-                    job_ms[2 * (size_t)i] = std::chrono::duration<double, std::milli>(b - a).count();
-                    job_ms[2 * (size_t)i + 1] = std::chrono::duration<double, std::milli>(b - t0).count();
-                }
-            }
-        };
-        std::vector<std::thread> th;
-        for (uint32_t l = 1; l < lanes; ++l) th.emplace_back(worker, l);
-        worker(0);
-        for (auto &t : th) t.join();
+    if (st != LTL_OK) {
+        ltl_batch_destroy(b);
+        return st;
     }
-    for (uint32_t l = 0; l < lanes; ++l) {
-        if (ctxs[l]) ltl_ctx_destroy(ctxs[l]);
-        if (streams[l]) (void)hipStreamDestroy(streams[l]);
+    for (uint32_t l = 1; l < lanes; ++l) b->workers.emplace_back(batch_worker, b, l);
+    *out = b;
+    return LTL_OK;
+}
+
+extern "C" int ltl_batch_run(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, ltl_result *results,
+                             double *job_ms) {
+    if (!b || (!jobs && njobs) || (!results && njobs)) return LTL_E_INVAL;
+    if (b->running.exchange(true)) return LTL_E_STATE;
+    if (hipSetDevice(b->o.device) != hipSuccess) {
+        b->running = false;
+        return LTL_E_DEVICE;
     }
+    b->jobs = jobs;
+    b->njobs = njobs;
+    b->results = results;
+    b->job_ms = job_ms;
+    b->next = 0;
+    b->t0 = std::chrono::steady_clock::now();
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        b->lanes_busy = (uint32_t)b->workers.size();
+        ++b->generation;
+    }
+    b->cv_start.notify_all();
+    batch_lane_jobs(b, 0);
+    {
+        std::unique_lock<std::mutex> lk(b->mu);
+        b->cv_done.wait(lk, [&] { return b->lanes_busy == 0; });
+    }
+    b->running = false;
+    return LTL_OK;
+}
+
+extern "C" int ltl_learn_batch(const ltl_batch_opts *o, const ltl_batch_job *jobs, uint32_t njobs,
+                               ltl_result *results, double *job_ms) {
+    if (!o || (!jobs && njobs) || (!results && njobs)) return LTL_E_INVAL;
+    ltl_batch_opts oo = *o;
+    if (oo.lanes >= 1 && oo.lanes <= 64) oo.lanes = std::min<uint32_t>(oo.lanes, std::max<uint32_t>(njobs, 1u));
+    // the slice size is that of the requested lane count, so results do not depend on njobs
+    if (o->lanes >= 1 && o->lanes <= 64) oo.workspace_bytes = ((o->workspace_bytes / o->lanes) & ~255ull) * oo.lanes;
+    ltl_batch *b = nullptr;
+    int st = ltl_batch_create(&oo, &b);
+    if (st != LTL_OK) return st;
+    st = ltl_batch_run(b, jobs, njobs, results, job_ms);
+    ltl_batch_destroy(b);
     return st;
 }

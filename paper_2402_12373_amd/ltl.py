@@ -27,7 +27,8 @@ NO_SOLUTION = (1 << 64) - 1
 KERNEL_KINDS = ("eval", "verify", "materialize", "compact", "fallback", "intake")
 
 # every symbol include/ltl.h declares
-EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", "ltl_job_create", "ltl_eval_level",
+EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", "ltl_batch_create", "ltl_batch_run",
+           "ltl_batch_destroy", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
            "ltl_status_str")
 
@@ -109,6 +110,12 @@ def load_library(path: str = LIB_PATH):
     L.ltl_learn.restype = C.c_int
     L.ltl_learn_batch.argtypes = [P(BatchOpts), P(BatchJob), C.c_uint32, P(Result), P(C.c_double)]
     L.ltl_learn_batch.restype = C.c_int
+    L.ltl_batch_create.argtypes = [P(BatchOpts), P(C.c_void_p)]
+    L.ltl_batch_create.restype = C.c_int
+    L.ltl_batch_run.argtypes = [C.c_void_p, P(BatchJob), C.c_uint32, P(Result), P(C.c_double)]
+    L.ltl_batch_run.restype = C.c_int
+    L.ltl_batch_destroy.argtypes = [C.c_void_p]
+    L.ltl_batch_destroy.restype = None
     L.ltl_job_create.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(C.c_void_p)]
     L.ltl_job_create.restype = C.c_int
     L.ltl_eval_level.argtypes = [C.c_void_p, C.c_uint32, P(LevelStats)]
@@ -325,6 +332,71 @@ class Job:
         return i
 
 
+def _batch_opts(workspace, lanes, device, flags, hash_slots_log2, word_bits, fp_bits, max_entries):
+    o = BatchOpts()
+    o.device, o.flags, o.workspace = device, flags, workspace.data_ptr()
+    o.workspace_bytes = workspace.numel()
+    o.lanes, o.hash_slots_log2, o.word_bits, o.fp_bits, o.max_entries = lanes, hash_slots_log2, word_bits, \
+        fp_bits, max_entries
+    return o
+
+
+def _batch_jobs(specs, bounds, cost, ops):
+    bufs = [s if isinstance(s, SpecBuffers) else SpecBuffers(s) for s in specs]
+    jobs = (BatchJob * len(bufs))()
+    for i, b in enumerate(bufs):
+        jobs[i].spec = b.c
+        jobs[i].ops = opset(cost, ops)
+        jobs[i].cost_bound = int(bounds[i])
+    return jobs, bufs
+
+
+class Batch:
+    """A batch executor (ltl_batch_create): `lanes` contexts, each with its own stream,
+    workspace slice and hash table, kept across runs."""
+
+    def __init__(self, lanes: int = 4, workspace_bytes: int = 8 << 30, device: int = 0, flags: int = 0,
+                 hash_slots_log2: int = 0, word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0,
+                 workspace=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
+        self._L = load_library()
+        if workspace is None:
+            workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        self.workspace = workspace
+        self.lanes = lanes
+        o = _batch_opts(workspace, lanes, device, flags, hash_slots_log2, word_bits, fp_bits, max_entries)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        st = self._L.ltl_batch_create(C.byref(o), C.byref(h))
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_batch_create")
+        self._h = h
+
+    def run(self, specs, bounds, cost=None, ops=None):
+        """Runs the jobs; returns (results, durations_ms, completion_ms)."""
+        jobs, bufs = _batch_jobs(specs, bounds, cost, ops)
+        n = len(bufs)
+        res = (Result * n)()
+        ms = (C.c_double * (2 * n))()
+        st = self._L.ltl_batch_run(self._h, jobs, n, res, ms)
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_batch_run")
+        return [_convert(res[i]) for i in range(n)], [ms[2 * i] for i in range(n)], [ms[2 * i + 1] for i in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ltl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def learn_batch(specs, bounds, lanes: int = 8, workspace_bytes: int = 8 << 30, device: int = 0, flags: int = 0,
                 hash_slots_log2: int = 0, word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0,
                 cost=None, ops=None, workspace=None):
@@ -333,20 +405,11 @@ def learn_batch(specs, bounds, lanes: int = 8, workspace_bytes: int = 8 << 30, d
     if not torch.cuda.is_available():
         raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
     L = load_library()
-    bufs = [s if isinstance(s, SpecBuffers) else SpecBuffers(s) for s in specs]
-    n = len(bufs)
     if workspace is None:
         workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
-    o = BatchOpts()
-    o.device, o.flags, o.workspace = device, flags, workspace.data_ptr()
-    o.workspace_bytes = workspace.numel()
-    o.lanes, o.hash_slots_log2, o.word_bits, o.fp_bits, o.max_entries = lanes, hash_slots_log2, word_bits, \
-        fp_bits, max_entries
-    jobs = (BatchJob * n)()
-    for i, b in enumerate(bufs):
-        jobs[i].spec = b.c
-        jobs[i].ops = opset(cost, ops)
-        jobs[i].cost_bound = int(bounds[i])
+    o = _batch_opts(workspace, lanes, device, flags, hash_slots_log2, word_bits, fp_bits, max_entries)
+    jobs, bufs = _batch_jobs(specs, bounds, cost, ops)
+    n = len(bufs)
     res = (Result * n)()
     ms = (C.c_double * (2 * n))()
     torch.cuda.synchronize()

@@ -256,3 +256,25 @@ def test_batched_lanes_match_plain_runs(ltl):
     finally:
         plain.close()
     assert all(d > 0 for d in dur) and max(done) >= max(dur)
+
+
+def test_batch_executor_reuse(ltl):
+    """ltl_batch_create/run: lanes kept across runs (tables reused); results equal plain runs."""
+    jobs = [synth.preset_instance("tiny", s) for s in range(40, 60)]
+    insts = [j[0] for j in jobs]
+    bounds = [j[1]["bound"] for j in jobs]
+    ex = ltl.Batch(lanes=3, workspace_bytes=768 << 20, hash_slots_log2=16, max_entries=3000)
+    plain = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=16, max_entries=3000)
+    try:
+        first, _, _ = ex.run(insts[:12], bounds[:12])
+        second, dur, done = ex.run(insts[8:], bounds[8:])
+        bad, _, _ = ex.run(insts[:1], [0])              # a bad job fails alone; the run goes on
+        assert bad[0].status == ltl.LTL_E_INVAL
+        for inst, b, g in list(zip(insts[:12], bounds[:12], first)) + list(zip(insts[8:], bounds[8:], second)):
+            p = plain.learn(inst, b)
+            assert (g.status, g.cost, g.level_new, g.level_candidates, g.solution_index, g.solution) == \
+                   (p.status, p.cost, p.level_new, p.level_candidates, p.solution_index, p.solution)
+        assert len(dur) == 12 and all(d > 0 for d in dur)
+    finally:
+        ex.close()
+        plain.close()
