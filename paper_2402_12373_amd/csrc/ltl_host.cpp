@@ -102,7 +102,8 @@ struct ltl_job {
     uint64_t wsb = 0, used = 0;
     Counters *ctr = nullptr;
     void *valid = nullptr, *sepm = nullptr, *sepw = nullptr, *atoms = nullptr;
-    uint64_t *nxt = nullptr, *key = nullptr, *tfp = nullptr, *offsets_d = nullptr;
+    uint64_t *nxt = nullptr, *tfp = nullptr, *offsets_d = nullptr;
+    uint32_t *key = nullptr;
     uint32_t *row_trace = nullptr, *row_word = nullptr, *letters_d = nullptr;
     Block *blocks_d = nullptr;       // canonical order (candidate decode)
     Block *blocks_cls_d = nullptr;   // grouped by connective class, class-local tiles
@@ -111,6 +112,7 @@ struct ltl_job {
     uint32_t slots_log2 = 0;
     uint32_t *recipe = nullptr;
     uint32_t *entry_slot = nullptr;  // per global entry: its hash slot (to empty the table afterwards)
+    uint32_t *store = nullptr;       // per global entry: arena position of its matrix
     uint64_t recipe_cap = 0, max_entries = 0;
     bool table_consistent = true;    // every claimed slot belongs to a finalized entry
     char *arena = nullptr;
@@ -322,6 +324,8 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     while ((1ull << k) < maxlen) ++k;
     j->ksteps = k;
     j->cm_bytes = R * j->wbytes;
+    // kernels address rows of a matrix (and of the row tables) with 32-bit byte offsets
+    if (j->cm_bytes >= (1ull << 31) || R * 8ull >= (1ull << 31)) return LTL_E_TOO_LONG;
 
     // host row metadata
     const uint64_t W = wb;
@@ -345,9 +349,9 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
         }
     }
     const uint32_t nkeys = (wb == 64) ? 2u : 1u;
-    std::vector<uint64_t> keys((size_t)R * nkeys);
+    std::vector<uint32_t> keys((size_t)R * nkeys);
     uint64_t seed = 0x5eed1e55c0ffee11ull;
-    for (auto &kk : keys) kk = splitmix64(seed) | 1ull;
+    for (auto &kk : keys) kk = (uint32_t)(splitmix64(seed) >> 32) | 1u;
 
     // workspace carve: the language-cache hash table first (12 bytes per slot), at
     // a fixed place so that a context can hand an emptied table to its next job
@@ -364,7 +368,8 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     j->recipe_cap = nslots;
     j->recipe = (uint32_t *)ws_take(j, nslots * 4);
     j->entry_slot = (uint32_t *)ws_take(j, nslots * 4);
-    if (!j->tkey || !j->tval || !j->recipe || !j->entry_slot) return LTL_E_OOM;
+    j->store = (uint32_t *)ws_take(j, nslots * 4);
+    if (!j->tkey || !j->tval || !j->recipe || !j->entry_slot || !j->store) return LTL_E_OOM;
 
     char *upload = (char *)ws_take(j, UPLOAD_BYTES);   // counters, then the level's block tables
     j->ctr = (Counters *)upload;
@@ -372,7 +377,7 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     j->sepm = ws_take(j, R * j->wbytes);
     j->sepw = ws_take(j, R * j->wbytes);
     j->nxt = (uint64_t *)ws_take(j, R * 8);
-    j->key = (uint64_t *)ws_take(j, R * 8 * nkeys);
+    j->key = (uint32_t *)ws_take(j, R * 4 * nkeys);
     j->row_trace = (uint32_t *)ws_take(j, R * 4);
     j->row_word = (uint32_t *)ws_take(j, R * 4);
     j->atoms = ws_take(j, (uint64_t)j->A * R * j->wbytes);
@@ -405,7 +410,7 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     HIP_TRY(up_words(j->sepm, sepm));
     HIP_TRY(up_words(j->sepw, sepw));
     HIP_TRY(hipMemcpyAsync(j->nxt, nxt.data(), R * 8, hipMemcpyHostToDevice, j->s));
-    HIP_TRY(hipMemcpyAsync(j->key, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, j->s));
+    HIP_TRY(hipMemcpy(j->key, keys.data(), keys.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpyAsync(j->row_trace, row_trace.data(), R * 4, hipMemcpyHostToDevice, j->s));
     HIP_TRY(hipMemcpyAsync(j->row_word, row_word.data(), R * 4, hipMemcpyHostToDevice, j->s));
     if (!(spec->flags & LTL_SPEC_DEVICE)) {
@@ -517,18 +522,21 @@ static void add_block(LevelInfo &lv, int op, int la, int lb, const ltl_job *j, b
         b.nb = 0;
         b.a_gid = 0;
         b.a_ptr = (uint64_t)(uintptr_t)j->atoms;
+        b.ind = 0;
     } else {
+        // children are stored entries, found through store[] (claim order within a level)
         const LevelInfo &A = j->L[la];
         b.na = A.n;
         b.a_gid = A.gid_base;
-        b.a_ptr = (uint64_t)(uintptr_t)(j->arena + (uint64_t)A.gid_base * R * j->wbytes);
+        b.ind = 1;
         if (lb >= 0) {
             const LevelInfo &B = j->L[lb];
             b.nb = B.n;
             b.b_gid = B.gid_base;
-            b.b_ptr = (uint64_t)(uintptr_t)(j->arena + (uint64_t)B.gid_base * R * j->wbytes);
+            b.ind |= 2;
         }
     }
+    (void)R;
     uint64_t nc, nt;
     if (b.nb == 0) {
         nc = b.na;
@@ -645,11 +653,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
     uint32_t *new_slots = (uint32_t *)take_top((uint64_t)new_cap * 4);
+    uint32_t *claimer = (uint32_t *)take_top((uint64_t)new_cap * 4);
     uint32_t *new_owner = (uint32_t *)take_top((uint64_t)new_cap * 4);
     T *stage = (T *)take_top((uint64_t)j->R * sizeof(T));
     const uint64_t arena_off = (uint64_t)(j->arena - j->ws);
     const uint64_t arena_used = j->total_entries * j->cm_bytes;
-    if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !new_owner || !stage ||
+    if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !claimer || !new_owner || !stage ||
         arena_off + arena_used > top)
         return LTL_E_OOM;
     uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
@@ -680,7 +689,8 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             for (int q = 0; q < 4; ++q)
                 if (lv.blocks[bi].op == fops[q]) fuse_idx[q] = (int)bi;
         for (int q = 0; q < 4; ++q)
-            if (fuse_idx[q] < 0 || lv.blocks[fuse_idx[q]].a_ptr != lv.blocks[fuse_idx[0] < 0 ? 0 : fuse_idx[0]].a_ptr)
+            if (fuse_idx[q] < 0 || lv.blocks[fuse_idx[q]].a_gid != lv.blocks[fuse_idx[0] < 0 ? 0 : fuse_idx[0]].a_gid ||
+                lv.blocks[fuse_idx[q]].na != lv.blocks[fuse_idx[0] < 0 ? 0 : fuse_idx[0]].na)
                 fuse_idx[0] = -1;
     }
     const bool fuse = fuse_idx[0] >= 0;
@@ -706,7 +716,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     cls_first[4] = (uint32_t)grouped.size();
     memcpy(pin_grouped, grouped.data(), sizeof(Block) * grouped.size());
-    // small levels evaluate every class in one dispatch: one tile numbering over the grouped blocks
+    // small levels evaluate (and verify) every class in one dispatch: one tile numbering over the grouped blocks
     const bool merged_eval = split && !j->mw;
     Block *pin_all = pin_grouped + grouped.size();
     uint32_t all_tiles = 0;
@@ -738,6 +748,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.ctr = j->ctr;
     A.cand_slot = cand_slot;
     A.new_slots = new_slots;
+    A.claimer = claimer;
     A.new_owner = new_owner;
     A.new_cap = new_cap;
     A.bitmap = bitmap;
@@ -747,6 +758,11 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.arena = (T *)j->arena;
     A.level_base = lv.gid_base;
     A.recipe = j->recipe;
+    A.store = j->store;
+    // whole-row tiles write the claimers' matrices in the evaluation pass; row-split
+    // levels (partial fingerprints, claims made by k_probe) write them in k_materialize
+    A.cw = split ? 0u : 1u;
+    A.verify_rep = 0;
     A.stage = stage;
     A.arena_cap = arena_cap;
     A.ucarry = ucarry ? 1 : 0;
@@ -759,15 +775,15 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         A.mat_chunk = (uint32_t)((j->NB + per - 1) / per);
     }
     auto launch_level = [&](bool verify) -> hipError_t {
-        if (!verify && merged_eval) {
+        if (merged_eval) {
             const uint64_t per = std::max<uint64_t>(
                 1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max(1u, all_tiles)));
             const uint32_t chunk = (uint32_t)((j->NB + per - 1) / per);
             const uint64_t nchunk = (j->NB + chunk - 1) / chunk;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)all_tiles * nchunk + 3) / 4, MAX_GRID);
-            hipError_t e = Launch<T>::level_all(A, j->mw, false, all_d, (uint32_t)grouped.size(), all_tiles, chunk,
+            hipError_t e = Launch<T>::level_all(A, j->mw, verify, all_d, (uint32_t)grouped.size(), all_tiles, chunk,
                                                 grid, j->s);
-            if (e != hipSuccess) return e;
+            if (e != hipSuccess || verify) return e;
             return Launch<T>::probe(A, nc, j->s);
         }
         for (int k = 0; k < 4; ++k) {
@@ -801,20 +817,20 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         Timer tm(j, LTL_K_COMPACT, nw <= SMALL_COMPACT_WORDS ? 1u : 5u);
         if (nw <= SMALL_COMPACT_WORDS) {
             HIP_TRY(launch_compact_small(new_slots, j->ctr, arena_cap, j->tval, bitmap, nw, wordpre, j->recipe,
-                                         lv.gid_base, j->entry_slot, new_owner, j->s));
+                                         lv.gid_base, j->entry_slot, new_owner, j->store, j->s));
         } else {
             HIP_TRY(launch_mark(new_slots, j->ctr, arena_cap, j->tval, bitmap, grid_new, j->s));
             HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
             HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
-                                   j->entry_slot, new_owner, false, grid_new, j->s));
+                                   j->entry_slot, new_owner, j->store, false, grid_new, j->s));
         }
     }
-    {
+    if (split) {
         Timer tm(j, LTL_K_MATERIALIZE);
         HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
     }
     {
-        Timer tm(j, LTL_K_VERIFY, ncls);
+        Timer tm(j, LTL_K_VERIFY, merged_eval ? 1u : ncls);
         HIP_TRY(launch_level(true));
     }
     Counters hc;
@@ -823,9 +839,27 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     lv.first = (hc.first_sol == ~0ull) ? LTL_NO_SOLUTION : (uint64_t)hc.first_sol;
     lv.stored = lv.first == LTL_NO_SOLUTION && c < j->bound;
     uint32_t n_new = hc.n_new;
-    lv.colliders = hc.n_coll;
+    lv.colliders = 0;
     if (hc.n_coll) {
-        // exact resolution of fingerprint collisions, in canonical order
+        // A fingerprint group held two different matrices.  Exact re-check: every
+        // entry gets the matrix of its representative (the canonical-first member),
+        // every other candidate is compared with it, and the ones that differ go to
+        // the sequential fallback in canonical order.
+        HIP_TRY(hipMemsetAsync(coll_bits, 0, nwa * 4, j->s));
+        HIP_TRY(hipMemsetAsync(&j->ctr->n_coll, 0, sizeof(uint32_t), j->s));
+        A.verify_rep = 1;
+        {
+            Timer tm(j, LTL_K_MATERIALIZE);
+            HIP_TRY(Launch<T>::materialize(A, j->mw, 1u, grid_mat, j->s));
+        }
+        {
+            Timer tm(j, LTL_K_VERIFY, merged_eval ? 1u : ncls);
+            HIP_TRY(launch_level(true));
+        }
+        if (int e = sync_read_counters(j, &hc)) return e;
+        lv.colliders = hc.n_coll;
+    }
+    if (hc.n_coll) {
         {
             Timer tm(j, LTL_K_FALLBACK);
             HIP_TRY(Launch<T>::fallback(A, j->mw, nw, nc, j->s));
@@ -838,11 +872,11 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             HIP_TRY(launch_or_bits(bitmap, fb_bits, nw, j->s));
             HIP_TRY(launch_scan(bitmap, nw, chunks, wordpre, j->s));
             HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
-                                   j->entry_slot, new_owner, true, grid_new, j->s));
+                                   j->entry_slot, new_owner, j->store, true, grid_new, j->s));
         }
         {
             Timer tm(j, LTL_K_MATERIALIZE);
-            HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
+            HIP_TRY(Launch<T>::materialize(A, j->mw, 1u, grid_mat, j->s));
         }
     }
     j->table_consistent = true;
@@ -980,7 +1014,9 @@ extern "C" int ltl_job_dump_cm(ltl_job *j, uint32_t cost, uint64_t entry, uint8_
     const LevelInfo &lv = j->L[cost];
     if (!lv.evaluated || entry >= lv.n || cap < j->TB) return LTL_E_INVAL;
     std::vector<uint64_t> words(j->R);
-    const char *src = j->arena + (uint64_t)(lv.gid_base + entry) * j->cm_bytes;
+    uint32_t pos = 0;
+    HIP_TRY(hipMemcpy(&pos, j->store + lv.gid_base + entry, 4, hipMemcpyDeviceToHost));
+    const char *src = j->arena + (uint64_t)pos * j->cm_bytes;
     if (j->wbits == 64) {
         HIP_TRY(hipMemcpy(words.data(), src, j->cm_bytes, hipMemcpyDeviceToHost));
     } else {

@@ -27,9 +27,11 @@ struct Block {
     uint32_t ntile;       // tiles of the block
     uint32_t nti, ntj;    // tile grid (rows of a-tiles, columns of b-tiles)
     uint32_t a_gid, b_gid;   // global entry id of the first a / b entry (ATOM: prop 0)
-    uint64_t a_ptr;       // device address of the first a matrix
-    uint64_t b_ptr;       // device address of the first b matrix (0 for unary)
+    uint64_t a_ptr;       // ATOM: device address of the first atom matrix
+    uint64_t b_ptr;       // unused (0)
     uint32_t fcb[4];      // OP_FUSED4 blocks: canonical base of F, G, X, NOT over the same children
+    uint32_t ind;         // bit 0 / bit 1: a / b children are stored entries, found through store[]
+    uint32_t pad;
 };
 
 // Evaluation-only block: F, G, X and NOT over the same child level in one tile
@@ -52,7 +54,7 @@ struct Rows {
     const T *sepm;           // top bit for the first word of a live trace, else 0
     const T *sepw;           // expected value of that bit: set for P traces
     const uint64_t *nxt;     // lanes (in the row block) holding later words of the same trace
-    const uint64_t *key;     // fingerprint keys: 1 (W=32) or 2 (W=64) per row
+    const uint32_t *key;     // fingerprint keys (odd, 32-bit): 1 (W=32) or 2 (W=64) per row
     uint32_t R, NB;          // words per matrix, 64-word row blocks
     uint32_t ksteps;         // U doubling steps = ceil(log2(longest trace))
     uint32_t maxw;           // longest trace in words
@@ -69,7 +71,8 @@ struct LevelArgs {
     uint64_t fp_mask;
     Counters *ctr;
     uint32_t *cand_slot;     // per candidate: its hash slot (or NO_SLOT)
-    uint32_t *new_slots;     // slots claimed this level
+    uint32_t *new_slots;     // slots claimed this level, in claim order
+    uint32_t *claimer;       // per claim: the candidate that claimed the slot (its matrix is stored)
     uint32_t *new_owner;     // owner (canonical index) of each claimed slot, recorded at settlement
     uint32_t new_cap;
     uint32_t *bitmap;        // per candidate: group representative bit
@@ -79,6 +82,11 @@ struct LevelArgs {
     T *arena;
     uint32_t level_base;     // global id of the level's first entry
     uint32_t *recipe;        // per global entry: canonical candidate index in its level
+    uint32_t *store;         // per global entry: arena position of its matrix (claim order
+                             // within the level: position level_base + claim number)
+    uint32_t cw;             // the evaluation pass writes each claimer's matrix (whole-row tiles)
+    uint32_t verify_rep;     // verify against the representative (exact re-check) instead of
+                             // against the claimer
     T *stage;                // R words of scratch for the fallback
     uint32_t arena_cap;      // new entries the arena can take this level
     int ucarry;
@@ -101,7 +109,9 @@ struct Launch {
     // every connective class in one dispatch (small row-split levels)
     static hipError_t level_all(const LevelArgs<T> &A, bool mw, bool verify, const Block *blocks, uint32_t nblocks,
                                 uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
-    static hipError_t materialize(const LevelArgs<T> &A, bool mw, uint32_t n, uint32_t grid, hipStream_t s);
+    // rep_mode 0: claim order, matrix of each claimer at level_base + claim number;
+    // rep_mode 1: matrix of each entry's representative at store[entry]
+    static hipError_t materialize(const LevelArgs<T> &A, bool mw, uint32_t rep_mode, uint32_t grid, hipStream_t s);
     static hipError_t fallback(const LevelArgs<T> &A, bool mw, uint32_t nwords, uint32_t ncand, hipStream_t s);
     static hipError_t pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
                            const uint32_t *row_word, uint32_t R, uint32_t nprops, T *atoms, Counters *ctr,
@@ -116,11 +126,13 @@ hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipSt
 constexpr uint32_t SMALL_COMPACT_WORDS = 512;
 hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                                 uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
-                                uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner, hipStream_t s);
+                                uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store,
+                                hipStream_t s);
 // recipes + slot settlement (+ entry -> slot); repass re-reads the recorded owners
 hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
-                          uint32_t *entry_slot, uint32_t *new_owner, bool repass, uint32_t grid, hipStream_t s);
+                          uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store, bool repass, uint32_t grid,
+                          hipStream_t s);
 hipError_t launch_clear_slots(const uint32_t *entry_slot, uint32_t n, unsigned long long *tkey, uint32_t *tval,
                               hipStream_t s);
 hipError_t launch_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t nslots, hipStream_t s);

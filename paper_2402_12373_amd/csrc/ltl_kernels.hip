@@ -49,7 +49,8 @@ template <> struct Word<uint64_t> { static constexpr int BITS = 64; };
 template <typename T>
 struct RowMeta {
     T v, sm, sw;
-    uint64_t nx, hn, k0, k1;
+    uint64_t nx, hn;
+    uint32_t k0, k1;
 };
 
 // Global-address-space views: loads through them become global_load with a
@@ -66,6 +67,19 @@ __device__ __forceinline__ gptr<T> as_global(uint64_t p) {
     return (gptr<T>)(uintptr_t)p;
 }
 
+// Element idx of a global array, addressed as a scalar base plus a 32-bit byte
+// offset (one global_load with saddr, no 64-bit address arithmetic per lane).
+// Every array read this way is below 2 GiB (checked when a job is laid out).
+template <typename T>
+__device__ __forceinline__ T ldg(gptr<T> base, uint32_t idx) {
+    return *(gptr<T>)((const __attribute__((address_space(1))) char *)base + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T *base, uint32_t idx, T v) {
+    *(__attribute__((address_space(1))) T *)((__attribute__((address_space(1))) char *)(uintptr_t)base +
+                                             idx * (uint32_t)sizeof(T)) = v;
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
@@ -76,16 +90,17 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 template <typename T, bool MW, bool FULL>
 __device__ __forceinline__ RowMeta<T> load_meta(const Rows<T> &rw, uint32_t r, int lane) {
     RowMeta<T> m;
-    m.v = as_global(rw.valid)[r];
+    m.v = ldg(as_global(rw.valid), r);
     if constexpr (FULL) {
-        m.sw = as_global(rw.sepw)[r];
-        if constexpr (MW || sizeof(T) == 8) m.sm = as_global(rw.sepm)[r];
+        m.sw = ldg(as_global(rw.sepw), r);
+        if constexpr (MW || sizeof(T) == 8) m.sm = ldg(as_global(rw.sepm), r);
         else m.sm = m.v & (T)0x80000000u;     // one word per trace: every live row is a first word
         if constexpr (sizeof(T) == 8) {       // two 32-bit halves, two keys per row
-            m.k0 = as_global(rw.key)[2 * (size_t)r];
-            m.k1 = as_global(rw.key)[2 * (size_t)r + 1];
+            const uint64_t kk = ldg(as_global((const uint64_t *)rw.key), r);
+            m.k0 = (uint32_t)kk;
+            m.k1 = (uint32_t)(kk >> 32);
         } else {
-            m.k0 = as_global(rw.key)[r];
+            m.k0 = ldg(as_global(rw.key), r);
             m.k1 = 0;
         }
     } else {
@@ -93,7 +108,7 @@ __device__ __forceinline__ RowMeta<T> load_meta(const Rows<T> &rw, uint32_t r, i
         m.k0 = m.k1 = 0;
     }
     if constexpr (MW) {
-        m.nx = as_global(rw.nxt)[r];
+        m.nx = ldg(as_global(rw.nxt), r);
     } else {
         m.nx = 0;
     }
@@ -205,11 +220,13 @@ __device__ __forceinline__ T apply(T a, T b, const RowMeta<T> &m, const Rows<T> 
 
 // ---------------------------------------------------------------------------
 // Fingerprint: fp = sum over 32-bit halves h of premix(h) * key (mod 2^64),
-// keys random odd 64-bit numbers per row.  premix is the bijection
-// y = w ^ w>>8; y ^ y>>16, which keeps the 2-adic valuation of any difference
-// below 8, so two matrices differing anywhere collide with probability about
-// 2^-56 over the keys.  Only a function of the matrix matters: every match is
-// confirmed by a full compare.
+// keys random odd 32-bit numbers per half-word (one 32x32->64 multiply-add
+// each).  premix is the bijection y = w ^ w>>8; y ^ y>>16.  Two matrices that
+// differ in one half-word never collide (a nonzero 33-bit difference times an
+// odd 32-bit key is nonzero below 2^64); premix keeps the 2-adic valuation of
+// any difference below 8, so that differences confined to the top bits (the
+// position-0 bits) still spread over the sum.  Only a function of the matrix
+// matters: every match is confirmed by a full compare.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t premix(uint32_t w) {
     uint32_t y = w ^ (w >> 8);
@@ -219,10 +236,10 @@ __device__ __forceinline__ uint32_t premix(uint32_t w) {
 template <typename T>
 __device__ __forceinline__ void fp_add(uint64_t &acc, T w, const RowMeta<T> &m) {
     if constexpr (sizeof(T) == 4) {
-        acc += (uint64_t)premix((uint32_t)w) * m.k0;
+        acc += (uint64_t)premix((uint32_t)w) * (uint64_t)m.k0;
     } else {
-        acc += (uint64_t)premix((uint32_t)w) * m.k0;
-        acc += (uint64_t)premix((uint32_t)(w >> 32)) * m.k1;
+        acc += (uint64_t)premix((uint32_t)w) * (uint64_t)m.k0;
+        acc += (uint64_t)premix((uint32_t)(w >> 32)) * (uint64_t)m.k1;
     }
 }
 
@@ -318,7 +335,8 @@ __device__ __forceinline__ uint32_t rank_of(const uint32_t *bitmap, const uint32
 // level (the smallest canonical index wins by atomicMin).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx) {
+__device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx, uint32_t &claim) {
+    claim = 0xFFFFFFFFu;
     uint32_t h = (uint32_t)(mix64(fp) >> 32) & A.slot_mask;
     for (uint32_t n = 0; n < MAX_PROBES; ++n) {
         unsigned long long k = __hip_atomic_load(&A.tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -327,8 +345,13 @@ __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx
             if (prev == 0ull) {
                 atomicMin(&A.tval[h], idx);
                 uint32_t pos = atomicAdd(&A.ctr->n_new, 1u);
-                if (pos < A.new_cap) A.new_slots[pos] = h;
-                else atomicOr(&A.ctr->overflow, 1u);
+                if (pos < A.new_cap) {
+                    A.new_slots[pos] = h;
+                    A.claimer[pos] = idx;
+                    claim = pos;
+                } else {
+                    atomicOr(&A.ctr->overflow, 1u);
+                }
                 return h;
             }
             k = prev;
@@ -346,8 +369,10 @@ __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx
 
 // ---------------------------------------------------------------------------
 // Level evaluation tile: TI x TJ candidates of one block (TJ = 1 for unary).
-// EVAL   : fingerprint + separation, probe/claim in the language cache.
-// VERIFY : recompute, compare in full with the presumed owner.
+// EVAL   : fingerprint + separation, probe/claim in the language cache; with
+//          A.cw, a second pass writes the matrix of every candidate that
+//          claimed a new slot (its children are still in cache).
+// VERIFY : recompute, compare in full with the stored matrix of the owner.
 // ---------------------------------------------------------------------------
 // F, G, X, NOT of one child, selected by a compile-time index (fused unary tiles)
 template <typename T, bool MW>
@@ -358,24 +383,81 @@ __device__ __forceinline__ T apply_fused(int k, T a, const RowMeta<T> &m, const 
     return apply<T, MW, LTL_NOT>(a, (T)0, m, rw, lane);
 }
 
-template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY>
-__device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane, uint32_t rb0,
+// The words of one row block of every candidate of a tile.  For U, the App. B
+// update cs1 <- cs1 & (cs1 << s) depends on phi (the a side) only: its chain is
+// computed once per a-child and shared by the TJ pairs of that child.
+template <typename T, bool MW, int OP, int TI, int TJ>
+__device__ __forceinline__ void tile_words(const T (&av)[TI], const T (&bv)[TJ], const RowMeta<T> &m,
+                                           const Rows<T> &rw, int lane, T (&w)[TI * TJ]) {
+    if constexpr (OP == LTL_U) {
+        T c1[TI];
+#pragma unroll
+        for (int ii = 0; ii < TI; ++ii) {
+            c1[ii] = av[ii];
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) w[ii * TJ + jj] = bv[jj];
+        }
+        const uint32_t k = rw.ksteps;
+        for (uint32_t i = 0; i < k; ++i) {
+            const uint32_t sh = 1u << i;
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < TJ; ++jj) {
+                    T &c2 = w[ii * TJ + jj];
+                    c2 |= c1[ii] & shl_pos<T, MW>(c2, sh, m, lane);
+                }
+            if (i + 1 < k) {
+#pragma unroll
+                for (int ii = 0; ii < TI; ++ii) c1[ii] &= shl_pos<T, MW>(c1[ii], sh, m, lane);
+            }
+        }
+    } else if constexpr (OP == (int)OP_FUSED4) {
+#pragma unroll
+        for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) w[ii * TJ + jj] = apply_fused<T, MW>(jj, av[ii], m, rw, lane);
+    } else {
+#pragma unroll
+        for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) w[ii * TJ + jj] = apply<T, MW, OP>(av[ii], bv[jj], m, rw, lane);
+    }
+}
+
+// Scalar address of child i on side `which` (0: a, 1: b) of a block: stored
+// entries are found through store[] (claim order within their level), atoms
+// directly.
+template <typename T>
+__device__ __forceinline__ uint64_t child_addr(const LevelArgs<T> &A, const Block &b, int which, uint32_t i) {
+    const uint64_t cmb = (uint64_t)A.rows.R * sizeof(T);
+    if (b.ind & (which ? 2u : 1u)) {
+        const uint32_t pos = uniform(A.store[(which ? b.b_gid : b.a_gid) + i]);
+        return (uint64_t)(uintptr_t)A.arena + (uint64_t)pos * cmb;
+    }
+    return (which ? b.b_ptr : b.a_ptr) + (uint64_t)i * cmb;
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t arena_addr(const LevelArgs<T> &A, uint32_t pos) {
+    return (uint64_t)(uintptr_t)A.arena + (uint64_t)pos * A.rows.R * sizeof(T);
+}
+
+template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY, bool CW = true>
+__device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane, uint32_t rb0,
                          uint32_t rb1) {
     constexpr int NP = TI * TJ;
     constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
     constexpr bool FUSED = (OP == (int)OP_FUSED4);
-    const uint32_t R = A.rows.R;
     const uint32_t nbj = b.tri ? b.na : b.nb;
     // child matrices of the tile (clamped; results of out-of-range pairs are dropped)
     gptr<T> ap[TI];
     gptr<T> bp[TJ];
 #pragma unroll
-    for (int ii = 0; ii < TI; ++ii)
-        ap[ii] = as_global<T>(uniform64(b.a_ptr + (uint64_t)min(i0 + ii, b.na - 1) * R * sizeof(T)));
+    for (int ii = 0; ii < TI; ++ii) ap[ii] = as_global<T>(child_addr<T>(A, b, 0, min(i0 + ii, b.na - 1)));
 #pragma unroll
     for (int jj = 0; jj < TJ; ++jj)
-        bp[jj] = BIN ? as_global<T>(uniform64(b.b_ptr + (uint64_t)min(j0 + jj, nbj - 1) * R * sizeof(T)))
-                     : (gptr<T>)nullptr;
+        bp[jj] = BIN ? as_global<T>(child_addr<T>(A, b, 1, min(j0 + jj, nbj - 1))) : (gptr<T>)nullptr;
     // canonical index of each pair, 0xFFFFFFFF if the pair is outside the block
     uint32_t idx[NP];
 #pragma unroll
@@ -395,9 +477,8 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
         T av[TI], bv[TJ];
         T tv[VERIFY ? NP : 1];
     };
-    uint32_t tgt[VERIFY ? NP : 1];
+    gptr<T> tp[VERIFY ? NP : 1];      // VERIFY: stored matrix to compare with, or null
     if constexpr (VERIFY) {
-        // presumed owner of each pair: a stored entry (global id), or none (representative / no slot)
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             uint32_t g = 0xFFFFFFFFu;
@@ -407,28 +488,31 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
                     const uint32_t v = uniform(A.tval[h]);
                     if (v & VAL_SETTLED) {
                         g = v & ~VAL_SETTLED;
-                        // a representative of this level is not compared with itself
-                        if (g >= A.level_base && uniform(A.recipe[g]) == idx[p]) g = 0xFFFFFFFFu;
+                        // the candidate whose matrix is stored is not compared with itself
+                        if (g >= A.level_base) {
+                            const uint32_t src = A.verify_rep
+                                ? uniform(A.recipe[g])
+                                : uniform(A.claimer[uniform(A.store[g]) - A.level_base]);
+                            if (src == idx[p]) g = 0xFFFFFFFFu;
+                        }
                     } else if (v != idx[p]) {
                         g = A.level_base + uniform(rank_of(A.bitmap, A.wordpre, v));
                     }
                 }
             }
-            tgt[p] = g;
+            tp[p] = (g != 0xFFFFFFFFu) ? as_global<T>(arena_addr<T>(A, uniform(A.store[g]))) : (gptr<T>)nullptr;
         }
     }
-    gptr<T> arena = as_global<T>((const T *)A.arena);
     auto load = [&](uint32_t blk, Rowset &L) {
         const uint32_t r = blk * 64u + (uint32_t)lane;
         L.m = load_meta<T, MW, !VERIFY>(A.rows, r, lane);
 #pragma unroll
-        for (int ii = 0; ii < TI; ++ii) L.av[ii] = ap[ii][r];
+        for (int ii = 0; ii < TI; ++ii) L.av[ii] = ldg(ap[ii], r);
 #pragma unroll
-        for (int jj = 0; jj < TJ; ++jj) L.bv[jj] = BIN ? bp[jj][r] : (T)0;
+        for (int jj = 0; jj < TJ; ++jj) L.bv[jj] = BIN ? ldg(bp[jj], r) : (T)0;
         if constexpr (VERIFY) {
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
-                L.tv[p] = (tgt[p] != 0xFFFFFFFFu) ? arena[(size_t)tgt[p] * R + r] : (T)0;
+            for (int p = 0; p < NP; ++p) L.tv[p] = tp[p] ? ldg(tp[p], r) : (T)0;
         }
     };
 
@@ -442,20 +526,16 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
         for (uint32_t blk = rb0; blk < rb1; ++blk) {
             if (blk + 1 < rb1) load(blk + 1, nxt);
             finish_meta<T, MW>(cur.m, lane);
+            T w[NP];
+            tile_words<T, MW, OP, TI, TJ>(cur.av, cur.bv, cur.m, A.rows, lane, w);
 #pragma unroll
-            for (int ii = 0; ii < TI; ++ii)
-#pragma unroll
-                for (int jj = 0; jj < TJ; ++jj) {
-                    const int p = ii * TJ + jj;
-                    T w;
-                    if constexpr (FUSED) w = apply_fused<T, MW>(jj, cur.av[ii], cur.m, A.rows, lane);
-                    else w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
-                    // one word per trace (32-bit layout): every live row is a first word and dead
-                    // rows are zero, so the position-0 bit is masked once, after the loop
-                    if constexpr (!MW && sizeof(T) == 4) viol[p] |= w ^ cur.m.sw;
-                    else viol[p] |= (w ^ cur.m.sw) & cur.m.sm;
-                    fp_add<T>(acc[p], w, cur.m);
-                }
+            for (int p = 0; p < NP; ++p) {
+                // one word per trace (32-bit layout): every live row is a first word and dead
+                // rows are zero, so the position-0 bit is masked once, after the loop
+                if constexpr (!MW && sizeof(T) == 4) viol[p] |= w[p] ^ cur.m.sw;
+                else viol[p] |= (w[p] ^ cur.m.sw) & cur.m.sm;
+                fp_add<T>(acc[p], w[p], cur.m);
+            }
             cur = nxt;
         }
         uint64_t my_fp = 0;
@@ -468,13 +548,48 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
             const bool bad = __ballot(viol[p] != 0) != 0ull;
             if (lane == p) { my_fp = sum; my_idx = idx[p]; my_bad = bad; }
         }
+        uint32_t my_claim = 0xFFFFFFFFu;
         if (my_idx != 0xFFFFFFFFu) {
             if (A.split_mode) {        // partial result of one row chunk
                 atomicAdd(&A.cand_fp[my_idx], (unsigned long long)my_fp);
                 if (my_bad) atomicOr(&A.cand_viol[my_idx >> 5], 1u << (my_idx & 31u));
             } else {
                 if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
-                A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx);
+                A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx, my_claim);
+            }
+        }
+        // claimers' matrices, written while the children are still in cache (whole-row tiles only)
+        if (CW && A.cw && __ballot(my_claim < A.arena_cap) != 0ull) {
+            gptr<T> dp[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const uint32_t cp = (uint32_t)__builtin_amdgcn_readlane((int)my_claim, p);
+                dp[p] = (cp < A.arena_cap) ? as_global<T>(arena_addr<T>(A, A.level_base + cp)) : (gptr<T>)nullptr;
+            }
+            struct RowsetW {
+                RowMeta<T> m;
+                T av[TI], bv[TJ];
+            };
+            auto loadw = [&](uint32_t blk, RowsetW &L) {
+                const uint32_t r = blk * 64u + (uint32_t)lane;
+                L.m = load_meta<T, MW, false>(A.rows, r, lane);
+#pragma unroll
+                for (int ii = 0; ii < TI; ++ii) L.av[ii] = ldg(ap[ii], r);
+#pragma unroll
+                for (int jj = 0; jj < TJ; ++jj) L.bv[jj] = BIN ? ldg(bp[jj], r) : (T)0;
+            };
+            RowsetW cw, nw;
+            loadw(rb0, cw);
+            for (uint32_t blk = rb0; blk < rb1; ++blk) {
+                if (blk + 1 < rb1) loadw(blk + 1, nw);
+                finish_meta<T, MW>(cw.m, lane);
+                T w[NP];
+                tile_words<T, MW, OP, TI, TJ>(cw.av, cw.bv, cw.m, A.rows, lane, w);
+                const uint32_t r = blk * 64u + (uint32_t)lane;
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    if (dp[p]) stg((T *)(uintptr_t)dp[p], r, w[p]);
+                cw = nw;
             }
         }
     } else {
@@ -486,22 +601,15 @@ __device__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uin
         for (uint32_t blk = rb0; blk < rb1; ++blk) {
             if (blk + 1 < rb1) load(blk + 1, nxt);
             finish_meta<T, MW>(cur.m, lane);
+            T w[NP];
+            tile_words<T, MW, OP, TI, TJ>(cur.av, cur.bv, cur.m, A.rows, lane, w);
 #pragma unroll
-            for (int ii = 0; ii < TI; ++ii)
-#pragma unroll
-                for (int jj = 0; jj < TJ; ++jj) {
-                    const int p = ii * TJ + jj;
-                    if (tgt[p] != 0xFFFFFFFFu) {
-                        T w;
-                        if constexpr (FUSED) w = apply_fused<T, MW>(jj, cur.av[ii], cur.m, A.rows, lane);
-                        else w = apply<T, MW, OP>(cur.av[ii], cur.bv[jj], cur.m, A.rows, lane);
-                        diff[p] |= w ^ cur.tv[p];
-                    }
-                }
+            for (int p = 0; p < NP; ++p) diff[p] |= w[p] ^ cur.tv[p];
             cur = nxt;
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
+            if (!tp[p]) continue;
             const bool mism = __ballot(diff[p] != 0) != 0ull;
             if (mism && lane == 0) {
                 const uint32_t bit = 1u << (idx[p] & 31u);
@@ -528,7 +636,7 @@ __device__ __forceinline__ Block uniform_block(const Block &in) {
 enum { CLS_UNARY = 0, CLS_ANDOR = 1, CLS_U = 2, CLS_UC = 3 };
 
 template <typename T, bool MW, bool VERIFY, int CLS>
-__global__ __launch_bounds__(256) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
                                                uint32_t ntiles, uint32_t chunk) {
     const int lane = (int)__lane_id();
     if constexpr (VERIFY) {
@@ -593,18 +701,18 @@ __global__ __launch_bounds__(256) void k_level_all(LevelArgs<T> A, const Block *
         i0 = uniform(i0);
         j0 = uniform(j0);
         switch (b.op) {
-        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
+        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
         case LTL_U:
-            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
-            else run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1);
+            else run_tile<T, MW, LTL_U, TILE, TILE, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1);
             break;
-        default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+        default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY, false>(A, b, i0, j0, lane, rb0, rb1); break;
         }
     }
 }
@@ -615,7 +723,8 @@ __global__ __launch_bounds__(256) void k_probe(LevelArgs<T> A, uint32_t ncand) {
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ncand; x += gridDim.x * blockDim.x) {
         const bool bad = (A.cand_viol[x >> 5] >> (x & 31u)) & 1u;
         if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)x);
-        A.cand_slot[x] = probe_claim<T>(A, finish_fp(A.cand_fp[x], A.fp_mask), x);
+        uint32_t claim;
+        A.cand_slot[x] = probe_claim<T>(A, finish_fp(A.cand_fp[x], A.fp_mask), x, claim);
     }
 }
 
@@ -638,9 +747,8 @@ __device__ __forceinline__ void cand_children(const LevelArgs<T> &A, uint32_t x,
     cand_decode(b, x - b.cand_base, i, j);
     op = (int)b.op;
     if (op == LTL_U && A.ucarry) op = OP_UC;
-    pa = (const T *)b.a_ptr + (size_t)i * A.rows.R;
-    pb = b.nb ? (const T *)b.b_ptr + (size_t)j * A.rows.R : pa;
-    if (b.tri) pb = (const T *)b.b_ptr + (size_t)j * A.rows.R;
+    pa = (const T *)(uintptr_t)child_addr<T>(A, b, 0, i);
+    pb = b.nb ? (const T *)(uintptr_t)child_addr<T>(A, b, 1, j) : pa;
 }
 
 // Writes (or compares) one candidate's matrix, one row block at a time.  The
@@ -679,7 +787,6 @@ __device__ void write_matrix(const LevelArgs<T> &A, const T *pa, const T *pb, T 
     constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
     gptr<T> a = as_global<T>(pa);
     gptr<T> b = as_global<T>(pb);
-    __attribute__((address_space(1))) T *d = (__attribute__((address_space(1))) T *)(uintptr_t)dst;
     for (uint32_t blk = rb0; blk < NB; blk += UNR) {
         RowMeta<T> m[UNR];
         T av[UNR], bv[UNR];
@@ -688,8 +795,8 @@ __device__ void write_matrix(const LevelArgs<T> &A, const T *pa, const T *pb, T 
             if (blk + u < NB) {
                 const uint32_t r = (blk + u) * 64u + (uint32_t)lane;
                 m[u] = load_meta<T, MW, false>(A.rows, r, lane);
-                av[u] = a[r];
-                bv[u] = BIN ? b[r] : (T)0;
+                av[u] = ldg(a, r);
+                bv[u] = BIN ? ldg(b, r) : (T)0;
             }
         }
 #pragma unroll
@@ -697,18 +804,21 @@ __device__ void write_matrix(const LevelArgs<T> &A, const T *pa, const T *pb, T 
             if (blk + u < NB) {
                 const uint32_t r = (blk + u) * 64u + (uint32_t)lane;
                 finish_meta<T, MW>(m[u], lane);
-                d[r] = apply<T, MW, OP>(av[u], bv[u], m[u], A.rows, lane);
+                stg(dst, r, apply<T, MW, OP>(av[u], bv[u], m[u], A.rows, lane));
             }
         }
     }
 }
 
-// New entries of the level: entry e holds the representative recipe[base + e].
-// A work item is one chunk of A.mat_chunk row blocks of one entry.
+// New entries of the level.  Claim order (rep_mode 0): claim q stores the matrix
+// of its claimer at level_base + q.  Representative order (rep_mode 1, the exact
+// re-check after a failed compare): entry e stores the matrix of its
+// representative recipe[base + e] at store[base + e].  A work item is one chunk
+// of A.mat_chunk row blocks of one entry.
 template <typename T, bool MW>
-__global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t n_fixed) {
+__global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t rep_mode) {
     const int lane = (int)__lane_id();
-    const uint32_t n_entries = n_fixed ? n_fixed : uniform(level_new_count(A.ctr, A.arena_cap));
+    const uint32_t n_entries = uniform(level_new_count(A.ctr, A.arena_cap));
     const uint32_t NB = A.rows.NB;
     const uint32_t chunk = A.mat_chunk;
     const uint32_t nchunk = (NB + chunk - 1) / chunk;
@@ -718,14 +828,15 @@ __global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t n_
     for (uint32_t w = wave; w < nwork; w += nwaves) {
         const uint32_t e = w / nchunk, q = w - e * nchunk;
         const uint32_t rb0 = q * chunk, rb1 = min(NB, rb0 + chunk);
-        const uint32_t x = uniform(A.recipe[A.level_base + e]);
+        const uint32_t x = uniform(rep_mode ? A.recipe[A.level_base + e] : A.claimer[e]);
+        const uint32_t pos = rep_mode ? uniform(A.store[A.level_base + e]) : A.level_base + e;
         int op;
         const T *pa, *pb;
         cand_children<T>(A, x, op, pa, pb);
         op = (int)uniform((uint32_t)op);
         pa = (const T *)uniform64((uint64_t)(uintptr_t)pa);
         pb = (const T *)uniform64((uint64_t)(uintptr_t)pb);
-        T *dst = A.arena + (size_t)(A.level_base + e) * A.rows.R;
+        T *dst = (T *)(uintptr_t)arena_addr<T>(A, pos);
         switch (op) {
         case LTL_ATOM: write_matrix<T, MW, LTL_ATOM>(A, pa, pb, dst, lane, rb0, rb1); break;
         case LTL_NOT:  write_matrix<T, MW, LTL_NOT>(A, pa, pb, dst, lane, rb0, rb1); break;
@@ -847,11 +958,12 @@ __global__ __launch_bounds__(256) void k_fallback(LevelArgs<T> A, uint32_t nword
                     int t_op = 0;
                     const T *t_pa = nullptr, *t_pb = nullptr;
                     if (v & VAL_SETTLED) {
-                        target = A.arena + (size_t)(v & ~VAL_SETTLED) * A.rows.R;
+                        target = (const T *)(uintptr_t)arena_addr<T>(A, A.store[v & ~VAL_SETTLED]);
                     } else if ((A.fb_bits[v >> 5] >> (v & 31u)) & 1u) {
                         cand_children<T>(A, v, t_op, t_pa, t_pb);
                     } else {
-                        target = A.arena + (size_t)(A.level_base + rank_of(A.bitmap, A.wordpre, v)) * A.rows.R;
+                        target = (const T *)(uintptr_t)arena_addr<T>(
+                            A, A.store[A.level_base + rank_of(A.bitmap, A.wordpre, v)]);
                     }
                     if (fb_equal<T, MW>(A, target, t_op, t_pa, t_pb, &s_flag, lane, wv, nw)) break;
                 }
@@ -949,16 +1061,18 @@ __device__ __forceinline__ uint32_t level_new_count(const Counters *ctr, uint32_
 // representatives -> recipes (entry order = canonical order of the representative),
 // and settlement of the level's slots: owner index -> global entry id.  The owner
 // of each new slot is recorded (new_owner) for a re-pass after the exact fallback.
+// The matrix of claim i sits at arena position level_base + i (store[]).
 __device__ __forceinline__ void settle_slot(uint32_t i, const uint32_t *new_slots, uint32_t *tval,
                                             const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe,
                                             uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner,
-                                            bool repass) {
+                                            uint32_t *store, bool repass) {
     const uint32_t s = new_slots[i];
     const uint32_t x = repass ? new_owner[i] : tval[s];
     if (!repass) new_owner[i] = x;
     const uint32_t g = level_base + rank_of(bitmap, wordpre, x);
     recipe[g] = x;
     entry_slot[g] = s;
+    store[g] = level_base + i;
     tval[s] = VAL_SETTLED | g;
 }
 
@@ -970,7 +1084,7 @@ constexpr uint32_t SMALL_WORDS = 1024 * SMALL_WPT;
 __global__ __launch_bounds__(1024) void k_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap,
                                                         uint32_t *tval, uint32_t *bitmap, uint32_t nw,
                                                         uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
-                                                        uint32_t *entry_slot, uint32_t *new_owner) {
+                                                        uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store) {
     __shared__ uint32_t s_tmp[16];
     const uint32_t n = level_new_count(ctr, cap);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -996,7 +1110,7 @@ __global__ __launch_bounds__(1024) void k_compact_small(const uint32_t *new_slot
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-        settle_slot(i, new_slots, tval, bitmap, wordpre, recipe, level_base, entry_slot, new_owner, false);
+        settle_slot(i, new_slots, tval, bitmap, wordpre, recipe, level_base, entry_slot, new_owner, store, false);
 }
 
 // slot owners -> representative bits
@@ -1016,10 +1130,11 @@ __global__ void k_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw) {
 
 __global__ void k_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
-                          uint32_t *entry_slot, uint32_t *new_owner, uint32_t repass) {
+                          uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store, uint32_t repass) {
     const uint32_t n = level_new_count(ctr, cap);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        settle_slot(i, new_slots, tval, bitmap, wordpre, recipe, level_base, entry_slot, new_owner, repass != 0);
+        settle_slot(i, new_slots, tval, bitmap, wordpre, recipe, level_base, entry_slot, new_owner, store,
+                    repass != 0);
 }
 
 // return the slots of a finished job to the empty state
@@ -1132,14 +1247,15 @@ hipError_t Launch<T>::probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s
 }
 
 template <typename T>
-hipError_t Launch<T>::materialize(const LevelArgs<T> &A, bool mw, uint32_t n, uint32_t grid, hipStream_t s) {
+hipError_t Launch<T>::materialize(const LevelArgs<T> &A, bool mw, uint32_t rep_mode, uint32_t grid,
+                                  hipStream_t s) {
     if constexpr (sizeof(T) == 8) {
         if (mw) {
-            hipLaunchKernelGGL((k_materialize<T, true>), dim3(grid), dim3(256), 0, s, A, n);
+            hipLaunchKernelGGL((k_materialize<T, true>), dim3(grid), dim3(256), 0, s, A, rep_mode);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_materialize<T, false>), dim3(grid), dim3(256), 0, s, A, n);
+    hipLaunchKernelGGL((k_materialize<T, false>), dim3(grid), dim3(256), 0, s, A, rep_mode);
     return hipGetLastError();
 }
 
@@ -1184,9 +1300,10 @@ hipError_t launch_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t 
 
 hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                                 uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
-                                uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner, hipStream_t s) {
+                                uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store,
+                                hipStream_t s) {
     hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(1024), 0, s, new_slots, ctr, cap, tval, bitmap, nw, wordpre,
-                       recipe, level_base, entry_slot, new_owner);
+                       recipe, level_base, entry_slot, new_owner, store);
     return hipGetLastError();
 }
 
@@ -1198,9 +1315,10 @@ hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipSt
 
 hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
-                          uint32_t *entry_slot, uint32_t *new_owner, bool repass, uint32_t grid, hipStream_t s) {
+                          uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store, bool repass, uint32_t grid,
+                          hipStream_t s) {
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(256), 0, s, new_slots, ctr, cap, tval, bitmap, wordpre, recipe,
-                       level_base, entry_slot, new_owner, repass ? 1u : 0u);
+                       level_base, entry_slot, new_owner, store, repass ? 1u : 0u);
     return hipGetLastError();
 }
 
