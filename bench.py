@@ -8,7 +8,9 @@ cost bound 11, 32-bit words, 2^26 hash slots), seeds 0..7, each solved by
 ltl_learn from a device-resident specification.  The metric is the number of
 canonical candidates evaluated, over the timed wall time.
 
-Prints ONE JSON line (see the design doc for every field).
+Prints ONE JSON line: the metric and its config, per-kernel GPU time (HIP events on
+the library's streams), the roofline of the dominant kernel kind and the CPU oracle
+timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -54,10 +56,14 @@ def parse_seeds(s: str):
     return out
 
 
-# Algorithmic work per candidate, per 32-bit half-word of its matrix ("Roofline"):
-#   connective: NOT 2, AND/OR 1, X 1, F 2, G 5, U (doubling, k steps) 5k-2, ATOM 0
-#   fingerprint 7 (premix 4, multiply-add 3), separation 3
+# Algorithmic work per candidate, per 32-bit half-word of its matrix, in basic 32-bit
+# integer operations:
+#   connective: NOT 2, AND/OR 1, X 1, F 2 (x | -x), G 5, ATOM 0,
+#               U by doubling (App. B, k steps) 5k-2, U by the carry adder 5
+#   fingerprint 5 (premix: two shift-xor pairs; one 32x32->64 multiply-add)
+#   separation 2 (xor with the expected bit, or into the violation word)
 OP_OPS = {"atom": 0, "not": 2, "and": 1, "or": 1, "x": 1, "f": 2, "g": 5}
+FP_SEP_OPS = 5 + 2
 
 
 def main():
@@ -309,7 +315,7 @@ def roofline(ltl, results, geom, ucarry):
             if C == 0:
                 continue
             if c == 1:
-                ops_total += C * halves * (OP_OPS["atom"] + 10)
+                ops_total += C * halves * (OP_OPS["atom"] + FP_SEP_OPS)
             else:
                 x = c - 1
                 un = E[x] if x >= 1 else 0
@@ -319,8 +325,8 @@ def roofline(ltl, results, geom, ucarry):
                     b = x - a
                     ao += E[a] * E[b] if a < b else E[a] * (E[a] - 1) // 2
                 uop = 5 if ucarry else 5 * k - 2
-                per_level_ops = un * (OP_OPS["f"] + OP_OPS["g"] + OP_OPS["x"] + OP_OPS["not"] + 4 * 10) \
-                    + u_pairs * (uop + 10) + ao * (OP_OPS["and"] + OP_OPS["or"] + 2 * 10)
+                per_level_ops = un * (OP_OPS["f"] + OP_OPS["g"] + OP_OPS["x"] + OP_OPS["not"] + 4 * FP_SEP_OPS) \
+                    + u_pairs * (uop + FP_SEP_OPS) + ao * (OP_OPS["and"] + OP_OPS["or"] + 2 * FP_SEP_OPS)
                 ops_total += per_level_ops * halves
             # verify: every non-representative reads its owner's matrix once
             bytes_verify += (C - r.level_new[c]) * cm_bytes

@@ -24,7 +24,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = True, extra=None) -> str:
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # no packed-FP32 instruction selection (device code hygiene)
+           # no packed-FP32 instruction selection: some of its forms are unreliable on this target
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-result",
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),

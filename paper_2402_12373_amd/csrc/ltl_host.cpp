@@ -63,6 +63,8 @@ struct ltl_ctx {
     hipStream_t s = nullptr;
     bool busy = false;
     char *pinned = nullptr;          // page-locked host staging: two block tables + counters
+    char *jpin = nullptr;            // page-locked staging of a job's row tables (grown on demand)
+    uint64_t jpin_bytes = 0;
     uint32_t table_clean_log2 = 0;   // the hash table at the start of the workspace is empty (this size)
 };
 
@@ -113,6 +115,7 @@ struct ltl_job {
     uint32_t *recipe = nullptr;
     uint32_t *entry_slot = nullptr;  // per global entry: its hash slot (to empty the table afterwards)
     uint32_t *store = nullptr;       // per global entry: arena position of its matrix
+    std::vector<uint32_t> recipe_h;  // host copy of recipe[0 .. size) (formula reconstruction)
     uint64_t recipe_cap = 0, max_entries = 0;
     bool table_consistent = true;    // every claimed slot belongs to a finalized entry
     char *arena = nullptr;
@@ -251,6 +254,7 @@ extern "C" int ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out) {
 extern "C" void ltl_ctx_destroy(ltl_ctx *ctx) {
     if (!ctx) return;
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->jpin) (void)hipHostFree(ctx->jpin);
     delete ctx;
 }
 
@@ -327,10 +331,34 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     // kernels address rows of a matrix (and of the row tables) with 32-bit byte offsets
     if (j->cm_bytes >= (1ull << 31) || R * 8ull >= (1ull << 31)) return LTL_E_TOO_LONG;
 
-    // host row metadata
+    // host row metadata, written straight into one page-locked image of the device
+    // row tables: [valid | sepm | sepw (R words each) | nxt (R x 8 B) | keys (R x 4 B per
+    // 32-bit half) | row_trace | row_word (R x 4 B each)], then room for the trace
+    // fingerprints read back
     const uint64_t W = wb;
-    std::vector<uint64_t> valid(R, 0), sepm(R, 0), sepw(R, 0), nxt(R, 0);
-    std::vector<uint32_t> row_trace(R, 0xFFFFFFFFu), row_word(R, 0);
+    const uint32_t nkeys = (wb == 64) ? 2u : 1u;
+    const uint64_t o_valid = 0, o_sepm = R * j->wbytes, o_sepw = 2 * R * j->wbytes, o_nxt = 3 * R * j->wbytes;
+    const uint64_t o_key = o_nxt + R * 8, o_rtr = o_key + R * 4 * nkeys, o_rwd = o_rtr + R * 4;
+    const uint64_t tables_bytes = o_rwd + R * 4;
+    const uint64_t o_tfp = align_up(tables_bytes, 256);
+    const uint64_t jpin_need = o_tfp + (uint64_t)T * 8;
+    if (c->jpin_bytes < jpin_need) {
+        if (c->jpin) (void)hipHostFree(c->jpin);
+        c->jpin = nullptr;
+        c->jpin_bytes = 0;
+        if (hipHostMalloc((void **)&c->jpin, jpin_need, hipHostMallocDefault) != hipSuccess) return LTL_E_DEVICE;
+        c->jpin_bytes = jpin_need;
+    }
+    char *img = c->jpin;
+    memset(img, 0, tables_bytes);
+    uint32_t *row_trace = (uint32_t *)(img + o_rtr);
+    uint32_t *row_word = (uint32_t *)(img + o_rwd);
+    uint64_t *nxt = (uint64_t *)(img + o_nxt);
+    for (uint64_t rr = 0; rr < R; ++rr) row_trace[rr] = 0xFFFFFFFFu;
+    auto put = [&](uint64_t off, uint64_t row, uint64_t v) {
+        if (wb == 64) ((uint64_t *)(img + off))[row] = v;
+        else ((uint32_t *)(img + off))[row] = (uint32_t)v;
+    };
     const uint64_t full = (wb == 64) ? ~0ull : 0xFFFFFFFFull;
     const uint64_t msb = 1ull << (wb - 1);
     for (uint32_t t = 0; t < T; ++t) {
@@ -338,9 +366,9 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
         for (uint32_t w = 0; w < j->nwords[t]; ++w) {
             const uint64_t row = j->row0[t] + w;
             const uint64_t n = std::min<uint64_t>(W, len - (uint64_t)w * W);
-            valid[row] = (n == W) ? full : ((full << (W - n)) & full);
-            sepm[row] = (w == 0) ? msb : 0;
-            sepw[row] = (w == 0 && t < j->npos) ? msb : 0;
+            put(o_valid, row, (n == W) ? full : ((full << (W - n)) & full));
+            put(o_sepm, row, (w == 0) ? msb : 0);
+            put(o_sepw, row, (w == 0 && t < j->npos) ? msb : 0);
             const uint32_t later = j->nwords[t] - 1 - w;
             const uint32_t lane = (uint32_t)(row & 63u);
             nxt[row] = later ? (((later == 64 ? 0ull : (1ull << later)) - 1ull) << (lane + 1)) : 0ull;
@@ -348,10 +376,11 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
             row_word[row] = w;
         }
     }
-    const uint32_t nkeys = (wb == 64) ? 2u : 1u;
-    std::vector<uint32_t> keys((size_t)R * nkeys);
-    uint64_t seed = 0x5eed1e55c0ffee11ull;
-    for (auto &kk : keys) kk = (uint32_t)(splitmix64(seed) >> 32) | 1u;
+    {
+        uint32_t *keys = (uint32_t *)(img + o_key);
+        uint64_t seed = 0x5eed1e55c0ffee11ull;
+        for (uint64_t q = 0; q < R * nkeys; ++q) keys[q] = (uint32_t)(splitmix64(seed) >> 32) | 1u;
+    }
 
     // workspace carve: the language-cache hash table first (12 bytes per slot), at
     // a fixed place so that a context can hand an emptied table to its next job
@@ -373,13 +402,16 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
 
     char *upload = (char *)ws_take(j, UPLOAD_BYTES);   // counters, then the level's block tables
     j->ctr = (Counters *)upload;
-    j->valid = ws_take(j, R * j->wbytes);
-    j->sepm = ws_take(j, R * j->wbytes);
-    j->sepw = ws_take(j, R * j->wbytes);
-    j->nxt = (uint64_t *)ws_take(j, R * 8);
-    j->key = (uint32_t *)ws_take(j, R * 4 * nkeys);
-    j->row_trace = (uint32_t *)ws_take(j, R * 4);
-    j->row_word = (uint32_t *)ws_take(j, R * 4);
+    char *tables = (char *)ws_take(j, tables_bytes);
+    if (tables) {
+        j->valid = tables + o_valid;
+        j->sepm = tables + o_sepm;
+        j->sepw = tables + o_sepw;
+        j->nxt = (uint64_t *)(tables + o_nxt);
+        j->key = (uint32_t *)(tables + o_key);
+        j->row_trace = (uint32_t *)(tables + o_rtr);
+        j->row_word = (uint32_t *)(tables + o_rwd);
+    }
     j->atoms = ws_take(j, (uint64_t)j->A * R * j->wbytes);
     j->tfp = (uint64_t *)ws_take(j, (uint64_t)T * 8);
     j->blocks_d = upload ? (Block *)(upload + 256) : nullptr;
@@ -398,21 +430,8 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     if ((uint64_t)(j->arena - j->ws) >= j->wsb) return LTL_E_OOM;
     j->arena_region = j->wsb - (uint64_t)(j->arena - j->ws);
 
-    // uploads
-    std::vector<uint32_t> v32;
-    auto up_words = [&](void *dst, const std::vector<uint64_t> &src) -> hipError_t {
-        if (wb == 64) return hipMemcpyAsync(dst, src.data(), R * 8, hipMemcpyHostToDevice, j->s);
-        v32.resize(R);
-        for (uint64_t i = 0; i < R; ++i) v32[i] = (uint32_t)src[i];
-        return hipMemcpy(dst, v32.data(), R * 4, hipMemcpyHostToDevice);
-    };
-    HIP_TRY(up_words(j->valid, valid));
-    HIP_TRY(up_words(j->sepm, sepm));
-    HIP_TRY(up_words(j->sepw, sepw));
-    HIP_TRY(hipMemcpyAsync(j->nxt, nxt.data(), R * 8, hipMemcpyHostToDevice, j->s));
-    HIP_TRY(hipMemcpy(j->key, keys.data(), keys.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpyAsync(j->row_trace, row_trace.data(), R * 4, hipMemcpyHostToDevice, j->s));
-    HIP_TRY(hipMemcpyAsync(j->row_word, row_word.data(), R * 4, hipMemcpyHostToDevice, j->s));
+    // uploads: the row tables in one copy
+    HIP_TRY(hipMemcpyAsync(tables, img, tables_bytes, hipMemcpyHostToDevice, j->s));
     if (!(spec->flags & LTL_SPEC_DEVICE)) {
         HIP_TRY(hipMemcpyAsync(j->letters_d, spec->letters, j->TB * 4, hipMemcpyHostToDevice, j->s));
         HIP_TRY(hipMemcpyAsync(j->offsets_d, spec->offsets, ((uint64_t)T + 1) * 8, hipMemcpyHostToDevice, j->s));
@@ -430,14 +449,14 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
                                            (uint32_t *)j->atoms, j->ctr, j->s));
         HIP_TRY(launch_trace_fp(j->letters_d, j->offsets_d, T, j->tfp, j->s));
     }
+    const uint64_t *tf = (const uint64_t *)(img + o_tfp);
+    HIP_TRY(hipMemcpyAsync((void *)tf, j->tfp, (uint64_t)T * 8, hipMemcpyDeviceToHost, j->s));
     Counters hc;
-    if (int e = sync_read_counters(j, &hc)) return e;
+    if (int e = sync_read_counters(j, &hc)) return e;     // also waits for the fingerprints
     collect_times(j);
     if (j->A < 32 && (hc.letter_or >> j->A)) return LTL_E_INVAL;      // a letter names a missing proposition
 
     // P and N must be disjoint (Sec. 2): equal fingerprints are compared exactly
-    std::vector<uint64_t> tf(T);
-    HIP_TRY(hipMemcpy(tf.data(), j->tfp, (uint64_t)T * 8, hipMemcpyDeviceToHost));
     std::unordered_multimap<uint64_t, uint32_t> pos;
     pos.reserve(j->npos * 2 + 1);
     for (uint32_t t = 0; t < j->npos; ++t) pos.emplace(tf[t], t);
@@ -960,13 +979,21 @@ static void host_cand_decode(const Block &b, uint32_t l, uint32_t &i, uint32_t &
 static int emit_candidate(ltl_job *j, uint32_t level, uint32_t x, ltl_node *buf, uint32_t cap, uint32_t &n,
                           uint32_t &root);
 
+// Host copy of the recipes of entries [0, upto), extended by one bulk copy.
+static int host_recipes(ltl_job *j, uint64_t upto) {
+    const uint64_t have = j->recipe_h.size();
+    if (upto <= have) return LTL_OK;
+    j->recipe_h.resize(upto);
+    HIP_TRY(hipMemcpy(j->recipe_h.data() + have, j->recipe + have, (upto - have) * 4, hipMemcpyDeviceToHost));
+    return LTL_OK;
+}
+
 static int emit_entry(ltl_job *j, uint32_t level, uint32_t e, ltl_node *buf, uint32_t cap, uint32_t &n,
                       uint32_t &root) {
     const LevelInfo &lv = j->L[level];
     if (e >= lv.n) return LTL_E_INVAL;
-    uint32_t x = 0;
-    HIP_TRY(hipMemcpy(&x, j->recipe + lv.gid_base + e, 4, hipMemcpyDeviceToHost));
-    return emit_candidate(j, level, x, buf, cap, n, root);
+    if (int st = host_recipes(j, (uint64_t)lv.gid_base + lv.n)) return st;
+    return emit_candidate(j, level, j->recipe_h[lv.gid_base + e], buf, cap, n, root);
 }
 
 static int emit_candidate(ltl_job *j, uint32_t level, uint32_t x, ltl_node *buf, uint32_t cap, uint32_t &n,

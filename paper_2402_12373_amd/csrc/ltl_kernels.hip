@@ -39,6 +39,11 @@ namespace ltl {
 
 constexpr int OP_UC = 8;   // U computed by the carry-chain adder
 
+// Row blocks of operands in flight per evaluation wave (a tuning constant)
+#ifndef LTL_EVAL_PIPE
+#define LTL_EVAL_PIPE 2
+#endif
+
 template <typename T> struct Word;
 template <> struct Word<uint32_t> { static constexpr int BITS = 32; };
 template <> struct Word<uint64_t> { static constexpr int BITS = 64; };
@@ -516,27 +521,42 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
         }
     };
 
+    // row blocks are streamed PIPE at a time, the next PIPE loaded while the current
+    // ones are computed
+    constexpr int PIPE = VERIFY ? 1 : LTL_EVAL_PIPE;
+    auto load_group = [&](uint32_t blk, Rowset (&L)[PIPE]) {
+#pragma unroll
+        for (int u = 0; u < PIPE; ++u)
+            if (blk + u < rb1) load(blk + u, L[u]);
+    };
+
     if constexpr (!VERIFY) {
         uint64_t acc[NP];
         T viol[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) { acc[p] = 0; viol[p] = 0; }
-        Rowset cur, nxt;
-        load(rb0, cur);
-        for (uint32_t blk = rb0; blk < rb1; ++blk) {
-            if (blk + 1 < rb1) load(blk + 1, nxt);
-            finish_meta<T, MW>(cur.m, lane);
-            T w[NP];
-            tile_words<T, MW, OP, TI, TJ>(cur.av, cur.bv, cur.m, A.rows, lane, w);
+        Rowset cur[PIPE], nxt[PIPE];
+        load_group(rb0, cur);
+        for (uint32_t blk = rb0; blk < rb1; blk += PIPE) {
+            if (blk + PIPE < rb1) load_group(blk + PIPE, nxt);
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                // one word per trace (32-bit layout): every live row is a first word and dead
-                // rows are zero, so the position-0 bit is masked once, after the loop
-                if constexpr (!MW && sizeof(T) == 4) viol[p] |= w[p] ^ cur.m.sw;
-                else viol[p] |= (w[p] ^ cur.m.sw) & cur.m.sm;
-                fp_add<T>(acc[p], w[p], cur.m);
+            for (int u = 0; u < PIPE; ++u) {
+                if (blk + u < rb1) {
+                    finish_meta<T, MW>(cur[u].m, lane);
+                    T w[NP];
+                    tile_words<T, MW, OP, TI, TJ>(cur[u].av, cur[u].bv, cur[u].m, A.rows, lane, w);
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        // one word per trace (32-bit layout): every live row is a first word and
+                        // dead rows are zero, so the position-0 bit is masked once, after the loop
+                        if constexpr (!MW && sizeof(T) == 4) viol[p] |= w[p] ^ cur[u].m.sw;
+                        else viol[p] |= (w[p] ^ cur[u].m.sw) & cur[u].m.sm;
+                        fp_add<T>(acc[p], w[p], cur[u].m);
+                    }
+                }
             }
-            cur = nxt;
+#pragma unroll
+            for (int u = 0; u < PIPE; ++u) cur[u] = nxt[u];
         }
         uint64_t my_fp = 0;
         uint32_t my_idx = 0xFFFFFFFFu;
@@ -566,46 +586,60 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                 const uint32_t cp = (uint32_t)__builtin_amdgcn_readlane((int)my_claim, p);
                 dp[p] = (cp < A.arena_cap) ? as_global<T>(arena_addr<T>(A, A.level_base + cp)) : (gptr<T>)nullptr;
             }
+            // a memory-bound pass (children re-read, new matrices written): several row
+            // blocks of loads in flight per wave
+            constexpr int UNR = 4;
             struct RowsetW {
                 RowMeta<T> m;
                 T av[TI], bv[TJ];
             };
-            auto loadw = [&](uint32_t blk, RowsetW &L) {
-                const uint32_t r = blk * 64u + (uint32_t)lane;
-                L.m = load_meta<T, MW, false>(A.rows, r, lane);
+            for (uint32_t blk = rb0; blk < rb1; blk += UNR) {
+                RowsetW L[UNR];
 #pragma unroll
-                for (int ii = 0; ii < TI; ++ii) L.av[ii] = ldg(ap[ii], r);
+                for (int u = 0; u < UNR; ++u) {
+                    if (blk + u < rb1) {
+                        const uint32_t r = (blk + u) * 64u + (uint32_t)lane;
+                        L[u].m = load_meta<T, MW, false>(A.rows, r, lane);
 #pragma unroll
-                for (int jj = 0; jj < TJ; ++jj) L.bv[jj] = BIN ? ldg(bp[jj], r) : (T)0;
-            };
-            RowsetW cw, nw;
-            loadw(rb0, cw);
-            for (uint32_t blk = rb0; blk < rb1; ++blk) {
-                if (blk + 1 < rb1) loadw(blk + 1, nw);
-                finish_meta<T, MW>(cw.m, lane);
-                T w[NP];
-                tile_words<T, MW, OP, TI, TJ>(cw.av, cw.bv, cw.m, A.rows, lane, w);
-                const uint32_t r = blk * 64u + (uint32_t)lane;
+                        for (int ii = 0; ii < TI; ++ii) L[u].av[ii] = ldg(ap[ii], r);
 #pragma unroll
-                for (int p = 0; p < NP; ++p)
-                    if (dp[p]) stg((T *)(uintptr_t)dp[p], r, w[p]);
-                cw = nw;
+                        for (int jj = 0; jj < TJ; ++jj) L[u].bv[jj] = BIN ? ldg(bp[jj], r) : (T)0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    if (blk + u < rb1) {
+                        finish_meta<T, MW>(L[u].m, lane);
+                        T w[NP];
+                        tile_words<T, MW, OP, TI, TJ>(L[u].av, L[u].bv, L[u].m, A.rows, lane, w);
+                        const uint32_t r = (blk + u) * 64u + (uint32_t)lane;
+#pragma unroll
+                        for (int p = 0; p < NP; ++p)
+                            if (dp[p]) stg((T *)(uintptr_t)dp[p], r, w[p]);
+                    }
+                }
             }
         }
     } else {
         T diff[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) diff[p] = 0;
-        Rowset cur, nxt;
-        load(rb0, cur);
-        for (uint32_t blk = rb0; blk < rb1; ++blk) {
-            if (blk + 1 < rb1) load(blk + 1, nxt);
-            finish_meta<T, MW>(cur.m, lane);
-            T w[NP];
-            tile_words<T, MW, OP, TI, TJ>(cur.av, cur.bv, cur.m, A.rows, lane, w);
+        Rowset cur[PIPE], nxt[PIPE];
+        load_group(rb0, cur);
+        for (uint32_t blk = rb0; blk < rb1; blk += PIPE) {
+            if (blk + PIPE < rb1) load_group(blk + PIPE, nxt);
 #pragma unroll
-            for (int p = 0; p < NP; ++p) diff[p] |= w[p] ^ cur.tv[p];
-            cur = nxt;
+            for (int u = 0; u < PIPE; ++u) {
+                if (blk + u < rb1) {
+                    finish_meta<T, MW>(cur[u].m, lane);
+                    T w[NP];
+                    tile_words<T, MW, OP, TI, TJ>(cur[u].av, cur[u].bv, cur[u].m, A.rows, lane, w);
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) diff[p] |= w[p] ^ cur[u].tv[p];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PIPE; ++u) cur[u] = nxt[u];
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {

@@ -17,7 +17,7 @@ Paper context:
     class of a trace is tr |= phi_planted, so phi_planted separates (P, N) and
     the minimal cost is at most size(phi_planted).
 
-Readings (also listed in the design doc):
+Readings of the workload descriptions:
   * ranges "[lo, hi]" of the workload descriptions are inclusive;
   * the planted formula is uniform over syntax trees with exactly `size` nodes
     over {not, and, or, X, F, G, U} and atoms uniform over the propositions;
@@ -277,7 +277,7 @@ def planted_instance(seed: int, num_props: int, k: int, lo: int, hi: int, p: flo
 
 # Workload presets: (props, k per class, len lo, len hi, Bernoulli p, planted size,
 # cost bound, word bits).  "tiny", "scale" and "long" are the plain-method
-# workloads; sizes as described in the design doc.
+# workloads.
 PRESETS = {
     "tiny":  dict(num_props=2, k=16,   lo=4,  hi=8,   p=0.5, size=5,  bound=7,  word_bits=32),
     "scale": dict(num_props=3, k=1024, lo=16, hi=32,  p=0.5, size=9,  bound=11, word_bits=32),
