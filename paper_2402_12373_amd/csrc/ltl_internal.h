@@ -123,7 +123,7 @@ hipError_t launch_mark(const uint32_t *new_slots, const Counters *ctr, uint32_t 
                        uint32_t *bitmap, uint32_t grid, hipStream_t s);
 hipError_t launch_or_bits(uint32_t *dst, const uint32_t *src, uint32_t nw, hipStream_t s);
 // mark + scan + scatter in one workgroup, for levels with at most SMALL_COMPACT_WORDS bitmap words
-constexpr uint32_t SMALL_COMPACT_WORDS = 512;
+constexpr uint32_t SMALL_COMPACT_WORDS = 128;
 hipError_t launch_compact_small(const uint32_t *new_slots, const Counters *ctr, uint32_t cap, uint32_t *tval,
                                 uint32_t *bitmap, uint32_t nw, uint32_t *wordpre, uint32_t *recipe,
                                 uint32_t level_base, uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store,
