@@ -33,14 +33,18 @@ namespace {
 
 constexpr int ORDER[7] = {LTL_F, LTL_U, LTL_G, LTL_X, LTL_AND, LTL_OR, LTL_NOT};   // Sec. 3 listing
 constexpr uint32_t MAX_GRID = 8192;
-// A level whose tiles give fewer waves than this is evaluated row-split: waves
-// take chunks of row blocks, so that small levels are not one long chain of
-// dependent row-block loads.
+// Row-split levels: the number of waves their row chunks aim for.
 constexpr uint64_t TARGET_WAVES = 8192;
+// Levels with fewer tiles than this are row-split (waves take chunks of row
+// blocks), so that small levels are not one long chain of dependent row-block
+// loads per wave (a tuning constant).
+#ifndef LTL_SPLIT_TILES
+#define LTL_SPLIT_TILES 8192
+#endif
+constexpr uint64_t SPLIT_TILES = LTL_SPLIT_TILES;
 constexpr uint64_t MIN_CHUNK = 4;        // row blocks per work item at least (per-item fixed cost)
-// pinned staging: [blocks canonical | blocks by class | counters in | counters out]
-// per-level upload, one copy: [counters init (256 B) | canonical blocks | blocks by class]
-// [counters init | canonical blocks | blocks by class | all blocks, one tile numbering]
+// per-level upload, one copy: [counters init (256 B) | canonical blocks | blocks by
+// class | all blocks, one tile numbering]
 constexpr uint64_t UPLOAD_BYTES = 256 + 3 * sizeof(Block) * MAX_BLOCKS;
 // pinned staging: the upload image, then 256 B for the counters read back
 constexpr uint64_t PINNED_BYTES = UPLOAD_BYTES + 256;
@@ -664,10 +668,10 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         return j->ws + top;
     };
     const uint64_t nwa = align_up(nw, 64);                 // words, so the bitmaps stay aligned
-    const bool split = ntiles < TARGET_WAVES;
-    // bitmap | coll_bits | fb_bits | cand_viol | cand_fp (split levels), cleared at once
-    const uint64_t clear_bytes = nwa * 4 * 4 + (split ? (uint64_t)nc * 8 : 0);
-    uint32_t *bits3 = (uint32_t *)take_top(align_up(nwa * 4 * 4 + (uint64_t)nc * 8, 256));
+    const bool split = ntiles < SPLIT_TILES;
+    // bitmap | coll_bits | fb_bits, cleared at once
+    const uint64_t clear_bytes = nwa * 4 * 3;
+    uint32_t *bits3 = (uint32_t *)take_top(align_up(clear_bytes, 256));
     uint32_t *cand_slot = (uint32_t *)take_top((uint64_t)nc * 4);
     uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
@@ -680,8 +684,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !claimer || !new_owner || !stage ||
         arena_off + arena_used > top)
         return LTL_E_OOM;
-    uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
-    unsigned long long *cand_fp = (unsigned long long *)(bits3 + 4 * nwa);
+    uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa;
     const uint64_t arena_free = top - (arena_off + arena_used);
     const uint32_t arena_cap = (uint32_t)std::min<uint64_t>(
         {arena_free / j->cm_bytes, j->recipe_cap - j->total_entries, (uint64_t)new_cap});
@@ -735,8 +738,8 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     cls_first[4] = (uint32_t)grouped.size();
     memcpy(pin_grouped, grouped.data(), sizeof(Block) * grouped.size());
-    // small levels evaluate (and verify) every class in one dispatch: one tile numbering over the grouped blocks
-    const bool merged_eval = split && !j->mw;
+    // row-split levels evaluate (and verify) every class in one dispatch: one tile numbering over the grouped blocks
+    const bool merged_eval = split;
     Block *pin_all = pin_grouped + grouped.size();
     uint32_t all_tiles = 0;
     if (merged_eval) {
@@ -778,16 +781,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.level_base = lv.gid_base;
     A.recipe = j->recipe;
     A.store = j->store;
-    // whole-row tiles write the claimers' matrices in the evaluation pass; row-split
-    // levels (partial fingerprints, claims made by k_probe) write them in k_materialize
-    A.cw = split ? 0u : 1u;
+    // the evaluation pass writes the claimers' matrices (row-split levels: each wave its rows)
+    A.cw = 1u;
     A.verify_rep = 0;
     A.stage = stage;
     A.arena_cap = arena_cap;
     A.ucarry = ucarry ? 1 : 0;
-    A.split_mode = split ? 1u : 0u;
-    A.cand_fp = cand_fp;
-    A.cand_viol = cand_viol;
     {   // materialize work items: entries x row chunks (sized on the candidate count, an upper bound)
         const uint64_t per = std::max<uint64_t>(
             1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max<uint64_t>(1, new_cap)));
@@ -795,15 +794,15 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     auto launch_level = [&](bool verify) -> hipError_t {
         if (merged_eval) {
+            if (!verify)
+                return Launch<T>::level_wg(A, j->mw, all_d, (uint32_t)grouped.size(), all_tiles,
+                                           std::min<uint32_t>(all_tiles, (uint32_t)MAX_GRID), j->s);
             const uint64_t per = std::max<uint64_t>(
                 1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max(1u, all_tiles)));
             const uint32_t chunk = (uint32_t)((j->NB + per - 1) / per);
             const uint64_t nchunk = (j->NB + chunk - 1) / chunk;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)all_tiles * nchunk + 3) / 4, MAX_GRID);
-            hipError_t e = Launch<T>::level_all(A, j->mw, verify, all_d, (uint32_t)grouped.size(), all_tiles, chunk,
-                                                grid, j->s);
-            if (e != hipSuccess || verify) return e;
-            return Launch<T>::probe(A, nc, j->s);
+            return Launch<T>::verify_all(A, j->mw, all_d, (uint32_t)grouped.size(), all_tiles, chunk, grid, j->s);
         }
         for (int k = 0; k < 4; ++k) {
             if (!cls_tiles[k]) continue;
@@ -818,7 +817,6 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
                                             cls_first[k + 1] - cls_first[k], cls_tiles[k], chunk, grid, j->s);
             if (e != hipSuccess) return e;
         }
-        if (!verify && split) return Launch<T>::probe(A, nc, j->s);
         return hipSuccess;
     };
     // kernels after the evaluation read the level's new-entry count on the device
@@ -829,7 +827,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t ncls = 0;
     for (int k = 0; k < 4; ++k) ncls += cls_tiles[k] ? 1u : 0u;
     {
-        Timer tm(j, LTL_K_EVAL, merged_eval ? 2u : ncls + (split ? 1u : 0u));
+        Timer tm(j, LTL_K_EVAL, merged_eval ? 1u : ncls);
         HIP_TRY(launch_level(false));
     }
     {
@@ -843,10 +841,6 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
                                    j->entry_slot, new_owner, j->store, false, grid_new, j->s));
         }
-    }
-    if (split) {
-        Timer tm(j, LTL_K_MATERIALIZE);
-        HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
     }
     {
         Timer tm(j, LTL_K_VERIFY, merged_eval ? 1u : ncls);

@@ -84,18 +84,12 @@ struct LevelArgs {
     uint32_t *recipe;        // per global entry: canonical candidate index in its level
     uint32_t *store;         // per global entry: arena position of its matrix (claim order
                              // within the level: position level_base + claim number)
-    uint32_t cw;             // the evaluation pass writes each claimer's matrix (whole-row tiles)
+    uint32_t cw;             // the evaluation pass writes each claimer's matrix
     uint32_t verify_rep;     // verify against the representative (exact re-check) instead of
                              // against the claimer
     T *stage;                // R words of scratch for the fallback
     uint32_t arena_cap;      // new entries the arena can take this level
     int ucarry;
-    // Row-split evaluation of small levels: a wave takes one chunk of row blocks of
-    // a tile; fingerprint sums (order-free, mod 2^64) and separation violations are
-    // combined per candidate, and k_probe claims the cache slots afterwards.
-    uint32_t split_mode;
-    unsigned long long *cand_fp;   // per candidate: sum of partial fingerprints
-    uint32_t *cand_viol;           // per candidate: separation violated (bit)
     uint32_t mat_chunk;            // row blocks per materialize work item
 };
 
@@ -105,10 +99,13 @@ struct Launch {
     // cls: 0 unary, 1 and/or, 2 until (doubling), 3 until (carry adder)
     static hipError_t level(const LevelArgs<T> &A, bool mw, bool verify, int cls, const Block *blocks,
                             uint32_t nblocks, uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
-    static hipError_t probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
-    // every connective class in one dispatch (small row-split levels)
-    static hipError_t level_all(const LevelArgs<T> &A, bool mw, bool verify, const Block *blocks, uint32_t nblocks,
-                                uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
+    // row-split levels, every connective class in one dispatch: evaluation with one
+    // workgroup per tile (claims and claimers' matrices included) ...
+    static hipError_t level_wg(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
+                               uint32_t ntiles, uint32_t grid, hipStream_t s);
+    // ... and verification with one wave per (tile, row chunk)
+    static hipError_t verify_all(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
+                                 uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
     // rep_mode 0: claim order, matrix of each claimer at level_base + claim number;
     // rep_mode 1: matrix of each entry's representative at store[entry]
     static hipError_t materialize(const LevelArgs<T> &A, bool mw, uint32_t rep_mode, uint32_t grid, hipStream_t s);

@@ -448,9 +448,21 @@ __device__ __forceinline__ uint64_t arena_addr(const LevelArgs<T> &A, uint32_t p
     return (uint64_t)(uintptr_t)A.arena + (uint64_t)pos * A.rows.R * sizeof(T);
 }
 
-template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY, bool CW = true>
-__device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane, uint32_t rb0,
-                         uint32_t rb1) {
+// Row-split tiles (small levels): the waves of one workgroup take the row chunks
+// of one tile and combine their partial fingerprints and separation flags here.
+constexpr int WG_WAVES = 8;
+struct WgShare {
+    unsigned long long fp[WG_WAVES][16];
+    uint32_t bad[WG_WAVES][16];
+    uint32_t claim[16];
+};
+
+// EVAL with WG: rows [rb0, rb1) are this wave's chunk of the tile; wave 0 of the
+// workgroup claims the slots, then every wave writes its chunk of each claimer.
+template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY, bool CW = true, bool WG = false>
+__device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane,
+                                         uint32_t rb0, uint32_t rb1, WgShare *sh = nullptr, uint32_t wv = 0,
+                                         uint32_t nwv = 1) {
     constexpr int NP = TI * TJ;
     constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U || OP == OP_UC);
     constexpr bool FUSED = (OP == (int)OP_FUSED4);
@@ -523,7 +535,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
 
     // row blocks are streamed PIPE at a time, the next PIPE loaded while the current
     // ones are computed
-    constexpr int PIPE = VERIFY ? 1 : LTL_EVAL_PIPE;
+    constexpr int PIPE = (VERIFY || WG) ? 1 : LTL_EVAL_PIPE;
     auto load_group = [&](uint32_t blk, Rowset (&L)[PIPE]) {
 #pragma unroll
         for (int u = 0; u < PIPE; ++u)
@@ -569,17 +581,36 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
             if (lane == p) { my_fp = sum; my_idx = idx[p]; my_bad = bad; }
         }
         uint32_t my_claim = 0xFFFFFFFFu;
-        if (my_idx != 0xFFFFFFFFu) {
-            if (A.split_mode) {        // partial result of one row chunk
-                atomicAdd(&A.cand_fp[my_idx], (unsigned long long)my_fp);
-                if (my_bad) atomicOr(&A.cand_viol[my_idx >> 5], 1u << (my_idx & 31u));
-            } else {
-                if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
-                A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx, my_claim);
+        if constexpr (WG) {
+            // partial results of this wave's row chunk -> wave 0 claims for the tile
+            if (lane < NP) {
+                sh->fp[wv][lane] = my_fp;
+                sh->bad[wv][lane] = my_bad ? 1u : 0u;
             }
+            __syncthreads();
+            if (wv == 0 && lane < NP) {
+                uint32_t claim = 0xFFFFFFFFu;
+                if (my_idx != 0xFFFFFFFFu) {
+                    uint64_t fp = 0;
+                    uint32_t bad = 0;
+                    for (uint32_t w = 0; w < nwv; ++w) {
+                        fp += sh->fp[w][lane];
+                        bad |= sh->bad[w][lane];
+                    }
+                    if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
+                    A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(fp, A.fp_mask), my_idx, claim);
+                }
+                sh->claim[lane] = claim;
+            }
+            __syncthreads();
+            if (lane < NP) my_claim = sh->claim[lane];
+            __syncthreads();   // the shared block is free for the next tile
+        } else if (my_idx != 0xFFFFFFFFu) {
+            if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
+            A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx, my_claim);
         }
-        // claimers' matrices, written while the children are still in cache (whole-row tiles only)
-        if (CW && A.cw && __ballot(my_claim < A.arena_cap) != 0ull) {
+        // claimers' matrices, written while the children are still in cache
+        if (CW && (WG || A.cw) && __ballot(my_claim < A.arena_cap) != 0ull) {
             gptr<T> dp[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
@@ -710,9 +741,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
 }
 
-// All connective classes in one dispatch (row-split small levels, where the
-// number of dispatches, not occupancy, bounds the level): blocks of every
-// class, one tile numbering, one chunk size.
+// Verification of a row-split level, all connective classes in one dispatch
+// (small levels, where the number of dispatches, not occupancy, bounds the
+// level): blocks of every class, one tile numbering, one row chunk per wave.
 template <typename T, bool MW, bool VERIFY>
 __global__ __launch_bounds__(256) void k_level_all(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
                                                    uint32_t ntiles, uint32_t chunk) {
@@ -751,14 +782,44 @@ __global__ __launch_bounds__(256) void k_level_all(LevelArgs<T> A, const Block *
     }
 }
 
-// Row-split levels: combine the partial results and claim cache slots.
-template <typename T>
-__global__ __launch_bounds__(256) void k_probe(LevelArgs<T> A, uint32_t ncand) {
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ncand; x += gridDim.x * blockDim.x) {
-        const bool bad = (A.cand_viol[x >> 5] >> (x & 31u)) & 1u;
-        if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)x);
-        uint32_t claim;
-        A.cand_slot[x] = probe_claim<T>(A, finish_fp(A.cand_fp[x], A.fp_mask), x, claim);
+// Row-split levels, every connective class in one dispatch: one workgroup of
+// WG_WAVES waves per tile, each wave a chunk of the row blocks; the tile's slots
+// are claimed and its claimers' matrices written in the same dispatch.
+// Multi-word rows need more registers per wave: half as many waves per tile.
+template <bool MW> constexpr int wg_waves() { return MW ? WG_WAVES / 2 : WG_WAVES; }
+
+template <typename T, bool MW>
+__global__ __launch_bounds__(64 * wg_waves<MW>()) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+void k_level_wg(LevelArgs<T> A, const Block *blocks,
+                                                                  uint32_t nblocks, uint32_t ntiles) {
+    __shared__ WgShare sh;
+    const int lane = (int)__lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    const uint32_t nwv = blockDim.x >> 6;
+    const uint32_t NB = A.rows.NB;
+    const uint32_t chunk = (NB + nwv - 1) / nwv;
+    const uint32_t rb0 = min(NB, wv * chunk), rb1 = min(NB, rb0 + chunk);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int bi = (int)uniform((uint32_t)find_block_tile(blocks, (int)nblocks, t));
+        const Block b = uniform_block(blocks[bi]);
+        uint32_t i0, j0;
+        decode_tile(b, t - b.tile_base, i0, j0);
+        i0 = uniform(i0);
+        j0 = uniform(j0);
+        switch (b.op) {
+        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_U:
+            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv);
+            else run_tile<T, MW, LTL_U, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv);
+            break;
+        default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        }
     }
 }
 
@@ -1192,29 +1253,41 @@ __global__ void k_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t 
 }
 
 // Atom matrices: bit (W-1-i) of word w of trace t for proposition p is p in tr_t[w*W + i].
+// One thread per (row, bit): the W threads of a row read W consecutive letters
+// (coalesced), and each proposition's word is one wave ballot, bit-reversed so
+// that position 0 lands in the most significant bit.  Dead rows get zero words.
 template <typename T>
-__global__ void k_pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
-                       const uint32_t *row_word, uint32_t R, uint32_t nprops, T *atoms, Counters *ctr) {
-    constexpr int BITS = Word<T>::BITS;
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const uint32_t t = row_trace[r];
-    if (t == 0xFFFFFFFFu) {
-        for (uint32_t p = 0; p < nprops; ++p) atoms[(size_t)p * R + r] = 0;
-        return;
+__global__ __launch_bounds__(256) void k_pack(const uint32_t *letters, const uint64_t *offsets,
+                                              const uint32_t *row_trace, const uint32_t *row_word, uint32_t R,
+                                              uint32_t nprops, T *atoms, Counters *ctr) {
+    constexpr uint32_t BITS = (uint32_t)Word<T>::BITS;
+    const uint32_t lane = (uint32_t)__lane_id();
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = (uint32_t)(g / BITS);          // whole waves: R * BITS is a multiple of 64
+    const uint32_t i = (uint32_t)(g % BITS);
+    uint32_t lt = 0;
+    if (r < R) {
+        const uint32_t t = row_trace[r];
+        if (t != 0xFFFFFFFFu) {
+            const uint64_t off = offsets[t];
+            const uint64_t len = offsets[t + 1] - off;
+            const uint64_t pos = (uint64_t)row_word[r] * BITS + i;
+            if (pos < len) lt = letters[off + pos];
+        }
     }
-    const uint64_t off = offsets[t];
-    const uint64_t len = offsets[t + 1] - off;
-    const uint64_t p0 = (uint64_t)row_word[r] * BITS;
-    const uint32_t n = (uint32_t)min((uint64_t)BITS, len - p0);
-    uint32_t lor = 0;
-    for (uint32_t i = 0; i < n; ++i) lor |= letters[off + p0 + i];
     for (uint32_t p = 0; p < nprops; ++p) {
-        T w = 0;
-        for (uint32_t i = 0; i < n; ++i) w |= (T)((letters[off + p0 + i] >> p) & 1u) << (BITS - 1 - i);
-        atoms[(size_t)p * R + r] = w;
+        const uint64_t m = __ballot((lt >> p) & 1u);
+        if (r < R && i == 0) {
+            T w;
+            if constexpr (BITS == 32) w = (T)__builtin_bitreverse32((uint32_t)(m >> (lane & 32u)));
+            else w = (T)__builtin_bitreverse64(m);
+            atoms[(size_t)p * R + r] = w;
+        }
     }
-    if (lor) atomicOr(&ctr->letter_or, lor);
+    uint32_t lor = lt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lor |= (uint32_t)__shfl_xor((int)lor, o);
+    if (lane == 0 && lor) atomicOr(&ctr->letter_or, lor);
 }
 
 // Per-trace fingerprint (length and letters), for the P/N disjointness check.
@@ -1259,24 +1332,30 @@ hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls
 }
 
 template <typename T>
-hipError_t Launch<T>::level_all(const LevelArgs<T> &A, bool mw, bool verify, const Block *blocks, uint32_t nblocks,
-                                uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s) {
+hipError_t Launch<T>::verify_all(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
+                                 uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s) {
     if constexpr (sizeof(T) == 8) {
         if (mw) {
-            if (verify) hipLaunchKernelGGL((k_level_all<T, true, true>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
-            else hipLaunchKernelGGL((k_level_all<T, true, false>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
+            hipLaunchKernelGGL((k_level_all<T, true, true>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
             return hipGetLastError();
         }
     }
-    if (verify) hipLaunchKernelGGL((k_level_all<T, false, true>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
-    else hipLaunchKernelGGL((k_level_all<T, false, false>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
+    hipLaunchKernelGGL((k_level_all<T, false, true>), dim3(grid), dim3(256), 0, s, A, blocks, nblocks, ntiles, chunk);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Launch<T>::probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
-    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((ncand + 255) / 256, 4096));
-    hipLaunchKernelGGL((k_probe<T>), dim3(grid), dim3(256), 0, s, A, ncand);
+hipError_t Launch<T>::level_wg(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
+                               uint32_t ntiles, uint32_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            hipLaunchKernelGGL((k_level_wg<T, true>), dim3(grid), dim3(64 * wg_waves<true>()), 0, s, A, blocks,
+                               nblocks, ntiles);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_level_wg<T, false>), dim3(grid), dim3(64 * wg_waves<false>()), 0, s, A, blocks, nblocks,
+                       ntiles);
     return hipGetLastError();
 }
 
@@ -1309,7 +1388,8 @@ template <typename T>
 hipError_t Launch<T>::pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
                            const uint32_t *row_word, uint32_t R, uint32_t nprops, T *atoms, Counters *ctr,
                            hipStream_t s) {
-    hipLaunchKernelGGL((k_pack<T>), dim3((R + 255) / 256), dim3(256), 0, s, letters, offsets, row_trace,
+    const uint64_t threads = (uint64_t)R * Word<T>::BITS;
+    hipLaunchKernelGGL((k_pack<T>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, letters, offsets, row_trace,
                        row_word, R, nprops, atoms, ctr);
     return hipGetLastError();
 }
