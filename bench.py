@@ -15,6 +15,7 @@ timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import statistics
@@ -69,8 +70,8 @@ FP_SEP_OPS = 5 + 2
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long", "batched"])
     ap.add_argument("--jobs", type=int, default=256, help="batched workload: number of jobs")
     ap.add_argument("--lanes", type=int, default=0,
@@ -114,6 +115,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbps = copy_ceiling(torch)
 
     free, total = torch.cuda.mem_get_info()
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
@@ -129,7 +131,8 @@ def main():
         ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots, flags=flags)
 
         def step():
-            res, dur, _ = ex.run(dev, [cfg["bound"]] * len(dev))
+            res, dur, done = ex.run(dev, [cfg["bound"]] * len(dev))
+            step.last = [(round(d - u, 3), round(d, 3)) for u, d in zip(dur, done)]
             return res, dur
     else:
         def step():
@@ -142,15 +145,21 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    results, job_ms, step_ms, step_jobs = [], [], [], []
+    gc.collect()
+    gc.disable()             # no collector pauses inside the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results, job_ms = [], []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         res, dur = step()
+        step_ms.append(round((time.perf_counter() - ts) * 1e3, 3))
+        step_jobs.append(getattr(step, "last", None))
         results += res
         job_ms += dur
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     wall = t1 - t0
 
     cands = sum(r.candidates for r in results)
@@ -172,17 +181,45 @@ def main():
     # the same jobs one after another on one stream (context for the concurrent figure)
     seq = None
     if lanes > 1:
+        gc.disable()
         torch.cuda.synchronize()
         a = time.perf_counter()
         sres = [ctx.learn(d, cfg["bound"]) for d in dev]
         torch.cuda.synchronize()
         sw = time.perf_counter() - a
+        gc.enable()
         same = all((x.status, x.cost, x.level_new, x.solution_index) == (y.status, y.cost, y.level_new, y.solution_index)
                    for x, y in zip(sres, results[:len(dev)]))
         sroof = roofline(ltl, sres, geom, args.ucarry)[0]
         seq = {"candidates_per_s": round(sum(r.candidates for r in sres) / sw, 1), "ms_per_step": round(sw * 1e3, 3),
                "roofline_frac": sroof["frac"], "avg_launch_ms": sroof["avg_launch_ms"],
                "identical_results": same}
+    one_stream = sres if lanes > 1 else results[:len(dev)]
+    # candidates over summed level-kernel time (one stream: no overlap between jobs)
+    kms = sum(sum(r.kernel_ms.values()) for r in one_stream)
+    cand_kernel = sum(r.candidates for r in one_stream) / (kms * 1e-3) if kms else None
+    # algorithmic HBM bytes (one matrix per candidate, children once per tile) over level-kernel time
+    alg = sum(sum(r.level_bytes) for r in one_stream)
+    hbm = {"bytes_per_step": alg, "GBps": round(alg / (kms * 1e-3) / 1e9, 1) if kms else None}
+    if kms:
+        hbm["frac_of_8TBps"] = round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        hbm["copy_ceiling_GBps"] = round(copy_gbps, 1)
+        hbm["frac_of_copy_ceiling"] = round(alg / (kms * 1e-3) / 1e9 / copy_gbps, 4)
+    # per level of the largest job (one stream)
+    big = max(range(len(one_stream)), key=lambda i: one_stream[i].candidates)
+    rb = one_stream[big]
+    per_level = [{"cost": c, "candidates": rb.level_candidates[c], "new": rb.level_new[c],
+                  "kernel_ms": round(rb.level_ms[c], 4),
+                  "candidates_per_kernel_s": round(rb.level_candidates[c] / (rb.level_ms[c] * 1e-3), 1)
+                  if rb.level_ms[c] else None,
+                  "alg_GBps": round(rb.level_bytes[c] / (rb.level_ms[c] * 1e-3) / 1e9, 1) if rb.level_ms[c] else None}
+                 for c in range(1, rb.levels_done + 1)]
+    # host-resident specifications: every job uploads its traces (PCIe included)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    hres = [ctx.learn(i, cfg["bound"]) for i in insts]
+    torch.cuda.synchronize()
+    hw = time.perf_counter() - a
 
     out = {
         "metric": "candidate formulae evaluated/s",
@@ -195,6 +232,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
+        "step_ms": step_ms,
+        "slowest_step_jobs_start_end_ms": step_jobs[max(range(len(step_ms)), key=lambda i: step_ms[i])],
         "dtype": "u32" if cfg["word_bits"] == 32 else "u64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['num_props']} props, {cfg['k']}+{cfg['k']} traces, "
@@ -216,6 +255,10 @@ def main():
     }
     if seq is not None:
         out["sequential"] = seq
+    out["candidates_per_kernel_s"] = round(cand_kernel, 1) if cand_kernel else None
+    out["hbm_model"] = hbm
+    out["per_level"] = {"job": f"seed {seeds[big]}", "levels": per_level}
+    out["host_spec_candidates_per_s"] = round(sum(r.candidates for r in hres) / hw, 1)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_levels)
@@ -346,18 +389,55 @@ def roofline(ltl, results, geom, ucarry):
     return roof, kern_ms, eval_tops, verify_gbs
 
 
-def cpu_baseline(insts, levels):
-    """The CPU oracle, unchanged, on a bounded sample: the first `levels` cost levels of every job."""
+def copy_ceiling(torch, mib: int = 1024) -> float:
+    """Device-to-device copy rate (bytes read + written per second, GB/s): the measured
+    ceiling of a kernel that only streams HBM."""
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del src, dst
+    return 2.0 * n / (ms * 1e-3) / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(insts, levels, threads):
     from oracle import oracle as O
-    threads = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     cands = 0
     for inst in insts:
         r = O.learn(inst, levels, mode=O.MODE_EXPAND, threads=threads)
         cands += sum(r.level_candidates[:r.levels_done + 1])
-    dt = time.perf_counter() - t0
+    return cands, time.perf_counter() - t0
+
+
+def cpu_baseline(insts, levels):
+    """The CPU oracle, unchanged, on a bounded sample: the first `levels` cost levels of every
+    job on up to 16 host threads, and a smaller sample on one thread."""
+    threads = min(16, os.cpu_count() or 1)
+    cands, dt = oracle_rate(insts, levels, threads)
+    c1, d1 = oracle_rate(insts, max(1, levels - 2), 1)
     return {"value": round(cands / dt, 1), "unit": "candidates/s", "cores": threads, "kind": "oracle",
-            "sample": f"levels 1..{levels} of each of the {len(insts)} jobs ({cands} candidates, {dt:.1f} s)"}
+            "sample": f"levels 1..{levels} of each of the {len(insts)} jobs ({cands} candidates, {dt:.1f} s)",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": round(c1 / d1, 1), "unit": "candidates/s",
+                              "sample": f"levels 1..{max(1, levels - 2)} of each job ({c1} candidates, {d1:.1f} s)"}}
 
 
 if __name__ == "__main__":

@@ -146,6 +146,9 @@ typedef struct {
     uint64_t colliders;                        /* fingerprint collisions resolved exactly   */
     double   kernel_ms[LTL_K_KINDS];           /* GPU time per kernel kind (LTL_CTX_TIMING) */
     uint32_t kernel_launches[LTL_K_KINDS];     /* launches per kernel kind                  */
+    uint32_t pad;
+    uint64_t level_bytes[LTL_MAX_LEVELS];      /* algorithmic HBM bytes per level (see
+                                                  ltl_level_stats.alg_bytes)                */
 } ltl_result;
 
 /* ---------------------------------------------------------------- learning */
@@ -224,6 +227,10 @@ typedef struct {
     uint64_t first_solution;     /* smallest separating canonical index, or LTL_NO_SOLUTION */
     uint64_t colliders;          /* fingerprint matches whose full compare failed         */
     double   kernel_ms;          /* GPU time of the level (LTL_CTX_TIMING), else 0        */
+    uint64_t alg_bytes;          /* algorithmic HBM bytes of the level: one matrix per
+                                    candidate (written if new, else compared with the
+                                    stored one) plus each child matrix read once per tile
+                                    (4 children a side); re-reads are not counted         */
 } ltl_level_stats;
 
 /* Evaluate exactly one cost level: every candidate of cost `cost` built from the

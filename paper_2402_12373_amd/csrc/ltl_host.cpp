@@ -80,6 +80,7 @@ struct LevelInfo {
     uint64_t cands = 0;
     uint64_t first = LTL_NO_SOLUTION;
     uint64_t colliders = 0;
+    uint64_t alg_bytes = 0;    // one matrix per candidate + each child once per tile
     double ms = 0.0;
     std::vector<Block> blocks;
     std::vector<int> a_level, b_level;   // child levels per block (host decode)
@@ -737,6 +738,24 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         cls_tiles[k] = tb;
     }
     cls_first[4] = (uint32_t)grouped.size();
+    {   // algorithmic bytes: every candidate's matrix written or compared once, each child
+        // matrix read once per tile (tiles of TILE children a side; fused unary tiles read a
+        // child once for its four connectives)
+        uint64_t child_reads = 0;
+        for (const Block &g : grouped) {
+            if (g.nb == 0) {
+                child_reads += g.na;
+            } else if (!g.tri) {
+                child_reads += (uint64_t)g.ntj * g.na + (uint64_t)g.nti * g.nb;
+            } else {
+                for (uint32_t it = 0; it < g.nti; ++it) {
+                    const uint64_t rows = std::min<uint64_t>(TILE, g.na - (uint64_t)it * TILE);
+                    child_reads += (uint64_t)(g.nti - it) * rows + (uint64_t)(it + 1) * rows;
+                }
+            }
+        }
+        lv.alg_bytes = (C + child_reads) * j->cm_bytes;
+    }
     memcpy(pin_grouped, grouped.data(), sizeof(Block) * grouped.size());
     // row-split levels evaluate (and verify) every class in one dispatch: one tile numbering over the grouped blocks
     const bool merged_eval = split;
@@ -928,6 +947,7 @@ extern "C" int ltl_eval_level(ltl_job *j, uint32_t c, ltl_level_stats *stats) {
         stats->first_solution = lv.first;
         stats->colliders = lv.colliders;
         stats->kernel_ms = lv.ms;
+        stats->alg_bytes = lv.alg_bytes;
     }
     if (lv.first != LTL_NO_SOLUTION) {
         j->status = LTL_OK;
@@ -1080,6 +1100,7 @@ extern "C" int ltl_job_result(ltl_job *j, ltl_result *out) {
         out->level_new[c] = j->L[c].n;
         out->level_candidates[c] = j->L[c].cands;
         out->level_ms[c] = j->L[c].ms;
+        out->level_bytes[c] = j->L[c].alg_bytes;
     }
     out->colliders = j->colliders;
     for (int k = 0; k < LTL_K_KINDS; ++k) {
@@ -1130,9 +1151,9 @@ struct ltl_batch {
     std::vector<std::thread> workers;
     std::mutex mu;
     std::condition_variable cv_start, cv_done;
-    uint64_t generation = 0;      // bumped once per run
-    uint32_t lanes_busy = 0;      // worker lanes still in the current run
-    bool quit = false;
+    std::atomic<uint64_t> generation{0};   // bumped once per run (under mu)
+    std::atomic<uint32_t> lanes_busy{0};   // worker lanes still in the current run
+    std::atomic<bool> quit{false};
     std::atomic<bool> running{false};
     // the current run
     const ltl_batch_job *jobs = nullptr;
@@ -1157,20 +1178,34 @@ static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
     }
 }
 
+// Waits up to `us` microseconds, polling, for pred(); true if it became true.  Runs
+// come back to back, and a sleeping thread can take milliseconds to be woken.
+template <typename Pred>
+static bool spin_for(Pred pred, int us) {
+    const auto t0 = std::chrono::steady_clock::now();
+    while (!pred()) {
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(us)) return false;
+        std::this_thread::yield();
+    }
+    return true;
+}
+
+constexpr int BATCH_SPIN_US = 5000;
+
 static void batch_worker(ltl_batch *b, uint32_t lane) {
     (void)hipSetDevice(b->o.device);
     uint64_t seen = 0;
     for (;;) {
-        {
+        if (!spin_for([&] { return b->quit.load() || b->generation.load() != seen; }, BATCH_SPIN_US)) {
             std::unique_lock<std::mutex> lk(b->mu);
-            b->cv_start.wait(lk, [&] { return b->quit || b->generation != seen; });
-            if (b->quit) return;
-            seen = b->generation;
+            b->cv_start.wait(lk, [&] { return b->quit.load() || b->generation.load() != seen; });
         }
+        if (b->quit.load()) return;
+        seen = b->generation.load();
         batch_lane_jobs(b, lane);
         {
             std::lock_guard<std::mutex> lk(b->mu);
-            if (--b->lanes_busy == 0) b->cv_done.notify_all();
+            if (b->lanes_busy.fetch_sub(1) == 1) b->cv_done.notify_all();
         }
     }
 }
@@ -1179,7 +1214,7 @@ extern "C" void ltl_batch_destroy(ltl_batch *b) {
     if (!b) return;
     {
         std::lock_guard<std::mutex> lk(b->mu);
-        b->quit = true;
+        b->quit.store(true);
     }
     b->cv_start.notify_all();
     for (auto &t : b->workers) t.join();
@@ -1251,13 +1286,13 @@ extern "C" int ltl_batch_run(ltl_batch *b, const ltl_batch_job *jobs, uint32_t n
     {
         std::lock_guard<std::mutex> lk(b->mu);
         b->lanes_busy = (uint32_t)b->workers.size();
-        ++b->generation;
+        b->generation.fetch_add(1);
     }
     b->cv_start.notify_all();
     batch_lane_jobs(b, 0);
-    {
+    if (!spin_for([&] { return b->lanes_busy.load() == 0; }, BATCH_SPIN_US)) {
         std::unique_lock<std::mutex> lk(b->mu);
-        b->cv_done.wait(lk, [&] { return b->lanes_busy == 0; });
+        b->cv_done.wait(lk, [&] { return b->lanes_busy.load() == 0; });
     }
     b->running = false;
     return LTL_OK;

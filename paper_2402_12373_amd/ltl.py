@@ -75,13 +75,14 @@ class Result(C.Structure):
                 ("num_nodes", C.c_uint32), ("nodes", Node * MAX_NODES), ("solution_index", C.c_uint64),
                 ("level_new", C.c_uint64 * MAX_LEVELS), ("level_candidates", C.c_uint64 * MAX_LEVELS),
                 ("level_ms", C.c_double * MAX_LEVELS), ("colliders", C.c_uint64),
-                ("kernel_ms", C.c_double * K_KINDS), ("kernel_launches", C.c_uint32 * K_KINDS)]
+                ("kernel_ms", C.c_double * K_KINDS), ("kernel_launches", C.c_uint32 * K_KINDS),
+                ("pad", C.c_uint32), ("level_bytes", C.c_uint64 * MAX_LEVELS)]
 
 
 class LevelStats(C.Structure):
     _fields_ = [("cost", C.c_uint32), ("stored", C.c_uint32), ("candidates", C.c_uint64),
                 ("new_entries", C.c_uint64), ("first_solution", C.c_uint64), ("colliders", C.c_uint64),
-                ("kernel_ms", C.c_double)]
+                ("kernel_ms", C.c_double), ("alg_bytes", C.c_uint64)]
 
 
 class JobInfo(C.Structure):
@@ -167,6 +168,7 @@ class LearnResult:
     colliders: int
     kernel_ms: dict = field(default_factory=dict)
     kernel_launches: dict = field(default_factory=dict)
+    level_bytes: List[int] = field(default_factory=list)
 
     @property
     def candidates(self) -> int:
@@ -183,7 +185,8 @@ def _convert(r: Result) -> LearnResult:
                        [float(r.level_ms[c]) for c in range(done + 1)], sol,
                        None if r.solution_index == NO_SOLUTION else int(r.solution_index), int(r.colliders),
                        {KERNEL_KINDS[k]: float(r.kernel_ms[k]) for k in range(K_KINDS)},
-                       {KERNEL_KINDS[k]: int(r.kernel_launches[k]) for k in range(K_KINDS)})
+                       {KERNEL_KINDS[k]: int(r.kernel_launches[k]) for k in range(K_KINDS)},
+                       [int(r.level_bytes[c]) for c in range(done + 1)])
 
 
 class SpecBuffers:

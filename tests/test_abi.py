@@ -54,7 +54,8 @@ int main(void) {
   S(ltl_opset); S(ltl_node);
   S(ltl_result); O(ltl_result, solution_index); O(ltl_result, level_new); O(ltl_result, level_ms);
   O(ltl_result, colliders); O(ltl_result, kernel_ms); O(ltl_result, kernel_launches);
-  S(ltl_level_stats); O(ltl_level_stats, kernel_ms);
+  O(ltl_result, level_bytes);
+  S(ltl_level_stats); O(ltl_level_stats, kernel_ms); O(ltl_level_stats, alg_bytes);
   S(ltl_job_info); O(ltl_job_info, arena_bytes);
   S(ltl_batch_opts); O(ltl_batch_opts, workspace); O(ltl_batch_opts, lanes); O(ltl_batch_opts, max_entries);
   S(ltl_batch_job); O(ltl_batch_job, ops); O(ltl_batch_job, cost_bound);

@@ -278,3 +278,54 @@ def test_batch_executor_reuse(ltl):
     finally:
         ex.close()
         plain.close()
+
+
+def _expected_alg_bytes(E, c, A, cm_bytes):
+    """One matrix per candidate plus each child matrix once per tile of 4 x 4 (unit costs,
+    every connective; F, G, X and NOT over one child level read the child once)."""
+    ceil4 = lambda n: (n + 3) // 4
+    if c == 1:
+        return A, (A + A) * cm_bytes
+    x = c - 1
+    cands = reads = 0
+    if E[x]:
+        cands += 4 * E[x]
+        reads += E[x]
+    for a in range(1, x):                              # U: every ordered split
+        na, nb = E[a], E[x - a]
+        if na and nb:
+            cands += na * nb
+            reads += ceil4(nb) * na + ceil4(na) * nb
+    for _ in range(2):                                 # AND, OR
+        for a in range(1, x // 2 + 1):
+            b = x - a
+            na, nb = E[a], E[b]
+            if a < b and na and nb:
+                cands += na * nb
+                reads += ceil4(nb) * na + ceil4(na) * nb
+            elif a == b and na > 1:
+                cands += na * (na - 1) // 2
+                nt = ceil4(na)
+                for it in range(nt):
+                    rows = min(4, na - 4 * it)
+                    reads += (nt - it) * rows + (it + 1) * rows
+    return cands, (cands + reads) * cm_bytes
+
+
+def test_level_algorithmic_bytes(ltl, ctx):
+    """Per-level algorithmic bytes equal the model computed here from the level sizes."""
+    inst, cfg = synth.preset_instance("tiny", 4)
+    job = ctx.job(inst, 6)
+    try:
+        cm = int(job.info().cm_bytes)
+        E = [0]
+        for c in range(1, 7):
+            st = job.eval_level(c)
+            cands, want = _expected_alg_bytes(E, c, inst.num_props, cm)
+            assert st.candidates == cands, c
+            assert st.alg_bytes == want, (c, st.alg_bytes, want)
+            E.append(st.new_entries)
+            if st.first_solution != ltl.NO_SOLUTION:
+                break
+    finally:
+        job.close()
