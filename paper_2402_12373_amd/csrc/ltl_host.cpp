@@ -62,9 +62,17 @@ bool is_unary(int op) { return op == LTL_NOT || op == LTL_X || op == LTL_F || op
 
 }  // namespace
 
+// Whole-row levels run the U class (VALU-bound) on a second stream, beside the
+// unary and AND/OR classes (HBM-bound), joined before the compaction (a tuning switch).
+#ifndef LTL_FORK_U
+#define LTL_FORK_U 1
+#endif
+
 struct ltl_ctx {
     ltl_ctx_opts o;
     hipStream_t s = nullptr;
+    hipStream_t aux = nullptr;       // second stream of the context (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool busy = false;
     char *pinned = nullptr;          // page-locked host staging: two block tables + counters
     char *jpin = nullptr;            // page-locked staging of a job's row tables (grown on demand)
@@ -150,6 +158,11 @@ struct ltl_job {
     do {                                                      \
         hipError_t e_ = (expr);                               \
         if (e_ != hipSuccess) return LTL_E_DEVICE;            \
+    } while (0)
+#define HIP_TRY_E(expr)                                       \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return e_;                      \
     } while (0)
 
 static void *ws_take(ltl_job *j, uint64_t bytes) {
@@ -248,8 +261,11 @@ extern "C" int ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out) {
     if (!c) return LTL_E_INVAL;
     c->o = *opts;
     c->s = (hipStream_t)opts->stream;
-    if (hipHostMalloc((void **)&c->pinned, PINNED_BYTES, hipHostMallocDefault) != hipSuccess) {
-        delete c;
+    if (hipHostMalloc((void **)&c->pinned, PINNED_BYTES, hipHostMallocDefault) != hipSuccess ||
+        (LTL_FORK_U && (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+                        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess))) {
+        ltl_ctx_destroy(c);
         return LTL_E_DEVICE;
     }
     *out = c;
@@ -258,6 +274,12 @@ extern "C" int ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out) {
 
 extern "C" void ltl_ctx_destroy(ltl_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->jpin) (void)hipHostFree(ctx->jpin);
     delete ctx;
@@ -823,18 +845,27 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)all_tiles * nchunk + 3) / 4, MAX_GRID);
             return Launch<T>::verify_all(A, j->mw, all_d, (uint32_t)grouped.size(), all_tiles, chunk, grid, j->s);
         }
-        for (int k = 0; k < 4; ++k) {
+        // whole-row tiles, one dispatch per connective class; the U class (VALU-bound)
+        // on the context's second stream when other classes (HBM-bound) run beside it
+        const int ucls = ucarry ? 3 : 2;
+        const bool fork = j->ctx->aux && cls_tiles[ucls] && (cls_tiles[0] || cls_tiles[1]);
+        if (fork) {
+            HIP_TRY_E(hipEventRecord(j->ctx->ev_fork, j->s));
+            HIP_TRY_E(hipStreamWaitEvent(j->ctx->aux, j->ctx->ev_fork, 0));
+        }
+        const int order[4] = {ucls, 0, 1, ucls == 2 ? 3 : 2};
+        for (int q = 0; q < 4; ++q) {
+            const int k = order[q];
             if (!cls_tiles[k]) continue;
-            uint64_t per = 1;          // row chunks per tile
-            if (split)
-                per = std::max<uint64_t>(1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK,
-                                                              TARGET_WAVES / cls_tiles[k]));
-            const uint32_t chunk = (uint32_t)((j->NB + per - 1) / per);
-            const uint64_t nchunk = (j->NB + chunk - 1) / chunk;
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] * nchunk + 3) / 4, MAX_GRID);
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] + 3) / 4, MAX_GRID);
             hipError_t e = Launch<T>::level(A, j->mw, verify, k, grouped_d + cls_first[k],
-                                            cls_first[k + 1] - cls_first[k], cls_tiles[k], chunk, grid, j->s);
+                                            cls_first[k + 1] - cls_first[k], cls_tiles[k], j->NB, grid,
+                                            (fork && k == ucls) ? j->ctx->aux : j->s);
             if (e != hipSuccess) return e;
+        }
+        if (fork) {
+            HIP_TRY_E(hipEventRecord(j->ctx->ev_join, j->ctx->aux));
+            HIP_TRY_E(hipStreamWaitEvent(j->s, j->ctx->ev_join, 0));
         }
         return hipSuccess;
     };
