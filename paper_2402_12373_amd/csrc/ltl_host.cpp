@@ -314,7 +314,10 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     // offsets on the host (device specs: copy them back; the letters stay on the device)
     j->off.resize((size_t)T + 1);
     if (spec->flags & LTL_SPEC_DEVICE) {
-        HIP_TRY(hipMemcpy(j->off.data(), spec->offsets, sizeof(uint64_t) * ((size_t)T + 1), hipMemcpyDeviceToHost));
+        // on the job's own stream, not the null stream (no wait behind other streams' work)
+        HIP_TRY(hipMemcpyAsync(j->off.data(), spec->offsets, sizeof(uint64_t) * ((size_t)T + 1),
+                               hipMemcpyDeviceToHost, j->s));
+        HIP_TRY(hipStreamSynchronize(j->s));
     } else {
         memcpy(j->off.data(), spec->offsets, sizeof(uint64_t) * ((size_t)T + 1));
     }
@@ -1029,7 +1032,9 @@ static int host_recipes(ltl_job *j, uint64_t upto) {
     const uint64_t have = j->recipe_h.size();
     if (upto <= have) return LTL_OK;
     j->recipe_h.resize(upto);
-    HIP_TRY(hipMemcpy(j->recipe_h.data() + have, j->recipe + have, (upto - have) * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(j->recipe_h.data() + have, j->recipe + have, (upto - have) * 4, hipMemcpyDeviceToHost,
+                           j->s));
+    HIP_TRY(hipStreamSynchronize(j->s));
     return LTL_OK;
 }
 
