@@ -351,6 +351,7 @@ def roofline(ltl, results, geom, ucarry):
     # candidate mix: the canonical blocks per level follow from the level sizes
     ops_total = 0.0
     bytes_verify = 0.0
+    bytes_eval = 0.0
     for r in results:
         E = r.level_new
         for c in range(1, r.levels_done + 1):
@@ -371,21 +372,29 @@ def roofline(ltl, results, geom, ucarry):
                 per_level_ops = un * (OP_OPS["f"] + OP_OPS["g"] + OP_OPS["x"] + OP_OPS["not"] + 4 * FP_SEP_OPS) \
                     + u_pairs * (uop + FP_SEP_OPS) + ao * (OP_OPS["and"] + OP_OPS["or"] + 2 * FP_SEP_OPS)
                 ops_total += per_level_ops * halves
-            # verify: every non-representative reads its owner's matrix once
+            # algorithmic bytes (the level's model, ltl_level_stats.alg_bytes): evaluation
+            # writes each new matrix and reads each child once per tile; verification
+            # reads one stored matrix per candidate that did not claim its group
             bytes_verify += (C - r.level_new[c]) * cm_bytes
+            bytes_eval += r.level_bytes[c] - (C - r.level_new[c]) * cm_bytes
     eval_ms, verify_ms = kern_ms["eval"], kern_ms["verify"]
     eval_tops = ops_total / (eval_ms * 1e-3) / 1e12 if eval_ms else 0.0
+    eval_gbs = bytes_eval / (eval_ms * 1e-3) / 1e9 if eval_ms else 0.0
     verify_gbs = bytes_verify / (verify_ms * 1e-3) / 1e9 if verify_ms else 0.0
     if dominant == "verify":
-        roof = {"bound": "hbm", "kernel": "k_level<verify>", "achieved": round(verify_gbs, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(verify_gbs / HBM_PEAK_GBS, 4)}
+        roof = {"bound": "hbm", "kernel": "k_level<verify>, k_level_all", "achieved": round(verify_gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(verify_gbs / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes": bytes_verify}
     else:
-        roof = {"bound": "alu", "kernel": "k_level<eval>", "achieved": round(eval_tops, 3),
-                "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
-                "frac": round(eval_tops / VALU_PEAK_TOPS, 4)}
+        roof = {"bound": "hbm", "kernel": "k_level<eval>, k_level_wg", "achieved": round(eval_gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(eval_gbs / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes": bytes_eval,
+                "valu_view": {"achieved_Tops": round(eval_tops, 3), "peak_Tops": round(VALU_PEAK_TOPS, 2),
+                              "frac": round(eval_tops / VALU_PEAK_TOPS, 4)}}
     roof["kind"] = dominant
     roof["avg_launch_ms"] = round(kern_ms[dominant] / max(1, kern_n[dominant]), 4)
     roof["launches"] = kern_n[dominant]
+    roof["algorithmic_MB_per_launch"] = round(roof["algorithmic_bytes"] / max(1, kern_n[dominant]) / 1e6, 3)
     return roof, kern_ms, eval_tops, verify_gbs
 
 

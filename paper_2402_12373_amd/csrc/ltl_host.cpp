@@ -696,8 +696,10 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     const uint64_t nwa = align_up(nw, 64);                 // words, so the bitmaps stay aligned
     const bool split = ntiles < SPLIT_TILES;
     // bitmap | coll_bits | fb_bits, cleared at once
-    const uint64_t clear_bytes = nwa * 4 * 3;
-    uint32_t *bits3 = (uint32_t *)take_top(align_up(clear_bytes, 256));
+    // bitmap | coll_bits | fb_bits | cand_viol | cand_fp (row-split levels whose tiles
+    // span several workgroups); cleared at once
+    uint64_t clear_bytes = nwa * 4 * 3;
+    uint32_t *bits3 = (uint32_t *)take_top(align_up(nwa * 4 * 4 + (split ? (uint64_t)nc * 8 : 0), 256));
     uint32_t *cand_slot = (uint32_t *)take_top((uint64_t)nc * 4);
     uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
@@ -710,7 +712,8 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !claimer || !new_owner || !stage ||
         arena_off + arena_used > top)
         return LTL_E_OOM;
-    uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa;
+    uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
+    unsigned long long *cand_fp = (unsigned long long *)(bits3 + 4 * nwa);
     const uint64_t arena_free = top - (arena_off + arena_used);
     const uint32_t arena_cap = (uint32_t)std::min<uint64_t>(
         {arena_free / j->cm_bytes, j->recipe_cap - j->total_entries, (uint64_t)new_cap});
@@ -793,6 +796,15 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             all_tiles += grouped[k].ntile;
         }
     }
+    // row-split levels: workgroups per tile, enough for the wave target when rows are long
+    uint32_t wg_split = 1;
+    if (merged_eval) {
+        const uint64_t need = std::max<uint64_t>(
+            1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max(1u, all_tiles)));
+        const uint32_t wgw = Launch<T>::waves_per_wg(j->mw);
+        wg_split = (uint32_t)((need + wgw - 1) / wgw);
+        if (wg_split > 1) clear_bytes = nwa * 4 * 4 + (uint64_t)nc * 8;
+    }
     *pin_ctr = Counters{};
     pin_ctr->first_sol = ~0ull;
     Block *grouped_d = j->blocks_d + lv.blocks.size();
@@ -831,6 +843,9 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.stage = stage;
     A.arena_cap = arena_cap;
     A.ucarry = ucarry ? 1 : 0;
+    A.wg_split = wg_split;
+    A.cand_fp = cand_fp;
+    A.cand_viol = cand_viol;
     {   // materialize work items: entries x row chunks (sized on the candidate count, an upper bound)
         const uint64_t per = std::max<uint64_t>(
             1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max<uint64_t>(1, new_cap)));
@@ -838,9 +853,13 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     auto launch_level = [&](bool verify) -> hipError_t {
         if (merged_eval) {
-            if (!verify)
-                return Launch<T>::level_wg(A, j->mw, all_d, (uint32_t)grouped.size(), all_tiles,
-                                           std::min<uint32_t>(all_tiles, (uint32_t)MAX_GRID), j->s);
+            if (!verify) {
+                const uint64_t items = (uint64_t)all_tiles * wg_split;
+                HIP_TRY_E(Launch<T>::level_wg(A, j->mw, all_d, (uint32_t)grouped.size(), all_tiles,
+                                              (uint32_t)std::min<uint64_t>(items, MAX_GRID), j->s));
+                if (wg_split > 1) return Launch<T>::probe(A, nc, j->s);
+                return hipSuccess;
+            }
             const uint64_t per = std::max<uint64_t>(
                 1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max(1u, all_tiles)));
             const uint32_t chunk = (uint32_t)((j->NB + per - 1) / per);
@@ -880,8 +899,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t ncls = 0;
     for (int k = 0; k < 4; ++k) ncls += cls_tiles[k] ? 1u : 0u;
     {
-        Timer tm(j, LTL_K_EVAL, merged_eval ? 1u : ncls);
+        Timer tm(j, LTL_K_EVAL, merged_eval ? (wg_split > 1 ? 2u : 1u) : ncls);
         HIP_TRY(launch_level(false));
+    }
+    if (wg_split > 1) {     // claimers' matrices (their rows were spread over workgroups)
+        Timer tm(j, LTL_K_MATERIALIZE);
+        HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
     }
     {
         Timer tm(j, LTL_K_COMPACT, nw <= SMALL_COMPACT_WORDS ? 1u : 5u);

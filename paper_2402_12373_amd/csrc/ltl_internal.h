@@ -91,6 +91,12 @@ struct LevelArgs {
     uint32_t arena_cap;      // new entries the arena can take this level
     int ucarry;
     uint32_t mat_chunk;            // row blocks per materialize work item
+    // Row-split tiles spread over wg_split workgroups (long rows, few tiles): each
+    // workgroup adds its partial fingerprint and separation flags per candidate;
+    // k_probe claims the slots and k_materialize writes the claimers afterwards.
+    uint32_t wg_split;
+    unsigned long long *cand_fp;   // per candidate: sum of partial fingerprints
+    uint32_t *cand_viol;           // per candidate: separation violated (bit)
 };
 
 
@@ -103,6 +109,9 @@ struct Launch {
     // workgroup per tile (claims and claimers' matrices included) ...
     static hipError_t level_wg(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
                                uint32_t ntiles, uint32_t grid, hipStream_t s);
+    // claims for tiles spread over several workgroups (A.wg_split > 1)
+    static hipError_t probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
+    static constexpr uint32_t waves_per_wg(bool mw) { return mw ? 4u : 8u; }
     // ... and verification with one wave per (tile, row chunk)
     static hipError_t verify_all(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
                                  uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);

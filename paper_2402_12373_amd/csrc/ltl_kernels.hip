@@ -597,8 +597,13 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                         fp += sh->fp[w][lane];
                         bad |= sh->bad[w][lane];
                     }
-                    if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
-                    A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(fp, A.fp_mask), my_idx, claim);
+                    if (A.wg_split > 1) {      // one of several workgroups of the tile: partial sums
+                        atomicAdd(&A.cand_fp[my_idx], (unsigned long long)fp);
+                        if (bad) atomicOr(&A.cand_viol[my_idx >> 5], 1u << (my_idx & 31u));
+                    } else {
+                        if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
+                        A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(fp, A.fp_mask), my_idx, claim);
+                    }
                 }
                 sh->claim[lane] = claim;
             }
@@ -784,8 +789,10 @@ __global__ __launch_bounds__(256) void k_level_all(LevelArgs<T> A, const Block *
 
 // Row-split levels, every connective class in one dispatch: one workgroup of
 // WG_WAVES waves per tile, each wave a chunk of the row blocks; the tile's slots
-// are claimed and its claimers' matrices written in the same dispatch.
-// Multi-word rows need more registers per wave: half as many waves per tile.
+// are claimed and its claimers' matrices written in the same dispatch.  Tiles of
+// long rows may be spread over A.wg_split workgroups, each a range of row blocks
+// (then k_probe claims and k_materialize writes).  Multi-word rows need more
+// registers per wave: half as many waves per workgroup.
 template <bool MW> constexpr int wg_waves() { return MW ? WG_WAVES / 2 : WG_WAVES; }
 
 template <typename T, bool MW>
@@ -797,9 +804,14 @@ void k_level_wg(LevelArgs<T> A, const Block *blocks,
     const uint32_t wv = uniform(threadIdx.x >> 6);
     const uint32_t nwv = blockDim.x >> 6;
     const uint32_t NB = A.rows.NB;
-    const uint32_t chunk = (NB + nwv - 1) / nwv;
-    const uint32_t rb0 = min(NB, wv * chunk), rb1 = min(NB, rb0 + chunk);
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint32_t G = A.wg_split;
+    const uint32_t gchunk = (NB + G - 1) / G;               // row blocks per workgroup of a tile
+    const uint32_t nwork = ntiles * G;
+    for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const uint32_t t = w / G, g = w - t * G;
+        const uint32_t g0 = min(NB, g * gchunk), g1 = min(NB, g0 + gchunk);
+        const uint32_t chunk = (g1 - g0 + nwv - 1) / nwv;
+        const uint32_t rb0 = min(g1, g0 + wv * chunk), rb1 = min(g1, rb0 + chunk);
         const int bi = (int)uniform((uint32_t)find_block_tile(blocks, (int)nblocks, t));
         const Block b = uniform_block(blocks[bi]);
         uint32_t i0, j0;
@@ -820,6 +832,17 @@ void k_level_wg(LevelArgs<T> A, const Block *blocks,
             break;
         default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
         }
+    }
+}
+
+// Tiles spread over several workgroups: combined partial results -> claims.
+template <typename T>
+__global__ __launch_bounds__(256) void k_probe(LevelArgs<T> A, uint32_t ncand) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ncand; x += gridDim.x * blockDim.x) {
+        const bool bad = (A.cand_viol[x >> 5] >> (x & 31u)) & 1u;
+        if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)x);
+        uint32_t claim;
+        A.cand_slot[x] = probe_claim<T>(A, finish_fp(A.cand_fp[x], A.fp_mask), x, claim);
     }
 }
 
@@ -1328,6 +1351,13 @@ hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls
     }
     if (verify) launch_cls<T, false, true>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
     else launch_cls<T, false, false>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((ncand + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_probe<T>), dim3(grid), dim3(256), 0, s, A, ncand);
     return hipGetLastError();
 }
 

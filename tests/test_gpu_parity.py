@@ -329,3 +329,13 @@ def test_level_algorithmic_bytes(ltl, ctx):
                 break
     finally:
         job.close()
+
+
+@pytest.mark.parametrize("lo,hi", [(8, 32), (40, 120)], ids=["u32-4096-traces", "u64-multiword"])
+def test_tiles_spread_over_workgroups(ltl, ctx, lo, hi):
+    """Long rows and few tiles: a tile's row blocks span several workgroups (partial
+    fingerprints added per candidate, claims by a probe pass, claimers written after)."""
+    rng = np.random.default_rng(lo * 1000 + hi)
+    inst = random_instance(rng, 2, 2048, 2048, lo, hi)
+    _say("spread tiles", lo, hi)
+    _level_by_level(ltl, ctx, inst, 4, max_entries_per_level=50)
