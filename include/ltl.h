@@ -253,7 +253,9 @@ int ltl_job_formula(ltl_job *job, uint32_t cost, uint64_t entry, ltl_node *buf, 
 
 /* Characteristic matrix of stored entry `entry` of level `cost`, one byte (0/1)
  * per position, traces in order P then N, positions 0..|tr|-1 of each.  cap must
- * be >= the total number of positions.  For tests and debugging. */
+ * be >= the total number of positions.  Only stored levels keep their matrices
+ * (a level with a solution, or at the cost bound, is not stored): LTL_E_STATE
+ * otherwise.  For tests and debugging. */
 int ltl_job_dump_cm(ltl_job *job, uint32_t cost, uint64_t entry, uint8_t *pos_bits, uint64_t cap);
 
 typedef struct {

@@ -706,10 +706,14 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t *new_slots = (uint32_t *)take_top((uint64_t)new_cap * 4);
     uint32_t *claimer = (uint32_t *)take_top((uint64_t)new_cap * 4);
     uint32_t *new_owner = (uint32_t *)take_top((uint64_t)new_cap * 4);
+    // whole-row levels: claim number per candidate, and the claims other candidates joined
+    uint32_t *cand_claim = split ? nullptr : (uint32_t *)take_top((uint64_t)nc * 4);
+    uint32_t *has_member = split ? nullptr : (uint32_t *)take_top(align_up((uint64_t)new_cap * 4, 256));
     T *stage = (T *)take_top((uint64_t)j->R * sizeof(T));
     const uint64_t arena_off = (uint64_t)(j->arena - j->ws);
     const uint64_t arena_used = j->total_entries * j->cm_bytes;
     if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !claimer || !new_owner || !stage ||
+        (!split && (!cand_claim || !has_member)) ||
         arena_off + arena_used > top)
         return LTL_E_OOM;
     uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
@@ -813,6 +817,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
                            256 + sizeof(Block) * (lv.blocks.size() + grouped.size() * (merged_eval ? 2 : 1)),
                            hipMemcpyHostToDevice, j->s));
     HIP_TRY(hipMemsetAsync(bits3, 0, clear_bytes, j->s));
+    if (has_member) HIP_TRY(hipMemsetAsync(has_member, 0, (uint64_t)new_cap * 4, j->s));
 
     LevelArgs<T> A{};
     A.rows = make_rows<T>(j);
@@ -837,8 +842,13 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.level_base = lv.gid_base;
     A.recipe = j->recipe;
     A.store = j->store;
-    // the evaluation pass writes the claimers' matrices (row-split levels: each wave its rows)
-    A.cw = 1u;
+    // row-split levels write the claimers' matrices in the evaluation dispatch (each wave its
+    // rows); whole-row levels in a write pass after the compaction, which keeps only what the
+    // verification reads when the level will not be stored
+    A.cw = split ? 1u : 0u;
+    A.cand_claim = cand_claim;
+    A.has_member = has_member;
+    A.bound_level = (c == j->bound) ? 1u : 0u;
     A.verify_rep = 0;
     A.stage = stage;
     A.arena_cap = arena_cap;
@@ -851,7 +861,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max<uint64_t>(1, new_cap)));
         A.mat_chunk = (uint32_t)((j->NB + per - 1) / per);
     }
-    auto launch_level = [&](bool verify) -> hipError_t {
+    auto launch_level = [&](bool verify, bool write = false) -> hipError_t {
         if (merged_eval) {
             if (!verify) {
                 const uint64_t items = (uint64_t)all_tiles * wg_split;
@@ -880,9 +890,11 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             const int k = order[q];
             if (!cls_tiles[k]) continue;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] + 3) / 4, MAX_GRID);
-            hipError_t e = Launch<T>::level(A, j->mw, verify, k, grouped_d + cls_first[k],
-                                            cls_first[k + 1] - cls_first[k], cls_tiles[k], j->NB, grid,
-                                            (fork && k == ucls) ? j->ctx->aux : j->s);
+            hipStream_t st = (fork && k == ucls) ? j->ctx->aux : j->s;
+            hipError_t e = write ? Launch<T>::write_pass(A, j->mw, k, grouped_d + cls_first[k],
+                                                         cls_first[k + 1] - cls_first[k], cls_tiles[k], grid, st)
+                                 : Launch<T>::level(A, j->mw, verify, k, grouped_d + cls_first[k],
+                                                    cls_first[k + 1] - cls_first[k], cls_tiles[k], j->NB, grid, st);
             if (e != hipSuccess) return e;
         }
         if (fork) {
@@ -906,6 +918,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         Timer tm(j, LTL_K_MATERIALIZE);
         HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
     }
+    const bool write_pass = !split;
     {
         Timer tm(j, LTL_K_COMPACT, nw <= SMALL_COMPACT_WORDS ? 1u : 5u);
         if (nw <= SMALL_COMPACT_WORDS) {
@@ -917,6 +930,11 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             HIP_TRY(launch_scatter(new_slots, j->ctr, arena_cap, j->tval, bitmap, wordpre, j->recipe, lv.gid_base,
                                    j->entry_slot, new_owner, j->store, false, grid_new, j->s));
         }
+    }
+    if (write_pass) {
+        Timer tm(j, LTL_K_MATERIALIZE, ncls + 1);
+        HIP_TRY(Launch<T>::mark_members(A, nc, j->s));
+        HIP_TRY(launch_level(false, true));
     }
     {
         Timer tm(j, LTL_K_VERIFY, merged_eval ? 1u : ncls);
@@ -1113,6 +1131,7 @@ extern "C" int ltl_job_dump_cm(ltl_job *j, uint32_t cost, uint64_t entry, uint8_
     if (!j || !pos_bits || cost > j->levels_done || cost >= j->L.size()) return LTL_E_INVAL;
     const LevelInfo &lv = j->L[cost];
     if (!lv.evaluated || entry >= lv.n || cap < j->TB) return LTL_E_INVAL;
+    if (!lv.stored) return LTL_E_STATE;      // matrices of a level that is not stored may be partial
     std::vector<uint64_t> words(j->R);
     uint32_t pos = 0;
     HIP_TRY(hipMemcpy(&pos, j->store + lv.gid_base + entry, 4, hipMemcpyDeviceToHost));

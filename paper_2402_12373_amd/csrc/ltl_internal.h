@@ -85,6 +85,13 @@ struct LevelArgs {
     uint32_t *store;         // per global entry: arena position of its matrix (claim order
                              // within the level: position level_base + claim number)
     uint32_t cw;             // the evaluation pass writes each claimer's matrix
+    // Whole-row levels write the claimers' matrices in a pass of their own, after the
+    // evaluation: if the level turns out not to be stored (a solution was found, or it
+    // is the bound level), only the claimers whose group other candidates joined
+    // (has_member) are written, for the verification to compare with.
+    uint32_t *cand_claim;    // per candidate: its claim number, or 0xFFFFFFFF
+    uint32_t *has_member;    // per claim: another candidate of the level joined its group
+    uint32_t bound_level;    // the level is the cost bound (never stored)
     uint32_t verify_rep;     // verify against the representative (exact re-check) instead of
                              // against the claimer
     T *stage;                // R words of scratch for the fallback
@@ -111,6 +118,10 @@ struct Launch {
                                uint32_t ntiles, uint32_t grid, hipStream_t s);
     // claims for tiles spread over several workgroups (A.wg_split > 1)
     static hipError_t probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
+    // whole-row levels: groups joined by other candidates, then the write pass per class
+    static hipError_t mark_members(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
+    static hipError_t write_pass(const LevelArgs<T> &A, bool mw, int cls, const Block *blocks, uint32_t nblocks,
+                                 uint32_t ntiles, uint32_t grid, hipStream_t s);
     static constexpr uint32_t waves_per_wg(bool mw) { return mw ? 4u : 8u; }
     // ... and verification with one wave per (tile, row chunk)
     static hipError_t verify_all(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,

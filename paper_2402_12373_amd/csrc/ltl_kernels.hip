@@ -459,7 +459,10 @@ struct WgShare {
 
 // EVAL with WG: rows [rb0, rb1) are this wave's chunk of the tile; wave 0 of the
 // workgroup claims the slots, then every wave writes its chunk of each claimer.
-template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY, bool CW = true, bool WG = false>
+// WONLY: the write pass of a whole-row level (no evaluation): the claimers of the
+// tile, known from cand_claim, get their matrices written.
+template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY, bool CW = true, bool WG = false,
+          bool WONLY = false>
 __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane,
                                          uint32_t rb0, uint32_t rb1, WgShare *sh = nullptr, uint32_t wv = 0,
                                          uint32_t nwv = 1) {
@@ -543,6 +546,21 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
     };
 
     if constexpr (!VERIFY) {
+      uint32_t my_claim = 0xFFFFFFFFu;
+      if constexpr (WONLY) {
+        // a level that will not be stored keeps only the matrices the verification reads
+        const bool keep_all = !A.bound_level && uniform64(A.ctr->first_sol) == ~0ull;
+        if (lane < NP) {
+            uint32_t idx_l = 0xFFFFFFFFu;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                if (lane == p) idx_l = idx[p];
+            if (idx_l != 0xFFFFFFFFu) {
+                const uint32_t q = A.cand_claim[idx_l];
+                if (q < A.arena_cap && (keep_all || A.has_member[q])) my_claim = q;
+            }
+        }
+      } else {
         uint64_t acc[NP];
         T viol[NP];
 #pragma unroll
@@ -580,7 +598,6 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
             const bool bad = __ballot(viol[p] != 0) != 0ull;
             if (lane == p) { my_fp = sum; my_idx = idx[p]; my_bad = bad; }
         }
-        uint32_t my_claim = 0xFFFFFFFFu;
         if constexpr (WG) {
             // partial results of this wave's row chunk -> wave 0 claims for the tile
             if (lane < NP) {
@@ -613,9 +630,11 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
         } else if (my_idx != 0xFFFFFFFFu) {
             if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
             A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx, my_claim);
+            if (A.cand_claim) A.cand_claim[my_idx] = my_claim;
         }
-        // claimers' matrices, written while the children are still in cache
-        if (CW && (WG || A.cw) && __ballot(my_claim < A.arena_cap) != 0ull) {
+      }
+        // claimers' matrices (in the evaluation pass the children are still in cache)
+        if (CW && (WG || WONLY || A.cw) && __ballot(my_claim < A.arena_cap) != 0ull) {
             gptr<T> dp[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
@@ -705,11 +724,11 @@ __device__ __forceinline__ Block uniform_block(const Block &in) {
 // A.cls_blocks with class-local tile numbering.
 enum { CLS_UNARY = 0, CLS_ANDOR = 1, CLS_U = 2, CLS_UC = 3 };
 
-template <typename T, bool MW, bool VERIFY, int CLS>
+template <typename T, bool MW, bool VERIFY, int CLS, bool WONLY = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
                                                uint32_t ntiles, uint32_t chunk) {
     const int lane = (int)__lane_id();
-    if constexpr (VERIFY) {
+    if constexpr (VERIFY || WONLY) {
         if (uniform(A.ctr->overflow) || uniform(A.ctr->n_new) > A.arena_cap) return;
     }
     const uint32_t NB = A.rows.NB;
@@ -728,20 +747,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         j0 = uniform(j0);
         if constexpr (CLS == CLS_UNARY) {
             switch (b.op) {
-            case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
-            default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
+            default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
             }
         } else if constexpr (CLS == CLS_ANDOR) {
-            if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
-            else run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+            if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
+            else run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
         } else if constexpr (CLS == CLS_U) {
-            run_tile<T, MW, LTL_U, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+            run_tile<T, MW, LTL_U, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
         } else {
-            run_tile<T, MW, OP_UC, TILE, TILE, VERIFY>(A, b, i0, j0, lane, rb0, rb1);
+            run_tile<T, MW, OP_UC, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
         }
     }
 }
@@ -832,6 +851,25 @@ void k_level_wg(LevelArgs<T> A, const Block *blocks,
             break;
         default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
         }
+    }
+}
+
+// Whole-row levels: claims whose group another candidate of the level joined
+// (after compaction: the candidate's slot holds an entry of this level that it did
+// not claim).  Only needed when the level will not be stored.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mark_members(LevelArgs<T> A, uint32_t ncand) {
+    if (!A.bound_level && uniform64(A.ctr->first_sol) == ~0ull) return;
+    if (uniform(A.ctr->overflow) || uniform(A.ctr->n_new) > A.arena_cap) return;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ncand; x += gridDim.x * blockDim.x) {
+        const uint32_t h = A.cand_slot[x];
+        if (h == NO_SLOT) continue;
+        const uint32_t v = A.tval[h];
+        if (!(v & VAL_SETTLED)) continue;
+        const uint32_t g = v & ~VAL_SETTLED;
+        if (g < A.level_base) continue;
+        const uint32_t q = A.store[g] - A.level_base;
+        if (A.claimer[q] != x) A.has_member[q] = 1u;
     }
 }
 
@@ -1351,6 +1389,38 @@ hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls
     }
     if (verify) launch_cls<T, false, true>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
     else launch_cls<T, false, false>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::mark_members(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((ncand + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_mark_members<T>), dim3(grid), dim3(256), 0, s, A, ncand);
+    return hipGetLastError();
+}
+
+template <typename T, bool MW>
+static void launch_write_cls(const LevelArgs<T> &A, int cls, const Block *blocks, uint32_t nb, uint32_t nt,
+                             uint32_t grid, hipStream_t s) {
+    const uint32_t ch = A.rows.NB;
+    switch (cls) {
+    case CLS_UNARY: hipLaunchKernelGGL((k_level<T, MW, false, CLS_UNARY, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    case CLS_ANDOR: hipLaunchKernelGGL((k_level<T, MW, false, CLS_ANDOR, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    case CLS_U:     hipLaunchKernelGGL((k_level<T, MW, false, CLS_U, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    default:        hipLaunchKernelGGL((k_level<T, MW, false, CLS_UC, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::write_pass(const LevelArgs<T> &A, bool mw, int cls, const Block *blocks, uint32_t nblocks,
+                                 uint32_t ntiles, uint32_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            launch_write_cls<T, true>(A, cls, blocks, nblocks, ntiles, grid, s);
+            return hipGetLastError();
+        }
+    }
+    launch_write_cls<T, false>(A, cls, blocks, nblocks, ntiles, grid, s);
     return hipGetLastError();
 }
 

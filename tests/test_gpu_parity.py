@@ -73,9 +73,16 @@ def _level_by_level(ltl, ctx, inst, bound, check_entries=True, max_entries_per_l
                 continue
             n = ora.level_new[c]
             step = 1 if max_entries_per_level is None else max(1, n // max_entries_per_level)
+            # a level with a solution, or at the bound, is not stored: formulas only
+            assert st.stored == (st.first_solution == ltl.NO_SOLUTION and c < bound), c
             for e in range(0, n, step):
                 assert job.formula(c, e) == run.entry_formula(c, e), (c, e)
-                np.testing.assert_array_equal(job.dump_cm(c, e), run.entry_cm(c, e), err_msg=f"level {c} entry {e}")
+                if st.stored:
+                    np.testing.assert_array_equal(job.dump_cm(c, e), run.entry_cm(c, e),
+                                                  err_msg=f"level {c} entry {e}")
+            if not st.stored and n:
+                with pytest.raises(ltl.LTLError):
+                    job.dump_cm(c, 0)
         g = job.result()
     finally:
         job.close()
