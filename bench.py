@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--workspace-gb", type=float, default=0.0)
     ap.add_argument("--ucarry", action="store_true", help="U by carry-chain add instead of doubling")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="no per-kernel HIP events (no kernel times, no roofline)")
     ap.add_argument("--cpu-levels", type=int, default=8, help="levels per job in the CPU-baseline sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device (a kernel of known traffic for "
@@ -120,15 +122,19 @@ def main():
     free, total = torch.cuda.mem_get_info()
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     slots = 26 if args.workload != "tiny" else 20
-    flags = ltl.CTX_TIMING | (ltl.CTX_U_CARRY if args.ucarry else 0)
+    ucarry = ltl.CTX_U_CARRY if args.ucarry else 0
+    # timed steps: one event pair per level (level GPU time, for the roofline); the one-stream
+    # pass: events around every kernel group (time per kernel kind)
+    timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
+    full_flags = (0 if args.no_timing else ltl.CTX_TIMING) | ucarry
     lanes = args.lanes or 4
     lanes = max(1, min(lanes, len(dev)))
     # lanes > 1: the batch executor takes the workspace; the one-stream comparison run gets a
     # workspace of one lane's size, so both see the same capacity per job
     ctx_bytes = ws_bytes if lanes == 1 else (ws_bytes // (lanes + 1)) & ~255
-    ctx = ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots, flags=flags)
+    ctx = ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots, flags=full_flags if lanes > 1 else timed_flags)
     if lanes > 1:
-        ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots, flags=flags)
+        ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots, flags=timed_flags)
 
         def step():
             res, dur, done = ex.run(dev, [cfg["bound"]] * len(dev))
@@ -190,13 +196,15 @@ def main():
         gc.enable()
         same = all((x.status, x.cost, x.level_new, x.solution_index) == (y.status, y.cost, y.level_new, y.solution_index)
                    for x, y in zip(sres, results[:len(dev)]))
-        sroof = roofline(ltl, sres, geom, args.ucarry)[0]
+        sroof, skern, _, _ = roofline(ltl, sres, geom, args.ucarry)
         seq = {"candidates_per_s": round(sum(r.candidates for r in sres) / sw, 1), "ms_per_step": round(sw * 1e3, 3),
                "roofline_frac": sroof["frac"], "avg_launch_ms": sroof["avg_launch_ms"],
+               "kernel_ms_per_step": {k: round(v, 3) for k, v in skern.items()},
+               "valu_view": sroof.get("valu_view"), "verify_view": sroof.get("verify_view"),
                "identical_results": same}
     one_stream = sres if lanes > 1 else results[:len(dev)]
     # candidates over summed level-kernel time (one stream: no overlap between jobs)
-    kms = sum(sum(r.kernel_ms.values()) for r in one_stream)
+    kms = sum(sum(r.level_ms) for r in one_stream)
     cand_kernel = sum(r.candidates for r in one_stream) / (kms * 1e-3) if kms else None
     # algorithmic HBM bytes (one matrix per candidate, children once per tile) over level-kernel time
     alg = sum(sum(r.level_bytes) for r in one_stream)
@@ -248,9 +256,7 @@ def main():
         "minimal_costs": [r.cost if r.status == 0 else None for r in results[:len(dev)]],
         "statuses": [r.status for r in results[:len(dev)]],
         "candidates_per_step": cands // args.steps,
-        "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in kern_ms.items()},
-        "verify_GBps": round(verify_gbs, 1),
-        "eval_Tops": round(eval_tops, 3),
+        "level_gpu_ms_per_step": round(sum(sum(r.level_ms) for r in results) / args.steps, 3),
         "roofline": roof,
     }
     if seq is not None:
@@ -380,7 +386,7 @@ def roofline(ltl, results, geom, ucarry):
                 ops_total += per_level_ops * halves
             bytes_level += r.level_bytes[c]
             bytes_verify += (C - r.level_new[c]) * cm_bytes
-    level_ms = sum(kern_ms[q] for q in kinds)
+    level_ms = sum(sum(r.level_ms) for r in results)      # GPU time of the levels (either timing mode)
     launches = sum(kern_n[q] for q in kinds)
     eval_ms, verify_ms = kern_ms["eval"], kern_ms["verify"]
     eval_tops = ops_total / (eval_ms * 1e-3) / 1e12 if eval_ms else 0.0
@@ -391,9 +397,11 @@ def roofline(ltl, results, geom, ucarry):
             "frac": round(level_gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": bytes_level,
             "kind": "level", "avg_launch_ms": round(level_ms / max(1, launches), 4), "launches": launches,
             "algorithmic_MB_per_launch": round(bytes_level / max(1, launches) / 1e6, 3),
-            "valu_view": {"kernel": "evaluation", "achieved_Tops": round(eval_tops, 3),
-                          "peak_Tops": round(VALU_PEAK_TOPS, 2), "frac": round(eval_tops / VALU_PEAK_TOPS, 4)},
-            "verify_view": {"achieved_GBps": round(verify_gbs, 1), "frac": round(verify_gbs / HBM_PEAK_GBS, 4)}}
+            "level_ms": round(level_ms, 3)}
+    if eval_ms:        # per-kind times (LTL_CTX_TIMING)
+        roof["valu_view"] = {"kernel": "evaluation", "achieved_Tops": round(eval_tops, 3),
+                             "peak_Tops": round(VALU_PEAK_TOPS, 2), "frac": round(eval_tops / VALU_PEAK_TOPS, 4)}
+        roof["verify_view"] = {"achieved_GBps": round(verify_gbs, 1), "frac": round(verify_gbs / HBM_PEAK_GBS, 4)}
     return roof, kern_ms, eval_tops, verify_gbs
 
 

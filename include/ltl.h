@@ -68,7 +68,10 @@ typedef struct ltl_job ltl_job;
 #define LTL_CTX_U_CARRY   0x1u   /* compute U by a carry-propagating add (one add per word)
                                     instead of the log2(n) shift-doubling of App. B; both give
                                     identical matrices                                         */
-#define LTL_CTX_TIMING    0x2u   /* record per-level kernel time with HIP events              */
+#define LTL_CTX_TIMING    0x2u   /* record GPU time per kernel kind and per level (HIP events
+                                    around each kernel group)                                  */
+#define LTL_CTX_TIMING_LEVEL 0x4u /* record only the GPU time of each level: one event pair from
+                                    its first to its last kernel (level_ms; kernel_ms stays 0) */
 
 typedef struct {
     int32_t  device;            /* HIP device ordinal used by every call of this context        */
@@ -142,7 +145,8 @@ typedef struct {
                                                   level, or LTL_NO_SOLUTION                 */
     uint64_t level_new[LTL_MAX_LEVELS];        /* distinct new languages per cost level     */
     uint64_t level_candidates[LTL_MAX_LEVELS]; /* candidates evaluated per cost level       */
-    double   level_ms[LTL_MAX_LEVELS];         /* GPU time per level (LTL_CTX_TIMING)       */
+    double   level_ms[LTL_MAX_LEVELS];         /* GPU time per level (LTL_CTX_TIMING or
+                                                  LTL_CTX_TIMING_LEVEL)                     */
     uint64_t colliders;                        /* fingerprint collisions resolved exactly   */
     double   kernel_ms[LTL_K_KINDS];           /* GPU time per kernel kind (LTL_CTX_TIMING) */
     uint32_t kernel_launches[LTL_K_KINDS];     /* launches per kernel kind                  */
@@ -226,7 +230,7 @@ typedef struct {
     uint64_t new_entries;        /* distinct languages first reached at this cost         */
     uint64_t first_solution;     /* smallest separating canonical index, or LTL_NO_SOLUTION */
     uint64_t colliders;          /* fingerprint matches whose full compare failed         */
-    double   kernel_ms;          /* GPU time of the level (LTL_CTX_TIMING), else 0        */
+    double   kernel_ms;          /* GPU time of the level (LTL_CTX_TIMING[_LEVEL]), else 0 */
     uint64_t alg_bytes;          /* algorithmic HBM bytes of the level: one matrix per
                                     candidate (written if new, else compared with the
                                     stored one) plus each child matrix read once per tile

@@ -73,6 +73,7 @@ struct ltl_ctx {
     hipStream_t s = nullptr;
     hipStream_t aux = nullptr;       // second stream of the context (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<hipEvent_t> events;  // timing events, kept across jobs (created on first use)
     bool busy = false;
     char *pinned = nullptr;          // page-locked host staging: two block tables + counters
     char *jpin = nullptr;            // page-locked staging of a job's row tables (grown on demand)
@@ -143,6 +144,8 @@ struct ltl_job {
     uint64_t sol_index = LTL_NO_SOLUTION;
     uint64_t colliders = 0;
     bool timing = false;
+    bool timing_level = false;       // one event pair per level only
+    double span_ms = 0.0;            // level spans collected (timing_level)
     std::vector<TimedLaunch> pending;
     std::vector<Block> grouped;
     Counters ctr_init{};
@@ -178,6 +181,11 @@ static hipEvent_t pool_event(ltl_job *j) {
         j->event_pool.pop_back();
         return e;
     }
+    if (!j->ctx->events.empty()) {       // the context's events, kept across jobs
+        hipEvent_t e = j->ctx->events.back();
+        j->ctx->events.pop_back();
+        return e;
+    }
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
@@ -208,13 +216,41 @@ struct Timer {
     }
 };
 
+// One event pair around a whole level, from its first to its last kernel
+// (LTL_CTX_TIMING_LEVEL: two events per level instead of two per kernel group).
+struct LevelSpan {
+    ltl_job *j;
+    TimedLaunch t{};
+    bool on = false;
+    explicit LevelSpan(ltl_job *job) : j(job) {
+        if (!j->timing_level) return;
+        t.kind = -1;
+        t.e0 = pool_event(j);
+        t.e1 = pool_event(j);
+        if (t.e0 && t.e1 && hipEventRecord(t.e0, j->s) == hipSuccess) {
+            on = true;
+        } else {
+            if (t.e0) j->event_pool.push_back(t.e0);
+            if (t.e1) j->event_pool.push_back(t.e1);
+        }
+    }
+    void end() {
+        if (!on) return;
+        (void)hipEventRecord(t.e1, j->s);
+        j->pending.push_back(t);
+        on = false;
+    }
+    ~LevelSpan() { end(); }
+};
+
 // Adds the elapsed times of completed launches; returns their sum.
 static double collect_times(ltl_job *j) {
     double tot = 0.0;
     for (auto &t : j->pending) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, t.e0, t.e1) == hipSuccess) {
-            j->kernel_ms[t.kind] += ms;
+            if (t.kind >= 0) j->kernel_ms[t.kind] += ms;
+            else j->span_ms += ms;                  // a whole level (timing_level)
             tot += ms;
         }
         j->event_pool.push_back(t.e0);
@@ -278,6 +314,7 @@ extern "C" void ltl_ctx_destroy(ltl_ctx *ctx) {
         (void)hipStreamSynchronize(ctx->aux);
         (void)hipStreamDestroy(ctx->aux);
     }
+    for (auto e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -309,6 +346,7 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     j->used = 0;
     j->s = c->s;
     j->timing = (c->o.flags & LTL_CTX_TIMING) != 0;
+    j->timing_level = !j->timing && (c->o.flags & LTL_CTX_TIMING_LEVEL) != 0;
     const uint32_t T = j->T;
 
     // offsets on the host (device specs: copy them back; the letters stay on the device)
@@ -551,8 +589,10 @@ extern "C" void ltl_job_destroy(ltl_job *j) {
         launch_clear_slots(j->entry_slot, (uint32_t)j->total_entries, j->tkey, j->tval, j->s) == hipSuccess)
         j->ctx->table_clean_log2 = j->slots_log2;
     if (j->s) (void)hipStreamSynchronize(j->s); else (void)hipDeviceSynchronize();
-    for (auto &t : j->pending) { (void)hipEventDestroy(t.e0); (void)hipEventDestroy(t.e1); }
-    for (auto e : j->event_pool) (void)hipEventDestroy(e);
+    if (j->ctx) {      // events go back to the context for its next job
+        for (auto &t : j->pending) { j->ctx->events.push_back(t.e0); j->ctx->events.push_back(t.e1); }
+        for (auto e : j->event_pool) j->ctx->events.push_back(e);
+    }
     if (j->ctx) j->ctx->busy = false;
     delete j;
 }
@@ -910,6 +950,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     j->table_consistent = false;
     uint32_t ncls = 0;
     for (int k = 0; k < 4; ++k) ncls += cls_tiles[k] ? 1u : 0u;
+    LevelSpan span(j);
     {
         Timer tm(j, LTL_K_EVAL, merged_eval ? (wg_split > 1 ? 2u : 1u) : ncls);
         HIP_TRY(launch_level(false));
@@ -940,6 +981,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         Timer tm(j, LTL_K_VERIFY, merged_eval ? 1u : ncls);
         HIP_TRY(launch_level(true));
     }
+    span.end();
     Counters hc;
     if (int e = sync_read_counters(j, &hc)) return e;
     if (hc.overflow || hc.n_new > arena_cap) return LTL_E_OOM;
@@ -998,12 +1040,12 @@ extern "C" int ltl_eval_level(ltl_job *j, uint32_t c, ltl_level_stats *stats) {
     if (hipSetDevice(j->ctx->o.device) != hipSuccess) return LTL_E_DEVICE;
     LevelInfo &lv = j->L[c];
     lv = LevelInfo();
-    const double before = [&] { double s = 0; for (double v : j->kernel_ms) s += v; return s; }();
+    const double before = [&] { double s = j->span_ms; for (double v : j->kernel_ms) s += v; return s; }();
     int st = LTL_OK;
     if (c >= j->ops.cost[LTL_ATOM]) st = (j->wbits == 64) ? eval_level_t<uint64_t>(j, c, lv) : eval_level_t<uint32_t>(j, c, lv);
     else lv.gid_base = (uint32_t)j->total_entries;
     collect_times(j);
-    double after = 0;
+    double after = j->span_ms;
     for (double v : j->kernel_ms) after += v;
     lv.ms = after - before;
     if (st != LTL_OK) {
