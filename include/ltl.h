@@ -233,8 +233,9 @@ typedef struct {
     double   kernel_ms;          /* GPU time of the level (LTL_CTX_TIMING[_LEVEL]), else 0 */
     uint64_t alg_bytes;          /* algorithmic HBM bytes of the level: one matrix per
                                     candidate (written if new, else compared with the
-                                    stored one) plus each child matrix read once per tile
-                                    (4 children a side); re-reads are not counted         */
+                                    stored one; a level that is not stored writes none)
+                                    plus each child matrix read once per tile (4 children
+                                    a side); re-reads are not counted                     */
 } ltl_level_stats;
 
 /* Evaluate exactly one cost level: every candidate of cost `cost` built from the

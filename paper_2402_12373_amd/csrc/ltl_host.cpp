@@ -89,7 +89,7 @@ struct LevelInfo {
     uint64_t cands = 0;
     uint64_t first = LTL_NO_SOLUTION;
     uint64_t colliders = 0;
-    uint64_t alg_bytes = 0;    // one matrix per candidate + each child once per tile
+    uint64_t alg_bytes = 0;    // one matrix per candidate (none written if not stored) + children once per tile
     double ms = 0.0;
     std::vector<Block> blocks;
     std::vector<int> a_level, b_level;   // child levels per block (host decode)
@@ -826,7 +826,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
                 }
             }
         }
-        lv.alg_bytes = (C + child_reads) * j->cm_bytes;
+        lv.alg_bytes = (C + child_reads) * j->cm_bytes;   // new entries written: a stored level
     }
     memcpy(pin_grouped, grouped.data(), sizeof(Block) * grouped.size());
     // row-split levels evaluate (and verify) every class in one dispatch: one tile numbering over the grouped blocks
@@ -988,6 +988,8 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     lv.first = (hc.first_sol == ~0ull) ? LTL_NO_SOLUTION : (uint64_t)hc.first_sol;
     lv.stored = lv.first == LTL_NO_SOLUTION && c < j->bound;
     uint32_t n_new = hc.n_new;
+    // a level that is not stored need not write its new entries (check-only)
+    if (!lv.stored) lv.alg_bytes -= (uint64_t)std::min<uint64_t>(n_new, C) * j->cm_bytes;
     lv.colliders = 0;
     if (hc.n_coll) {
         // A fingerprint group held two different matrices.  Exact re-check: every
