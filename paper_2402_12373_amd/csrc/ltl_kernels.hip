@@ -131,6 +131,16 @@ __device__ __forceinline__ void finish_meta(RowMeta<T> &m, int lane) {
 // Connectives
 // ---------------------------------------------------------------------------
 
+// The value of the next lane (lane 63 reads 0): a DPP whole-wave shift by one
+// lane, one VALU move per 32-bit half instead of a permute through LDS.  Every
+// lane of the wave must be active (rows are padded to whole 64-row blocks).
+__device__ __forceinline__ uint64_t from_next_lane(uint64_t x) {
+    constexpr int WAVE_SHL1 = 0x130;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)x, WAVE_SHL1, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), WAVE_SHL1, 0xF, 0xF, true);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Shift toward earlier positions by s within each trace: bits of later words of
 // the same trace move in; nothing crosses into another trace.
 template <typename T, bool MW>
@@ -138,10 +148,11 @@ __device__ __forceinline__ T shl_pos(T x, uint32_t s, const RowMeta<T> &m, int l
     if constexpr (!MW) {
         return x << s;
     } else {
-        if (s < 64) {
-            uint64_t nw = __shfl_down((unsigned long long)x, 1u);
-            if (!(m.nx & (2ull << lane))) nw = 0;
-            return (x << s) | (nw >> (64u - s));
+        if (s <= 64) {
+            // the move runs in every lane; lanes whose trace ends here drop it
+            const uint64_t nx = from_next_lane(x);
+            const uint64_t nw = (m.nx & (2ull << lane)) ? nx : 0ull;
+            return s < 64 ? (x << s) | (nw >> (64u - s)) : (T)nw;
         } else {
             uint32_t q = s >> 6;
             uint32_t src = (uint32_t)lane + q;
@@ -252,6 +263,38 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor((unsigned long long)x, o);
     return x;
+}
+
+// One halving step of wave_sums: H sums held, the partner at xor distance O
+// gets half of them; the kept half absorbs what the partner hands over.
+template <int H, int O, int NP>
+__device__ __forceinline__ void halve_sums(uint64_t (&v)[NP], int lane) {
+    if constexpr (H > 1) {
+        const bool up = (lane & O) != 0;
+#pragma unroll
+        for (int k = 0; k < H / 2; ++k) {
+            const uint64_t send = up ? v[k] : v[k + H / 2];
+            const uint64_t keep = up ? v[k + H / 2] : v[k];
+            v[k] = keep + (uint64_t)__shfl_xor((unsigned long long)send, O);
+        }
+        halve_sums<H / 2, O / 2, NP>(v, lane);
+    }
+}
+
+// NP wave sums at once (NP a power of two, at most 64): lane p < NP receives
+// the sum of v[p] over the wave.  Each xor step hands the partner half of the
+// sums still held and adds the half it receives (NP/2 + NP/4 + ... exchanges
+// instead of 6 per sum); afterwards lane l holds sum l / (64/NP), partial over
+// the lanes that agree in the higher bits, which the remaining steps complete.
+template <int NP>
+__device__ __forceinline__ uint64_t wave_sums(uint64_t (&v)[NP], int lane) {
+    static_assert(NP >= 1 && NP <= 64 && (NP & (NP - 1)) == 0, "NP must be a power of two");
+    constexpr int STRIDE = 64 / NP;
+    halve_sums<NP, 32, NP>(v, lane);
+    uint64_t x = v[0];
+#pragma unroll
+    for (int o = STRIDE / 2; o > 0; o >>= 1) x += (uint64_t)__shfl_xor((unsigned long long)x, o);
+    return (uint64_t)__shfl((unsigned long long)x, (lane % NP) * STRIDE);
 }
 
 // Stafford's "Mix13" 64-bit finalizer (as used by SplitMix64).
@@ -588,15 +631,14 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
 #pragma unroll
             for (int u = 0; u < PIPE; ++u) cur[u] = nxt[u];
         }
-        uint64_t my_fp = 0;
+        const uint64_t my_fp = wave_sums<NP>(acc, lane);   // valid in lanes < NP
         uint32_t my_idx = 0xFFFFFFFFu;
         bool my_bad = false;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const uint64_t sum = wave_sum(acc[p]);
             if constexpr (!MW && sizeof(T) == 4) viol[p] &= (T)0x80000000u;
             const bool bad = __ballot(viol[p] != 0) != 0ull;
-            if (lane == p) { my_fp = sum; my_idx = idx[p]; my_bad = bad; }
+            if (lane == p) { my_idx = idx[p]; my_bad = bad; }
         }
         if constexpr (WG) {
             // partial results of this wave's row chunk -> wave 0 claims for the tile
