@@ -434,10 +434,18 @@ __device__ __forceinline__ T apply_fused(int k, T a, const RowMeta<T> &m, const 
 // The words of one row block of every candidate of a tile.  For U, the App. B
 // update cs1 <- cs1 & (cs1 << s) depends on phi (the a side) only: its chain is
 // computed once per a-child and shared by the TJ pairs of that child.
-template <typename T, bool MW, int OP, int TI, int TJ>
+// `need` (wave-uniform, bit p = pair p) names the pairs whose words are used.
+// With GUARD and several words per trace (where one step of one pair costs
+// lane moves and 64-bit shifts), the U chains of the other pairs, and of
+// a-children none of whose pairs is needed, are skipped and their words left
+// unspecified.  With one word per trace a step is two instructions, less than
+// the branches that would skip it, so every pair is computed.
+template <typename T, bool MW, int OP, int TI, int TJ, bool GUARD = false>
 __device__ __forceinline__ void tile_words(const T (&av)[TI], const T (&bv)[TJ], const RowMeta<T> &m,
-                                           const Rows<T> &rw, int lane, T (&w)[TI * TJ]) {
+                                           const Rows<T> &rw, int lane, T (&w)[TI * TJ],
+                                           uint32_t need = ~0u) {
     if constexpr (OP == LTL_U) {
+        constexpr uint32_t ROW = (1u << TJ) - 1u;
         T c1[TI];
 #pragma unroll
         for (int ii = 0; ii < TI; ++ii) {
@@ -445,19 +453,26 @@ __device__ __forceinline__ void tile_words(const T (&av)[TI], const T (&bv)[TJ],
 #pragma unroll
             for (int jj = 0; jj < TJ; ++jj) w[ii * TJ + jj] = bv[jj];
         }
+        constexpr bool G = GUARD && MW;
         const uint32_t k = rw.ksteps;
         for (uint32_t i = 0; i < k; ++i) {
             const uint32_t sh = 1u << i;
 #pragma unroll
-            for (int ii = 0; ii < TI; ++ii)
+            for (int ii = 0; ii < TI; ++ii) {
+                if (G && !((need >> (ii * TJ)) & ROW)) continue;
 #pragma unroll
                 for (int jj = 0; jj < TJ; ++jj) {
+                    if (G && !((need >> (ii * TJ + jj)) & 1u)) continue;
                     T &c2 = w[ii * TJ + jj];
                     c2 |= c1[ii] & shl_pos<T, MW>(c2, sh, m, lane);
                 }
+            }
             if (i + 1 < k) {
 #pragma unroll
-                for (int ii = 0; ii < TI; ++ii) c1[ii] &= shl_pos<T, MW>(c1[ii], sh, m, lane);
+                for (int ii = 0; ii < TI; ++ii) {
+                    if (G && !((need >> (ii * TJ)) & ROW)) continue;
+                    c1[ii] &= shl_pos<T, MW>(c1[ii], sh, m, lane);
+                }
             }
         }
     } else if constexpr (OP == (int)OP_FUSED4) {
@@ -683,6 +698,11 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                 const uint32_t cp = (uint32_t)__builtin_amdgcn_readlane((int)my_claim, p);
                 dp[p] = (cp < A.arena_cap) ? as_global<T>(arena_addr<T>(A, A.level_base + cp)) : (gptr<T>)nullptr;
             }
+            uint32_t wneed = 0;     // the pairs whose matrices are written
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                if (dp[p]) wneed |= 1u << p;
+            wneed = uniform(wneed);
             // a memory-bound pass (children re-read, new matrices written): several row
             // blocks of loads in flight per wave
             constexpr int UNR = 4;
@@ -708,7 +728,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                     if (blk + u < rb1) {
                         finish_meta<T, MW>(L[u].m, lane);
                         T w[NP];
-                        tile_words<T, MW, OP, TI, TJ>(L[u].av, L[u].bv, L[u].m, A.rows, lane, w);
+                        tile_words<T, MW, OP, TI, TJ, true>(L[u].av, L[u].bv, L[u].m, A.rows, lane, w, wneed);
                         const uint32_t r = (blk + u) * 64u + (uint32_t)lane;
 #pragma unroll
                         for (int p = 0; p < NP; ++p)
@@ -718,6 +738,12 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
             }
         }
     } else {
+        uint32_t vneed = 0;     // the pairs compared with a stored matrix
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            if (tp[p]) vneed |= 1u << p;
+        vneed = uniform(vneed);
+        if (!vneed) return;
         T diff[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) diff[p] = 0;
@@ -730,7 +756,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                 if (blk + u < rb1) {
                     finish_meta<T, MW>(cur[u].m, lane);
                     T w[NP];
-                    tile_words<T, MW, OP, TI, TJ>(cur[u].av, cur[u].bv, cur[u].m, A.rows, lane, w);
+                    tile_words<T, MW, OP, TI, TJ, true>(cur[u].av, cur[u].bv, cur[u].m, A.rows, lane, w, vneed);
 #pragma unroll
                     for (int p = 0; p < NP; ++p) diff[p] |= w[p] ^ cur[u].tv[p];
                 }
