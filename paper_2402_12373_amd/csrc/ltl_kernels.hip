@@ -265,17 +265,48 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
     return x;
 }
 
+// Lane-group swaps of gfx950: with lo = what the lower partner keeps and hi = what
+// the upper partner keeps, the swap leaves the partner's copy of the kept value in
+// the other register, so one swap and one add per 32-bit half do a halving step
+// without selecting by lane.  O = 32: lanes l and l + 32; O = 16: lanes l and
+// l + 16 within each 32-lane half.
+template <int O>
+__device__ __forceinline__ uint32_t swap_add_u32(uint32_t lo, uint32_t hi, uint32_t &carry_src) {
+    if constexpr (O == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        carry_src = r[1];
+        return r[0];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(lo, hi, false, false);
+        carry_src = r[1];
+        return r[0];
+    }
+}
+
+template <int O>
+__device__ __forceinline__ uint64_t swap_add_u64(uint64_t lo, uint64_t hi) {
+    uint32_t b0, b1;
+    const uint32_t a0 = swap_add_u32<O>((uint32_t)lo, (uint32_t)hi, b0);
+    const uint32_t a1 = swap_add_u32<O>((uint32_t)(lo >> 32), (uint32_t)(hi >> 32), b1);
+    return (((uint64_t)a1 << 32) | a0) + (((uint64_t)b1 << 32) | b0);
+}
+
 // One halving step of wave_sums: H sums held, the partner at xor distance O
 // gets half of them; the kept half absorbs what the partner hands over.
 template <int H, int O, int NP>
 __device__ __forceinline__ void halve_sums(uint64_t (&v)[NP], int lane) {
     if constexpr (H > 1) {
-        const bool up = (lane & O) != 0;
+        if constexpr (O >= 16) {
 #pragma unroll
-        for (int k = 0; k < H / 2; ++k) {
-            const uint64_t send = up ? v[k] : v[k + H / 2];
-            const uint64_t keep = up ? v[k + H / 2] : v[k];
-            v[k] = keep + (uint64_t)__shfl_xor((unsigned long long)send, O);
+            for (int k = 0; k < H / 2; ++k) v[k] = swap_add_u64<O>(v[k], v[k + H / 2]);
+        } else {
+            const bool up = (lane & O) != 0;
+#pragma unroll
+            for (int k = 0; k < H / 2; ++k) {
+                const uint64_t send = up ? v[k] : v[k + H / 2];
+                const uint64_t keep = up ? v[k + H / 2] : v[k];
+                v[k] = keep + (uint64_t)__shfl_xor((unsigned long long)send, O);
+            }
         }
         halve_sums<H / 2, O / 2, NP>(v, lane);
     }
