@@ -72,7 +72,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long", "batched"])
+    ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long", "batched", "hamming"])
+    ap.add_argument("--ham-length", type=int, default=4, help="hamming workload: length of the positive trace")
+    ap.add_argument("--ham-delta", type=int, default=2, help="hamming workload: bit distance of the negatives")
     ap.add_argument("--jobs", type=int, default=256, help="batched workload: number of jobs")
     ap.add_argument("--lanes", type=int, default=0,
                     help="jobs in flight (lanes of a batch executor: own stream, workspace slice, hash table); "
@@ -105,10 +107,21 @@ def main():
     if args.workload == "batched":
         return bench_batched(args)
     seeds = parse_seeds(args.seeds)
-    cfg = dict(synth.PRESETS[args.workload])
+    ops = None                       # every connective, negation anywhere
+    if args.workload == "hamming":
+        # Hamming(B, l, delta) with the U-free NNF operator set of the experiments (Sec. 7)
+        cfg = dict(num_props=2, bound=16, word_bits=32 if args.ham_length <= 32 else 64)
+        ops = (0xFF & ~(1 << ltl.U)) | ltl.OPS_NNF
+        insts = [synth.hamming_instance(s, args.ham_length, args.ham_delta) for s in seeds]
+        workload_desc = (f"hamming: Hamming(B, {args.ham_length}, {args.ham_delta}) over 2 props, 1+"
+                         f"{insts[0].num_traces - 1} traces, U-free NNF operator set")
+    else:
+        cfg = dict(synth.PRESETS[args.workload])
+        insts = [synth.preset_instance(args.workload, s)[0] for s in seeds]
+        workload_desc = (f"{args.workload}: {cfg['num_props']} props, {cfg['k']}+{cfg['k']} traces, "
+                         f"len {cfg['lo']}..{cfg['hi']}, p={cfg['p']}, planted size {cfg['size']}")
     if args.bound:
         cfg["bound"] = args.bound
-    insts = [synth.preset_instance(args.workload, s)[0] for s in seeds]
     dev = [ltl.spec_to_device(i) for i in insts]            # inputs resident in HBM
 
     if args.copy_calibration_mib:
@@ -139,7 +152,7 @@ def main():
         ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots, flags=timed_flags)
 
         def step():
-            res, dur, done = ex.run(dev, [cfg["bound"]] * len(dev))
+            res, dur, done = ex.run(dev, [cfg["bound"]] * len(dev), ops=ops)
             step.last = [(round(d - u, 3), round(d, 3)) for u, d in zip(dur, done)]
             return res, dur
     else:
@@ -147,7 +160,7 @@ def main():
             res, dur = [], []
             for d in dev:
                 a = time.perf_counter()
-                res.append(ctx.learn(d, cfg["bound"]))
+                res.append(ctx.learn(d, cfg["bound"], ops=ops))
                 dur.append((time.perf_counter() - a) * 1e3)
             return res, dur
 
@@ -192,7 +205,7 @@ def main():
         gc.disable()
         torch.cuda.synchronize()
         a = time.perf_counter()
-        sres = [ctx.learn(d, cfg["bound"]) for d in dev]
+        sres = [ctx.learn(d, cfg["bound"], ops=ops) for d in dev]
         torch.cuda.synchronize()
         sw = time.perf_counter() - a
         gc.enable()
@@ -227,7 +240,7 @@ def main():
     # host-resident specifications: every job uploads its traces (PCIe included)
     torch.cuda.synchronize()
     a = time.perf_counter()
-    hres = [ctx.learn(i, cfg["bound"]) for i in insts]
+    hres = [ctx.learn(i, cfg["bound"], ops=ops) for i in insts]
     torch.cuda.synchronize()
     hw = time.perf_counter() - a
 
@@ -246,9 +259,7 @@ def main():
         "slowest_step_jobs_start_end_ms": step_jobs[max(range(len(step_ms)), key=lambda i: step_ms[i])],
         "dtype": "u32" if cfg["word_bits"] == 32 else "u64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {cfg['num_props']} props, {cfg['k']}+{cfg['k']} traces, "
-                               f"len {cfg['lo']}..{cfg['hi']}, p={cfg['p']}, planted size {cfg['size']}, "
-                               f"cost bound {cfg['bound']}, seeds {args.seeds}",
+        "config": {"workload": f"{workload_desc}, cost bound {cfg['bound']}, seeds {args.seeds}",
                    "jobs_per_step": len(dev), "lanes": lanes, "hash_slots_log2": slots,
                    "u_operator": "carry" if args.ucarry else "doubling"},
         "trace_bits_per_s": round(value * tb_mean, 1),
@@ -269,8 +280,8 @@ def main():
     out["host_spec_candidates_per_s"] = round(sum(r.candidates for r in hres) / hw, 1)
 
     if not args.no_cpu_baseline:
-        levels = args.cpu_levels or {"long": 4, "batched": 6}.get(args.workload, 8)
-        out["cpu_baseline"] = cpu_baseline(insts, levels)
+        levels = args.cpu_levels or {"long": 4, "batched": 6, "hamming": 12}.get(args.workload, 8)
+        out["cpu_baseline"] = cpu_baseline(insts, levels, ops)
     print(json.dumps(out), flush=True)
     if lanes > 1:
         ex.close()
@@ -439,14 +450,14 @@ def cpu_model() -> str:
 CPU_SAMPLE_S = 20.0   # oracle jobs are added to the sample until this much time has gone by
 
 
-def oracle_rate(insts, levels, threads):
+def oracle_rate(insts, levels, threads, ops=None):
     """Candidates and seconds of the oracle over levels 1..`levels` of the jobs in order, the
     first job always and further ones while the elapsed time is below CPU_SAMPLE_S."""
     from oracle import oracle as O
     t0 = time.perf_counter()
     cands = jobs = 0
     for inst in insts:
-        r = O.learn(inst, levels, mode=O.MODE_EXPAND, threads=threads)
+        r = O.learn(inst, levels, op_mask=O.ALL_OPS if ops is None else ops, mode=O.MODE_EXPAND, threads=threads)
         cands += sum(r.level_candidates[:r.levels_done + 1])
         jobs += 1
         dt = time.perf_counter() - t0
@@ -457,14 +468,14 @@ def oracle_rate(insts, levels, threads):
     return cands, time.perf_counter() - t0, jobs
 
 
-def cpu_baseline(insts, levels):
+def cpu_baseline(insts, levels, ops=None):
     """The CPU oracle, unchanged, on a bounded sample: the first `levels` cost levels of the
     jobs (as many as fit in about CPU_SAMPLE_S) on up to 16 host threads, and a smaller sample
     on one thread."""
     threads = min(16, os.cpu_count() or 1)
-    cands, dt, jobs = oracle_rate(insts, levels, threads)
+    cands, dt, jobs = oracle_rate(insts, levels, threads, ops)
     l1 = max(1, levels - 2)
-    c1, d1, jobs1 = oracle_rate(insts, l1, 1)
+    c1, d1, jobs1 = oracle_rate(insts, l1, 1, ops)
     return {"value": round(cands / dt, 1), "unit": "candidates/s", "cores": threads, "kind": "oracle",
             "sample": f"levels 1..{levels} of {jobs} of the {len(insts)} jobs ({cands} candidates, {dt:.1f} s)",
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),

@@ -113,9 +113,17 @@ typedef struct {
 /* Cost-homomorphism restricted to an operator set (Sec. 2): cost(op phi psi) =
  * cost[op] + cost(phi) + cost(psi).  Disabled connectives are never used. */
 typedef struct {
-    uint32_t op_mask;           /* bit k enables connective k; bit LTL_ATOM must be set        */
+    uint32_t op_mask;           /* bit k enables connective k; bit LTL_ATOM must be set;
+                                   LTL_OPS_NNF may be added; other bits are an error (INVAL)  */
     uint32_t cost[8];           /* cost of each enabled connective, >= 1                       */
 } ltl_opset;
+
+/* op_mask flag: negation normal form, i.e. negation applies to atoms only (the
+ * formulae of the experiments of Sec. 7 are learned U-free and in this form; a
+ * U-free set simply leaves bit LTL_U clear).  The cache keeps each language at its
+ * least cost, so the children of a negation are exactly the entries of the atom
+ * level (cost[LTL_ATOM]); the canonical order is otherwise unchanged. */
+#define LTL_OPS_NNF (1u << 8)
 
 /* Kernel kinds for per-kind GPU time (LTL_CTX_TIMING). */
 enum {

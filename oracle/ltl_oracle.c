@@ -48,6 +48,7 @@
 #endif
 
 enum { O_ATOM = 0, O_NOT = 1, O_AND = 2, O_OR = 3, O_X = 4, O_F = 5, O_G = 6, O_U = 7 };
+#define O_NNF (1u << 8)   /* op_mask flag: negation of atoms only */
 enum { MODE_QUANT = 0, MODE_EXPAND = 1 };
 enum { ST_OK = 0, ST_NOT_FOUND = 1, ST_EINVAL = -1, ST_EOOM = -4, ST_EINCONS = -2 };
 
@@ -407,6 +408,9 @@ static int run_level(o_run *r, int c, o_batch *B) {
         if (!(r->op_mask & (1u << op))) continue;
         int x = c - r->cost[op];
         if (x < 1) continue;
+        /* negation normal form (op_mask bit 8, the U-free NNF formulae of Sec. 7):
+         * negation of atoms only, i.e. of the entries of the atom level */
+        if (op == O_NOT && (r->op_mask & O_NNF) && x != r->cost[O_ATOM]) continue;
         if (op == O_NOT || op == O_X || op == O_F || op == O_G) {
             if (!level_exists(r, x)) continue;
             for (int64_t e = 0; e < r->L[x].n; ++e) batch_emit(B, op, x, e, -1, 0);
@@ -445,6 +449,7 @@ static double now_s(void) {
 
 /*
  * Runs the learner.  cost[ATOM..U] >= 1; op_mask bit k enables connective k
+ * (bit 8, O_NNF: negation of atoms only)
  * (ATOM must be enabled).  bound is inclusive.  max_entries caps the number of
  * stored entries (0 = none); a level must be stored iff it has no solution and
  * it is below the bound; if storing it would exceed the cap, the run stops with
@@ -461,7 +466,8 @@ o_run *oracle_run(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bo
     r->first = -1; r->found_cost = -1; r->levels_done = 0;
     r->status = ST_EINVAL;
     int T = s->num_pos + s->num_neg;
-    if (bound < 1 || s->num_props < 1 || s->num_props > 32 || T < 1 || !(op_mask & 1u)) return r;
+    if (bound < 1 || s->num_props < 1 || s->num_props > 32 || T < 1 || !(op_mask & 1u) ||
+        (op_mask & ~(0xFFu | O_NNF))) return r;
     for (int k = 0; k < 8; ++k) if ((op_mask & (1u << k)) && cost[k] < 1) return r;
     for (int t = 0; t < T; ++t) if (trace_len(s, t) < 1) return r;
     for (int64_t q = 0; q < total_positions(s); ++q)

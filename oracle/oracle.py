@@ -128,6 +128,8 @@ def apply(spec: Spec, op: int, a: np.ndarray, b: Optional[np.ndarray] = None, mo
 
 UNIT_COST = [1] * 8
 ALL_OPS = 0xFF
+NNF = 1 << 8                                   # op_mask flag: negation of atoms only
+U_FREE_NNF = (ALL_OPS & ~(1 << U)) | NNF       # the operator set of the experiments of Sec. 7
 
 
 @dataclass

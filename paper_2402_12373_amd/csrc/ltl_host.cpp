@@ -557,7 +557,7 @@ extern "C" int ltl_job_create(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opse
     const uint64_t T = (uint64_t)spec->num_pos + spec->num_neg;
     if (T < 1 || T > 0x7FFFFFFFull || !spec->letters || !spec->offsets) return LTL_E_INVAL;
     if (cost_bound < 1 || cost_bound >= LTL_MAX_LEVELS) return LTL_E_INVAL;
-    if (!(ops->op_mask & 1u) || (ops->op_mask >> 8)) return LTL_E_INVAL;
+    if (!(ops->op_mask & 1u) || (ops->op_mask & ~(0xFFu | LTL_OPS_NNF))) return LTL_E_INVAL;
     for (int k = 0; k < 8; ++k)
         if ((ops->op_mask >> k) & 1u)
             if (ops->cost[k] < 1 || ops->cost[k] >= LTL_MAX_LEVELS) return LTL_E_INVAL;
@@ -672,6 +672,8 @@ static uint64_t build_blocks(ltl_job *j, uint32_t c, LevelInfo &lv, uint64_t &nt
             if (!((j->ops.op_mask >> op) & 1u)) continue;
             const int x = (int)c - (int)j->ops.cost[op];
             if (x < 1) continue;
+            // negation normal form: negations of atoms only
+            if (op == LTL_NOT && (j->ops.op_mask & LTL_OPS_NNF) && x != (int)j->ops.cost[LTL_ATOM]) continue;
             if (is_unary(op)) {
                 if (!has(x)) continue;
                 total += j->L[x].n;

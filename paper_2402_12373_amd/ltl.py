@@ -144,12 +144,21 @@ def _status_str(st: int) -> str:
         return f"status {st}"
 
 
-def opset(cost: Optional[Sequence[int]] = None, ops: Optional[Sequence[int]] = None) -> OpSet:
+OPS_NNF = 1 << 8      # op_mask flag (LTL_OPS_NNF): negation of atoms only
+
+
+def opset(cost: Optional[Sequence[int]] = None, ops: Optional[Sequence[int]] = None, nnf: bool = False) -> OpSet:
+    """Operator set: `ops` lists the enabled connectives (default all; ATOM is always
+    enabled) or is a raw op_mask integer (LTL_OPS_NNF included), `cost` their costs
+    (default 1), `nnf` restricts negation to atoms."""
     o = OpSet()
-    mask = 0
-    for op in (ops if ops is not None else range(8)):
-        mask |= 1 << op
-    o.op_mask = mask | 1
+    if isinstance(ops, int):
+        mask = ops
+    else:
+        mask = 0
+        for op in (ops if ops is not None else range(8)):
+            mask |= 1 << op
+    o.op_mask = mask | 1 | (OPS_NNF if nnf else 0)
     for k in range(8):
         o.cost[k] = (cost[k] if cost is not None else 1)
     return o

@@ -348,3 +348,38 @@ def test_tiles_spread_over_workgroups(ltl, ctx, lo, hi):
     inst = random_instance(rng, 2, 2048, 2048, lo, hi)
     _say("spread tiles", lo, hi)
     _level_by_level(ltl, ctx, inst, 4, max_entries_per_level=50)
+
+
+def _mask(nnf, u_free):
+    return ((O.ALL_OPS & ~(1 << 7)) if u_free else O.ALL_OPS) | (O.NNF if nnf else 0)
+
+
+@pytest.mark.parametrize("nnf,u_free", [(True, True), (True, False), (False, True)],
+                         ids=["nnf-ufree", "nnf", "ufree"])
+def test_operator_sets_parity(ctx, nnf, u_free):
+    """The operator sets of the experiments (Sec. 7): negation of atoms only, no U, or
+    both; tiny planted workload, 32 seeds."""
+    mask = _mask(nnf, u_free)
+    for seed in range(32):
+        inst, cfg = synth.preset_instance("tiny", seed)
+        _say("operator set", hex(mask), "tiny seed", seed)
+        g = ctx.learn(inst, cfg["bound"], ops=mask)
+        o = O.learn(inst, cfg["bound"], op_mask=mask)
+        _same(g, o, f"ops {mask:#x} tiny/{seed}")
+
+
+@pytest.mark.parametrize("length,delta", [(3, 1), (3, 2), (4, 2)])
+def test_hamming_parity(ltl, length, delta):
+    """Hamming(B, l, delta) with the U-free NNF operator set (Sec. 7): one positive trace
+    against every trace at bit distance delta.  Tiny matrices, minimal costs 10-15,
+    levels of up to 1.4 M new languages."""
+    c = ltl.Context(workspace_bytes=4 << 30, hash_slots_log2=24)
+    try:
+        for seed in range(2):
+            inst = synth.hamming_instance(seed, length, delta)
+            _say("hamming", length, delta, "seed", seed)
+            g = c.learn(inst, 16, ops=O.U_FREE_NNF)
+            o = O.learn(inst, 16, op_mask=O.U_FREE_NNF, mode=O.MODE_EXPAND, threads=16)
+            _same(g, o, f"hamming/{length}/{delta}/{seed}")
+    finally:
+        c.close()

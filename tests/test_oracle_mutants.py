@@ -2,7 +2,8 @@
 
 Each mutant is a copy of oracle/ltl_oracle.c with one plausible mistake (weak
 next, wrong G base case, off-by-one in the U or F quantifier, no dedup, swapped
-classes in the separation check, an extra X at the last position).  It is
+classes in the separation check, an extra X at the last position, negation of
+compound formulae in negation normal form).  It is
 compiled on the CPU and the pin tests are run against it; every mutant must
 make at least one pin fail.
 """
@@ -26,6 +27,7 @@ MUTANTS = {
     "no_dedup": ("if (!map_contains(r, pk, B->hv[k])) {", "if (1) {"),
     "swapped_classes": ("if (t < s->num_pos ? !v : v) return 0;", "if (t < s->num_pos ? v : !v) return 0;"),
     "U_expand_no_phi": ("nxt = B[i] || (A[i] && nxt);", "nxt = B[i] || nxt;"),
+    "nnf_ignored": ("if (op == O_NOT && (r->op_mask & O_NNF) && x != r->cost[O_ATOM]) continue;", ";"),
 }
 
 

@@ -186,8 +186,9 @@ def _bf_apply(op, A, B, inst):
     return tuple(out)
 
 
-def brute_force(inst, max_size):
-    """All syntax trees up to max_size (no dedup): min size per language, min separating size."""
+def brute_force(inst, max_size, nnf=False, u_free=False):
+    """All syntax trees up to max_size (no dedup): min size per language, min separating size.
+    nnf: negation only directly above an atom; u_free: no U."""
     offs = inst.offsets.astype(np.int64)
     by_size = {1: []}
     for p in range(inst.num_props):
@@ -195,8 +196,10 @@ def brute_force(inst, max_size):
     for s in range(2, max_size + 1):
         cur = []
         for op in (NOT, X, F, G):
+            if op == NOT and nnf and s - 1 != 1:
+                continue
             cur += [_bf_apply(op, A, None, inst) for A in by_size[s - 1]]
-        for op in (AND, OR, U):
+        for op in ((AND, OR) if u_free else (AND, OR, U)):
             for a in range(1, s - 1):
                 for A in by_size[a]:
                     for B in by_size[s - 1 - a]:
@@ -237,6 +240,40 @@ def test_bruteforce_levels_and_min_cost(seed):
             assert res.status == O.ST_OK and res.cost == cstar
         for c in range(1, top + 1):
             assert res.level_new[c] == counts[c], (c, res.level_new, counts)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bruteforce_levels_nnf_ufree(seed):
+    # the operator sets of the experiments (Sec. 7): negation of atoms only, with and without U
+    rng = np.random.default_rng(200 + seed)
+    nprops = 1 + seed % 2
+    inst = random_instance(rng, nprops, 2 + seed % 2, 2, 1, 4)
+    max_size = 6 if nprops == 2 else 7
+    for u_free in (False, True):
+        counts, cstar = brute_force(inst, max_size, nnf=True, u_free=u_free)
+        mask = (O.ALL_OPS & ~(1 << U) if u_free else O.ALL_OPS) | O.NNF
+        res = O.learn(inst, max_size, op_mask=mask, mode=O.MODE_EXPAND)
+        if cstar is None:
+            assert res.status == O.ST_NOT_FOUND
+        else:
+            assert res.status == O.ST_OK and res.cost == cstar
+        for c in range(1, res.levels_done + 1):
+            assert res.level_new[c] == counts[c], (u_free, c, res.level_new, counts)
+
+
+def test_nnf_solution_negates_atoms_only():
+    # a spec whose unrestricted minimal formula negates a compound formula:
+    # P = traces where p0 never holds, N = traces where it holds somewhere
+    inst = synth.from_traces([[0, 0, 0], [0, 0]], [[0, 1, 0], [1, 0]], 1)
+    full = O.learn(inst, 6)
+    nnf = O.learn(inst, 6, op_mask=O.ALL_OPS | O.NNF)
+    assert full.status == O.ST_OK and nnf.status == O.ST_OK
+    assert full.cost == 3          # not F p0
+    assert nnf.cost == 3           # G not p0
+    nodes = nnf.solution
+    for k, (op, a, b) in enumerate(nodes):
+        if op == NOT:
+            assert nodes[a][0] == 0, nodes     # the child of a negation is an atom
 
 
 def test_bruteforce_no_solution_spec():
