@@ -1153,11 +1153,20 @@ __global__ __launch_bounds__(256) void k_fallback(LevelArgs<T> A, uint32_t nword
     __shared__ uint32_t s_flag;
     __shared__ unsigned long long s_key;
     __shared__ uint32_t s_val;
+    __shared__ uint32_t s_words[256];
     const int lane = (int)__lane_id();
     const int wv = (int)(threadIdx.x >> 6);
     const int nw = (int)(blockDim.x >> 6);
-    for (uint32_t wi = 0; wi < nwords; ++wi) {
-        uint32_t bits = A.coll_bits[wi];
+    // the collider bitmap is read a block-wide chunk at a time (one coalesced word per
+    // thread); chunks without a collider are skipped, the others are walked word by word
+    for (uint32_t base = 0; base < nwords; base += blockDim.x) {
+        const uint32_t mine = (base + threadIdx.x < nwords) ? A.coll_bits[base + threadIdx.x] : 0u;
+        if (!__syncthreads_or(mine != 0u)) continue;
+        s_words[threadIdx.x] = mine;
+        __syncthreads();
+      for (uint32_t k = 0; k < blockDim.x && base + k < nwords; ++k) {
+        const uint32_t wi = base + k;
+        uint32_t bits = s_words[k];
         while (bits) {
             const uint32_t x = wi * 32u + (uint32_t)__ffs(bits) - 1u;
             bits &= bits - 1u;
@@ -1227,6 +1236,8 @@ __global__ __launch_bounds__(256) void k_fallback(LevelArgs<T> A, uint32_t nword
             }
             __syncthreads();
         }
+      }
+        __syncthreads();     // s_words is rewritten by the next chunk
     }
 }
 
