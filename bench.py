@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--no-timing", action="store_true",
                     help="no per-kernel HIP events (no kernel times, no roofline)")
     ap.add_argument("--cpu-levels", type=int, default=0,
-                    help="levels per job in the CPU-baseline sample (default: 4 for the long workload, "
+                    help="levels per job in the CPU-baseline sample (default: 4 for the long workload, 15 for hamming, "
                          "6 for batched, else 8)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device (a kernel of known traffic for "
@@ -280,7 +280,7 @@ def main():
     out["host_spec_candidates_per_s"] = round(sum(r.candidates for r in hres) / hw, 1)
 
     if not args.no_cpu_baseline:
-        levels = args.cpu_levels or {"long": 4, "batched": 6, "hamming": 12}.get(args.workload, 8)
+        levels = args.cpu_levels or {"long": 4, "batched": 6, "hamming": 15}.get(args.workload, 8)
         out["cpu_baseline"] = cpu_baseline(insts, levels, ops)
     print(json.dumps(out), flush=True)
     if lanes > 1:
