@@ -61,10 +61,11 @@ def parse_seeds(s: str):
 # integer operations:
 #   connective: NOT 2, AND/OR 1, X 1, F 2 (x | -x), G 5, ATOM 0,
 #               U by doubling (App. B, k steps) 5k-2, U by the carry adder 5
-#   fingerprint 5 (premix: two shift-xor pairs; one 32x32->64 multiply-add)
+#   fingerprint 6 (premix: two shift-xor pairs and the row key added between them;
+#               one 32x32->64 multiply-add)
 #   separation 2 (xor with the expected bit, or into the violation word)
 OP_OPS = {"atom": 0, "not": 2, "and": 1, "or": 1, "x": 1, "f": 2, "g": 5}
-FP_SEP_OPS = 5 + 2
+FP_SEP_OPS = 6 + 2
 
 
 def main():

@@ -235,27 +235,36 @@ __device__ __forceinline__ T apply(T a, T b, const RowMeta<T> &m, const Rows<T> 
 }
 
 // ---------------------------------------------------------------------------
-// Fingerprint: fp = sum over 32-bit halves h of premix(h) * key (mod 2^64),
+// Fingerprint: fp = sum over 32-bit halves h of premix(h, key) * key (mod 2^64),
 // keys random odd 32-bit numbers per half-word (one 32x32->64 multiply-add
-// each).  premix is the bijection y = w ^ w>>8; y ^ y>>16.  Two matrices that
-// differ in one half-word never collide (a nonzero 33-bit difference times an
-// odd 32-bit key is nonzero below 2^64); premix keeps the 2-adic valuation of
-// any difference below 8, so that differences confined to the top bits (the
-// position-0 bits) still spread over the sum.  Only a function of the matrix
-// matters: every match is confirmed by a full compare.
+// each).  premix is the bijection y = w ^ w>>8; y += key; y ^ y>>16.
+// - Two matrices that differ in one half-word never collide (a nonzero 33-bit
+//   difference times an odd 32-bit key is nonzero below 2^64).
+// - The shifts keep the 2-adic valuation of any difference below 8, so that
+//   differences confined to the top bits (the position-0 bits) still spread over
+//   the sum.
+// - The key added between the two shift stages makes the value table of each
+//   row its own (the carries depend on the row).  Without it a short trace,
+//   whose word takes few values, contributes one of a few multiples of a shared
+//   constant times its key, and two matrices collide whenever the keys satisfy a
+//   small integer relation over the rows they differ in: 37 pairs of distinct
+//   languages shared a fingerprint among the 6.9 M of a length-4 Hamming
+//   specification, none with the added key.
+// Only a function of the matrix matters: every match is confirmed by a full
+// compare.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t premix(uint32_t w) {
-    uint32_t y = w ^ (w >> 8);
+__device__ __forceinline__ uint32_t premix(uint32_t w, uint32_t key) {
+    uint32_t y = (w ^ (w >> 8)) + key;
     return y ^ (y >> 16);
 }
 
 template <typename T>
 __device__ __forceinline__ void fp_add(uint64_t &acc, T w, const RowMeta<T> &m) {
     if constexpr (sizeof(T) == 4) {
-        acc += (uint64_t)premix((uint32_t)w) * (uint64_t)m.k0;
+        acc += (uint64_t)premix((uint32_t)w, m.k0) * (uint64_t)m.k0;
     } else {
-        acc += (uint64_t)premix((uint32_t)w) * (uint64_t)m.k0;
-        acc += (uint64_t)premix((uint32_t)(w >> 32)) * (uint64_t)m.k1;
+        acc += (uint64_t)premix((uint32_t)w, m.k0) * (uint64_t)m.k0;
+        acc += (uint64_t)premix((uint32_t)(w >> 32), m.k1) * (uint64_t)m.k1;
     }
 }
 
