@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
     ap.add_argument("--ucarry", action="store_true", help="U by carry-chain add instead of doubling")
+    ap.add_argument("--big-alone", action="store_true",
+                    help="batch lanes take turns for whole-row levels (LTL_BATCH_BIG_ALONE)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="no per-kernel HIP events (no kernel times, no roofline)")
@@ -150,7 +152,8 @@ def main():
     ctx_bytes = ws_bytes if lanes == 1 else (ws_bytes // (lanes + 1)) & ~255
     ctx = ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots, flags=full_flags if lanes > 1 else timed_flags)
     if lanes > 1:
-        ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots, flags=timed_flags)
+        ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots,
+                       flags=timed_flags | (ltl.BATCH_BIG_ALONE if args.big_alone else 0))
 
         def step():
             res, dur, done = ex.run(dev, [cfg["bound"]] * len(dev), ops=ops)
@@ -321,7 +324,8 @@ def bench_batched(args):
     ctx.close()
     print(f"plain path: {len(plain)} jobs in {t_plain:.2f} s", file=sys.stderr, flush=True)
     # batched: a batch executor (lanes created once, outside the timed region)
-    ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots)
+    ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots,
+                   flags=ltl.BATCH_BIG_ALONE if args.big_alone else 0)
     ex.run(dev[:lanes], bounds[:lanes])                     # warm-up: one job per lane
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -182,9 +182,14 @@ int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t
  * lanes, 256-byte aligned) and its own context, so the levels of different jobs
  * overlap on the device; every job's result equals that of ltl_learn on a
  * context with the same options and a workspace of the slice's size. */
+/* Batch flag: the whole-row levels (the device-filling ones) of different lanes run
+ * one at a time; smaller levels still overlap.  For mixes dominated by large jobs,
+ * whose big levels slow each other down when they share the device. */
+#define LTL_BATCH_BIG_ALONE 0x100u
+
 typedef struct {
     int32_t  device;
-    uint32_t flags;              /* LTL_CTX_* for every job                                  */
+    uint32_t flags;              /* LTL_CTX_* for every job, and LTL_BATCH_BIG_ALONE        */
     void    *workspace;          /* device pointer, caller-owned, split evenly among lanes   */
     uint64_t workspace_bytes;
     uint32_t lanes;              /* jobs in flight at once, 1..64                            */

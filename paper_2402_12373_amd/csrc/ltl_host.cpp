@@ -73,6 +73,7 @@ struct ltl_ctx {
     hipStream_t s = nullptr;
     hipStream_t aux = nullptr;       // second stream of the context (default priority)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::mutex *big_mu = nullptr;    // batch lanes with LTL_BATCH_BIG_ALONE: one whole-row level at a time
     std::vector<hipEvent_t> events;  // timing events, kept across jobs (created on first use)
     bool busy = false;
     char *pinned = nullptr;          // page-locked host staging: two block tables + counters
@@ -737,6 +738,9 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     };
     const uint64_t nwa = align_up(nw, 64);                 // words, so the bitmaps stay aligned
     const bool split = ntiles < SPLIT_TILES;
+    // batch lanes that take turns for whole-row levels: held until the level's work is done
+    std::unique_lock<std::mutex> big_turn;
+    if (!split && j->ctx->big_mu) big_turn = std::unique_lock<std::mutex>(*j->ctx->big_mu);
     // bitmap | coll_bits | fb_bits, cleared at once
     // bitmap | coll_bits | fb_bits | cand_viol | cand_fp (row-split levels whose tiles
     // span several workgroups); cleared at once
@@ -1270,6 +1274,7 @@ extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *op
 // lane 0 of each run.
 struct ltl_batch {
     ltl_batch_opts o{};
+    std::mutex big_mu;                     // LTL_BATCH_BIG_ALONE: turns for whole-row levels
     std::vector<hipStream_t> streams;
     std::vector<ltl_ctx *> ctxs;
     std::vector<std::thread> workers;
@@ -1374,7 +1379,7 @@ extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
         }
         ltl_ctx_opts co{};
         co.device = o->device;
-        co.flags = o->flags;
+        co.flags = o->flags & ~LTL_BATCH_BIG_ALONE;
         co.workspace = (char *)o->workspace + (uint64_t)l * slice;
         co.workspace_bytes = slice;
         co.stream = b->streams[l];
@@ -1383,6 +1388,7 @@ extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
         co.fp_bits = o->fp_bits;
         co.max_entries = o->max_entries;
         st = ltl_ctx_create(&co, &b->ctxs[l]);
+        if (st == LTL_OK && (o->flags & LTL_BATCH_BIG_ALONE)) b->ctxs[l]->big_mu = &b->big_mu;
     }
     if (st != LTL_OK) {
         ltl_batch_destroy(b);
