@@ -386,3 +386,27 @@ def test_hamming_parity(ltl, length, delta):
             assert g.colliders == 0, (length, delta, seed, g.colliders)
     finally:
         c.close()
+
+
+def test_batch_big_levels_take_turns(ltl):
+    """LTL_BATCH_BIG_ALONE: lanes take turns for whole-row levels (scale jobs reach levels of
+    10^5-10^6 candidates); every result equals the run without the flag and the plain run."""
+    insts = [synth.preset_instance("scale", s)[0] for s in (3, 4, 1, 6)]
+    dev = [ltl.spec_to_device(i) for i in insts]
+    bound = synth.PRESETS["scale"]["bound"]
+    key = lambda r: (r.status, r.cost, r.level_new, r.level_candidates, r.solution_index, r.solution)
+    turns = ltl.Batch(lanes=3, workspace_bytes=48 << 30, hash_slots_log2=24, flags=ltl.BATCH_BIG_ALONE)
+    free = ltl.Batch(lanes=3, workspace_bytes=48 << 30, hash_slots_log2=24)
+    plain = ltl.Context(workspace_bytes=16 << 30, hash_slots_log2=24)
+    try:
+        a, _, _ = turns.run(dev, [bound] * len(dev))
+        b, _, _ = free.run(dev, [bound] * len(dev))
+        for i, (x, y) in enumerate(zip(a, b)):
+            _say("big-alone job", i)
+            assert key(x) == key(y), i
+            assert key(x) == key(plain.learn(dev[i], bound)), i
+        assert max(sum(1 for c in r.level_candidates if c >= 131072) for r in a) >= 1   # whole-row levels ran
+    finally:
+        turns.close()
+        free.close()
+        plain.close()
