@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
     ap.add_argument("--ucarry", action="store_true", help="U by carry-chain add instead of doubling")
+    ap.add_argument("--ruc", action="store_true",
+                    help="relaxed uniqueness check (LTL_CTX_RUC): fingerprint match taken as equality, no compare")
     ap.add_argument("--big-alone", action="store_true",
                     help="batch lanes take turns for whole-row levels (LTL_BATCH_BIG_ALONE)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -140,7 +142,7 @@ def main():
     free, total = torch.cuda.mem_get_info()
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     slots = 26 if args.workload != "tiny" else 20
-    ucarry = ltl.CTX_U_CARRY if args.ucarry else 0
+    ucarry = (ltl.CTX_U_CARRY if args.ucarry else 0) | (ltl.CTX_RUC if args.ruc else 0)
     # timed steps: one event pair per level (level GPU time, for the roofline); the one-stream
     # pass: events around every kernel group (time per kernel kind)
     timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
@@ -265,7 +267,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{workload_desc}, cost bound {cfg['bound']}, seeds {args.seeds}",
                    "jobs_per_step": len(dev), "lanes": lanes, "hash_slots_log2": slots,
-                   "u_operator": "carry" if args.ucarry else "doubling"},
+                   "u_operator": "carry" if args.ucarry else "doubling",
+                   "dedup": "relaxed (fingerprint only)" if args.ruc else "exact (fingerprint + full compare)"},
         "trace_bits_per_s": round(value * tb_mean, 1),
         "jobs_per_s": round(len(results) / wall, 3),
         "job_ms_p50": round(statistics.median(job_ms), 3),

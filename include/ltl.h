@@ -72,6 +72,13 @@ typedef struct ltl_job ltl_job;
                                     around each kernel group)                                  */
 #define LTL_CTX_TIMING_LEVEL 0x4u /* record only the GPU time of each level: one event pair from
                                     its first to its last kernel (level_ms; kernel_ms stays 0) */
+#define LTL_CTX_RUC       0x8u   /* relaxed uniqueness check (Sec. 5): a candidate whose 64-bit
+                                    fingerprint is already cached is taken as that language
+                                    without the full compare (no verification pass, no exact
+                                    re-check).  Results equal the default exact mode unless two
+                                    distinct matrices share a fingerprint; then a language can
+                                    be dropped (the formula may not be minimal) and level counts
+                                    are counts of distinct fingerprints                         */
 
 typedef struct {
     int32_t  device;            /* HIP device ordinal used by every call of this context        */

@@ -978,12 +978,15 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
                                    j->entry_slot, new_owner, j->store, false, grid_new, j->s));
         }
     }
+    // relaxed uniqueness check: nothing is compared, so no claim needs writing for the
+    // verification (has_member stays clear) and there is no verification pass
+    const bool ruc = (j->ctx->o.flags & LTL_CTX_RUC) != 0;
     if (write_pass) {
-        Timer tm(j, LTL_K_MATERIALIZE, ncls + 1);
-        HIP_TRY(Launch<T>::mark_members(A, nc, j->s));
+        Timer tm(j, LTL_K_MATERIALIZE, ruc ? ncls : ncls + 1);
+        if (!ruc) HIP_TRY(Launch<T>::mark_members(A, nc, j->s));
         HIP_TRY(launch_level(false, true));
     }
-    {
+    if (!ruc) {
         Timer tm(j, LTL_K_VERIFY, merged_eval ? 1u : ncls);
         HIP_TRY(launch_level(true));
     }
@@ -996,6 +999,8 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t n_new = hc.n_new;
     // a level that is not stored need not write its new entries (check-only)
     if (!lv.stored) lv.alg_bytes -= (uint64_t)std::min<uint64_t>(n_new, C) * j->cm_bytes;
+    // relaxed check: the candidates that joined a cached language are not compared
+    if (ruc) lv.alg_bytes -= (C - std::min<uint64_t>(n_new, C)) * j->cm_bytes;
     lv.colliders = 0;
     if (hc.n_coll) {
         // A fingerprint group held two different matrices.  Exact re-check: every

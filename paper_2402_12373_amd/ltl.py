@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "libltl.so")
 LTL_OK, LTL_NOT_FOUND = 0, 1
 LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG, LTL_E_OOM, LTL_E_DEVICE, LTL_E_STATE = -1, -2, -3, -4, -5, -6
 ATOM, NOT, AND, OR, X, F, G, U = range(8)
-CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL = 0x1, 0x2, 0x4
+CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL, CTX_RUC = 0x1, 0x2, 0x4, 0x8
 BATCH_BIG_ALONE = 0x100    # batch flag: whole-row levels of different lanes take turns
 SPEC_DEVICE = 0x1
 MAX_LEVELS, MAX_NODES, K_KINDS = 64, 64, 6

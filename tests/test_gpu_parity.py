@@ -410,3 +410,38 @@ def test_batch_big_levels_take_turns(ltl):
         turns.close()
         free.close()
         plain.close()
+
+
+def test_relaxed_uniqueness_check(ltl):
+    """LTL_CTX_RUC (the paper's relaxed check, Sec. 5): with full fingerprints the results
+    equal the exact mode's; with fingerprints cut to 4 bits the exact mode still matches the
+    oracle while the relaxed one drops languages."""
+    key = lambda r: (r.status, r.cost, r.level_new, r.level_candidates, r.solution_index, r.solution)
+    exact = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22)
+    ruc = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, flags=ltl.CTX_RUC)
+    try:
+        for seed in range(16):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            _say("ruc tiny seed", seed)
+            assert key(ruc.learn(inst, cfg["bound"])) == key(exact.learn(inst, cfg["bound"])), seed
+        inst = synth.hamming_instance(0, 3, 2)
+        assert key(ruc.learn(inst, 16, ops=O.U_FREE_NNF)) == key(exact.learn(inst, 16, ops=O.U_FREE_NNF))
+    finally:
+        exact.close()
+        ruc.close()
+    exact4 = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, fp_bits=4)
+    ruc4 = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, fp_bits=4, flags=ltl.CTX_RUC)
+    try:
+        differs = 0
+        for seed in range(8):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            o = O.learn(inst, cfg["bound"])
+            _same(exact4.learn(inst, cfg["bound"]), o, f"exact fp4 tiny/{seed}")
+            r = ruc4.learn(inst, cfg["bound"])
+            differs += int(key(r)[:4] != (o.status, o.cost, o.level_new, o.level_candidates))
+            # a relaxed level never holds more languages than the exact one
+            assert r.level_new[1] <= o.level_new[1]
+        assert differs > 0
+    finally:
+        exact4.close()
+        ruc4.close()
