@@ -271,6 +271,21 @@ int ltl_eval_level(ltl_job *job, uint32_t cost, ltl_level_stats *stats);
  * LTL_NOT_FOUND while none has, or the error that stopped the job). */
 int ltl_job_result(ltl_job *job, ltl_result *out);
 
+/* The overfitting formula of (P, N) (Sec. 2): the disjunction, over the traces of
+ * P in order, of tr's description, in which each position's letter is the
+ * conjunction of every proposition (in index order), negated when it is absent,
+ * chained to the next position by X, and the last letter conjoined with not X true
+ * (the last position; true = p0 or not p0).  Its language is exactly P, so it
+ * separates (P, N); the learner of Sec. 3 enumerates below its cost and returns it
+ * when nothing cheaper separates.  Host-only (no device call): reads the spec's host
+ * buffers.  Writes the postfix nodes (root last, no shared subformulas) into
+ * buf[0..cap) and their cost under `ops` into *cost.  Errors: LTL_E_INVAL (null
+ * pointer, device spec, invalid spec or letters, an operator set without NOT, AND,
+ * OR or X, or with LTL_OPS_NNF: not X true negates a compound formula), LTL_E_OOM
+ * (more than cap nodes; *num_nodes then holds the number needed). */
+int ltl_overfit(const ltl_spec *spec, const ltl_opset *ops, ltl_node *buf, uint32_t cap, uint32_t *num_nodes,
+                uint64_t *cost);
+
 /* Formula of stored entry `entry` of level `cost` (postfix nodes into buf, at
  * most cap).  Errors: LTL_E_INVAL (no such entry, cap too small). */
 int ltl_job_formula(ltl_job *job, uint32_t cost, uint64_t entry, ltl_node *buf, uint32_t cap,

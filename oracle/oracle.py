@@ -185,6 +185,56 @@ class Run:
         return out
 
 
+def overfit(inst, cost=UNIT_COST):
+    """The overfitting formula of (P, N), written out from its definition (Sec. 2):
+      overfit(letter)   = AND over the propositions of p_k (present) or NOT p_k (absent)
+      overfit(a . tr)   = overfit(a) AND X overfit(tr)      (tr non-empty)
+      overfit(a)        = overfit(a) AND NOT X true           (a the last letter: the trace ends)
+      overfit(P, N)     = OR over tr in P of overfit(tr);  true = p0 OR NOT p0
+    (The printed base case puts the end marker under one more X, which with the strong X of
+    Sec. 2 would describe traces one letter longer; the reading above gives L = P.)
+    Returns (postfix nodes (op, a, b) with the root last, cost)."""
+    nodes = []
+
+    def emit(op, a=0, b=0):
+        nodes.append((op, a, b))
+        return len(nodes) - 1
+
+    def letter(bits):
+        root = None
+        for k in range(inst.num_props):
+            lit = emit(ATOM, k)
+            if not (bits >> k) & 1:
+                lit = emit(NOT, lit)
+            root = lit if root is None else emit(AND, root, lit)
+        return root
+
+    def trace(letters):
+        head = letter(int(letters[0]))
+        if len(letters) == 1:
+            tru = emit(OR, emit(ATOM, 0), emit(NOT, emit(ATOM, 0)))
+            return emit(AND, head, emit(NOT, emit(X, tru)))
+        return emit(AND, head, emit(X, trace(letters[1:])))
+
+    root = None
+    for t in range(inst.num_pos):
+        o, e = int(inst.offsets[t]), int(inst.offsets[t + 1])
+        f = trace(inst.letters[o:e])
+        root = f if root is None else emit(OR, root, f)
+    return nodes, sum(cost[op] for op, _, _ in nodes)
+
+
+def formula_tree(nodes, k=None):
+    """Postfix nodes -> nested tuples (shape only), for comparing encodings of one formula."""
+    k = len(nodes) - 1 if k is None else k
+    op, a, b = nodes[k]
+    if op == ATOM:
+        return (ATOM, a)
+    if op in (NOT, X, F, G):
+        return (op, formula_tree(nodes, a))
+    return (op, formula_tree(nodes, a), formula_tree(nodes, b))
+
+
 def learn(inst, bound: int, cost=UNIT_COST, op_mask: int = ALL_OPS, mode: int = MODE_QUANT, threads: int = 1,
           max_entries: int = 0) -> Result:
     spec = Spec.of(inst)

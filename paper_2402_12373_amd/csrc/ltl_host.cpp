@@ -1171,6 +1171,56 @@ static int emit_candidate(ltl_job *j, uint32_t level, uint32_t x, ltl_node *buf,
     return LTL_OK;
 }
 
+// The overfitting formula (Sec. 2), built position by position from the end of each
+// trace of P; nodes are counted even when buf is full, so the caller learns the size.
+extern "C" int ltl_overfit(const ltl_spec *spec, const ltl_opset *ops, ltl_node *buf, uint32_t cap,
+                           uint32_t *num_nodes, uint64_t *cost) {
+    if (!spec || !ops || !num_nodes || !cost || (!buf && cap)) return LTL_E_INVAL;
+    if (spec->flags & LTL_SPEC_DEVICE) return LTL_E_INVAL;
+    if (!spec->letters || !spec->offsets || spec->num_pos < 1) return LTL_E_INVAL;
+    if (spec->num_props < 1 || spec->num_props > 32) return LTL_E_INVAL;
+    const uint32_t need_ops = (1u << LTL_ATOM) | (1u << LTL_NOT) | (1u << LTL_AND) | (1u << LTL_OR) | (1u << LTL_X);
+    if ((ops->op_mask & need_ops) != need_ops || (ops->op_mask & LTL_OPS_NNF)) return LTL_E_INVAL;
+    if (ops->op_mask & ~(0xFFu | LTL_OPS_NNF)) return LTL_E_INVAL;
+    for (int k = 0; k < 8; ++k)
+        if (((ops->op_mask >> k) & 1u) && ops->cost[k] < 1) return LTL_E_INVAL;
+    const uint32_t A = spec->num_props;
+    uint32_t n = 0;
+    uint64_t c = 0;
+    auto node = [&](uint32_t op, uint32_t a, uint32_t b) -> uint32_t {
+        if (n < cap) buf[n] = ltl_node{op, a, b};
+        c += ops->cost[op];
+        return n++;
+    };
+    uint32_t disj = 0;
+    for (uint32_t t = 0; t < spec->num_pos; ++t) {
+        const uint64_t o0 = spec->offsets[t], o1 = spec->offsets[t + 1];
+        if (o1 <= o0) return LTL_E_INVAL;                    // empty trace
+        // not X true: the last position
+        const uint32_t p0 = node(LTL_ATOM, 0, 0);
+        const uint32_t np0 = node(LTL_NOT, node(LTL_ATOM, 0, 0), 0);
+        const uint32_t tru = node(LTL_OR, p0, np0);
+        const uint32_t xt = node(LTL_X, tru, 0);
+        uint32_t rest = node(LTL_NOT, xt, 0);
+        for (uint64_t q = o1; q-- > o0;) {
+            const uint32_t letter = spec->letters[q];
+            if (A < 32 && (letter >> A)) return LTL_E_INVAL;
+            uint32_t conj = 0;
+            for (uint32_t k = 0; k < A; ++k) {
+                uint32_t lit = node(LTL_ATOM, k, 0);
+                if (!((letter >> k) & 1u)) lit = node(LTL_NOT, lit, 0);
+                conj = k ? node(LTL_AND, conj, lit) : lit;
+            }
+            rest = node(LTL_AND, conj, rest);
+            if (q > o0) rest = node(LTL_X, rest, 0);
+        }
+        disj = t ? node(LTL_OR, disj, rest) : rest;
+    }
+    *num_nodes = n;
+    *cost = c;
+    return n <= cap ? LTL_OK : LTL_E_OOM;
+}
+
 extern "C" int ltl_job_formula(ltl_job *j, uint32_t cost, uint64_t entry, ltl_node *buf, uint32_t cap,
                                uint32_t *num_nodes) {
     if (!j || !buf || !num_nodes || cost > j->levels_done || cost >= j->L.size()) return LTL_E_INVAL;

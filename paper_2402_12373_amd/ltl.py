@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -31,7 +31,7 @@ KERNEL_KINDS = ("eval", "verify", "materialize", "compact", "fallback", "intake"
 EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", "ltl_batch_create", "ltl_batch_run",
            "ltl_batch_destroy", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
-           "ltl_status_str")
+           "ltl_status_str", "ltl_overfit")
 
 
 class LTLError(RuntimeError):
@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH):
     L.ltl_eval_level.restype = C.c_int
     L.ltl_job_result.argtypes = [C.c_void_p, P(Result)]
     L.ltl_job_result.restype = C.c_int
+    L.ltl_overfit.argtypes = [P(Spec), P(OpSet), P(Node), C.c_uint32, P(C.c_uint32), P(C.c_uint64)]
+    L.ltl_overfit.restype = C.c_int
     L.ltl_job_formula.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P(Node), C.c_uint32, P(C.c_uint32)]
     L.ltl_job_formula.restype = C.c_int
     L.ltl_job_dump_cm.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, C.c_void_p, C.c_uint64]
@@ -219,6 +221,38 @@ class SpecBuffers:
             self.c.flags = SPEC_DEVICE
             self.c.letters = self.letters.data_ptr()
             self.c.offsets = self.offsets.data_ptr()
+
+
+def overfit(inst, cost=None, ops=None):
+    """The overfitting formula of (P, N) (Sec. 2) and its cost: (postfix nodes (op, a, b), root
+    last; cost under the operator set).  Host-only, no device."""
+    L = load_library()
+    sb = SpecBuffers(inst)
+    o = opset(cost, ops)
+    n, c = C.c_uint32(0), C.c_uint64(0)
+    st = L.ltl_overfit(C.byref(sb.c), C.byref(o), None, 0, C.byref(n), C.byref(c))
+    if st not in (LTL_OK, LTL_E_OOM):
+        raise LTLError(st, "ltl_overfit")
+    buf = (Node * max(1, n.value))()
+    st = L.ltl_overfit(C.byref(sb.c), C.byref(o), buf, n.value, C.byref(n), C.byref(c))
+    if st != LTL_OK:
+        raise LTLError(st, "ltl_overfit")
+    return [(int(buf[k].op), int(buf[k].a), int(buf[k].b)) for k in range(n.value)], int(c.value)
+
+
+def learn_complete(ctx: "Context", inst_or_spec, inst=None, cost=None, ops=None) -> LearnResult:
+    """The learner of Sec. 3: enumerate the cost levels below the cost of overfitting; if no
+    formula there separates (P, N), the overfitting formula is the answer (status LTL_OK,
+    solution_index None).  `inst` gives the host traces when inst_or_spec is a device spec.
+    When the cost of overfitting exceeds the level range, the enumeration stops at the last
+    level and its result is returned as is (no claim of minimality for a fallback)."""
+    host = inst if inst is not None else inst_or_spec
+    nodes, co = overfit(host, cost, ops)
+    bound = min(co - 1, MAX_LEVELS - 1)
+    r = ctx.learn(inst_or_spec, bound, cost, ops)
+    if r.status == LTL_NOT_FOUND and bound == co - 1:
+        return replace(r, status=LTL_OK, cost=co, solution=nodes, solution_index=None)
+    return r
 
 
 def spec_to_device(inst, device="cuda"):

@@ -7,6 +7,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -102,3 +103,22 @@ def test_hamming_generator_size():
     from paper_2402_12373_amd import synth
     inst = synth.hamming_instance(0, 12, 2)
     assert inst.num_pos == 1 and inst.num_neg == 24 * 23 // 2
+
+
+def test_overfit_matches_oracle_and_rejects_bad_sets():
+    """ltl_overfit is host-only: the library's formula equals the oracle's (same tree, same
+    cost) for random specifications and operator costs; NNF and sets without X are refused."""
+    from oracle import oracle as O
+    from ltl_text import random_instance
+    from paper_2402_12373_amd import ltl
+    rng = np.random.default_rng(17)
+    for seed in range(12):
+        inst = random_instance(rng, 1 + seed % 3, 1 + seed % 4, 2, 1, 6)
+        cost = [int(c) for c in rng.integers(1, 4, size=8)]
+        nodes, c = ltl.overfit(inst, cost=cost)
+        onodes, oc = O.overfit(inst, cost)
+        assert c == oc and O.formula_tree(nodes) == O.formula_tree(onodes), seed
+    inst = random_instance(rng, 2, 2, 2, 1, 4)
+    for ops in (0xFF | ltl.OPS_NNF, 0xFF & ~(1 << ltl.X), 0xFF & ~(1 << ltl.OR)):
+        with pytest.raises(ltl.LTLError):
+            ltl.overfit(inst, ops=ops)

@@ -445,3 +445,22 @@ def test_relaxed_uniqueness_check(ltl):
     finally:
         exact4.close()
         ruc4.close()
+
+
+def test_learn_complete(ltl, ctx, monkeypatch):
+    """The learner of Sec. 3 (enumerate below the cost of overfitting, else return the
+    overfitting formula).  Enumeration path: the oracle's result.  Fallback path: with the
+    overfitting cost stubbed to 2 only the atom level is enumerated; no atom separates, so the
+    result is the overfitting formula at that cost."""
+    for seed in range(8):
+        inst, cfg = synth.preset_instance("tiny", seed)
+        r = ltl.learn_complete(ctx, inst)
+        _, co = ltl.overfit(inst)
+        o = O.learn(inst, min(co - 1, 63))
+        _same(r, o, f"complete tiny/{seed}")
+    inst = synth.from_traces([[1, 0]], [[1, 1], [0, 0], [1]], 1)
+    assert O.learn(inst, 1).status == O.ST_NOT_FOUND
+    nodes, _ = ltl.overfit(inst)
+    monkeypatch.setattr(ltl, "overfit", lambda i, cost=None, ops=None: (nodes, 2))
+    r = ltl.learn_complete(ctx, inst)
+    assert (r.status, r.cost, r.solution, r.solution_index, r.levels_done) == (ltl.LTL_OK, 2, nodes, None, 1)

@@ -374,3 +374,50 @@ def test_bound_and_atom_level():
     inst = synth.from_traces([[1, 0, 1]], [[1, 1, 1]], 1)      # needs X / G style formulas
     res1 = O.learn(inst, 1)
     assert res1.status == O.ST_NOT_FOUND and res1.levels_done == 1
+
+
+# ---------------------------------------------------------------- overfitting (Sec. 2)
+
+def _overfit_closed_cost(inst):
+    """Unit costs: per trace of length n with m_i absent propositions at position i:
+    sum_i (A + m_i + (A - 1)) literals and their ANDs, n ANDs joining a position to the rest,
+    n - 1 X, and 6 for NOT X (p0 OR NOT p0); traces joined by |P| - 1 ORs."""
+    A = inst.num_props
+    total = 0
+    for t in range(inst.num_pos):
+        o, e = int(inst.offsets[t]), int(inst.offsets[t + 1])
+        n = e - o
+        absent = sum(A - bin(int(l) & ((1 << A) - 1)).count("1") for l in inst.letters[o:e])
+        total += (2 * A - 1) * n + absent + n + (n - 1) + 6
+    return total + inst.num_pos - 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_overfit_language_is_exactly_P(seed):
+    rng = np.random.default_rng(300 + seed)
+    nprops = 1 + seed % 3
+    inst = random_instance(rng, nprops, 1 + seed % 3, 3, 1, 5)
+    nodes, cost = O.overfit(inst)
+    assert cost == _overfit_closed_cost(inst) == len(nodes)
+    # on the specification: true at position 0 of every P trace, false on every N trace
+    spec = O.Spec.of(inst)
+    cm = O.eval_formula(spec, nodes, O.MODE_QUANT)
+    offs = inst.offsets.astype(np.int64)
+    assert all(cm[offs[t]] for t in range(inst.num_pos))
+    assert not any(cm[offs[t]] for t in range(inst.num_pos, inst.num_traces))
+    # on traces next to P: one bit flipped, one letter longer or shorter -> outside P
+    pos = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_pos)]
+    near = []
+    for tr in pos:
+        for i in range(len(tr)):
+            for k in range(nprops):
+                v = list(tr); v[i] ^= 1 << k; near.append(v)
+        near.append(tr + [0])
+        if len(tr) > 1:
+            near.append(tr[:-1])
+    near = [v for v in near if v not in pos]
+    probe = synth.from_traces(pos, near, nprops)
+    cm2 = O.eval_formula(O.Spec.of(probe), nodes, O.MODE_EXPAND)
+    o2 = probe.offsets.astype(np.int64)
+    assert all(cm2[o2[t]] for t in range(probe.num_pos))
+    assert not any(cm2[o2[t]] for t in range(probe.num_pos, probe.num_traces))
