@@ -235,6 +235,78 @@ def formula_tree(nodes, k=None):
     return (op, formula_tree(nodes, a), formula_tree(nodes, b))
 
 
+def det_split(pos, neg, num_props: int, win: int, cost=UNIT_COST, op_mask: int = ALL_OPS, max_entries: int = 0,
+              threads: int = 1):
+    """Deterministic splitting (Sec. 6), with the learner of Sec. 3 at the leaves: enumerate
+    the levels below the cost of overfitting, else the overfitting formula.  L = the traces
+    accepted by both formulas of the first pair (their conjunction), R24.  Returns
+    (status, postfix nodes or None)."""
+    from paper_2402_12373_amd import synth
+
+    def accepted(nodes, traces):
+        if not traces:
+            return []
+        sp = Spec.of(synth.from_traces(traces, [], num_props))
+        cm = eval_formula(sp, nodes, MODE_EXPAND)
+        starts = sp.offsets[:-1].astype(np.int64)
+        return [bool(cm[o]) for o in starts]
+
+    def leaf(P, N):
+        inst = synth.from_traces(P, N, num_props)
+        of_nodes, of_cost = overfit(inst, cost)
+        r = learn(inst, min(of_cost - 1, 63), cost, op_mask, MODE_EXPAND, threads, max_entries)
+        if r.status == ST_OK:
+            return ST_OK, r.solution
+        if r.status == ST_NOT_FOUND:
+            return ST_OK, of_nodes
+        return r.status, None
+
+    def combine(op, f, g):
+        shift = len(f)
+        moved = []
+        for o, a, b in g:
+            if o == ATOM:
+                moved.append((o, a, b))
+            elif o in (AND, OR, U):
+                moved.append((o, a + shift, b + shift))
+            else:
+                moved.append((o, a + shift, b))
+        return f + moved + [(op, shift - 1, shift + len(g) - 1)]
+
+    def split(P, N, w):
+        if len(P) == 0:
+            return ST_OK, None
+        if len(P) + len(N) <= w or max(len(P), len(N)) <= 1:
+            return leaf(P, N)
+        P1, P2 = P[:len(P) // 2], P[len(P) // 2:]
+        N1, N2 = N[:len(N) // 2], N[len(N) // 2:]
+        st, f11 = split(P1, N1, w)
+        f12 = None
+        if st == ST_OK and f11 is not None:
+            left = [n for n, ok in zip(N2, accepted(f11, N2)) if ok]
+            if left:
+                st, f12 = split(P1, left, w)
+        first = None if f11 is None else (f11 if f12 is None else combine(AND, f11, f12))
+        f21 = f22 = None
+        if st == ST_OK:
+            P2r = P2 if first is None else [p for p, ok in zip(P2, accepted(first, P2)) if not ok]
+            st, f21 = split(P2r, N1, w)
+            if st == ST_OK and f21 is not None:
+                left = [n for n, ok in zip(N2, accepted(f21, N2)) if ok]
+                if left:
+                    st, f22 = split(P2r, left, w)
+        if st == ST_EOOM:
+            return (ST_EOOM, None) if w <= 1 else split(P, N, w // 2)
+        if st != ST_OK:
+            return st, None
+        second = None if f21 is None else (f21 if f22 is None else combine(AND, f21, f22))
+        if first is None:
+            return ST_OK, second
+        return ST_OK, first if second is None else combine(OR, first, second)
+
+    return split(list(pos), list(neg), win)
+
+
 def learn(inst, bound: int, cost=UNIT_COST, op_mask: int = ALL_OPS, mode: int = MODE_QUANT, threads: int = 1,
           max_entries: int = 0) -> Result:
     spec = Spec.of(inst)

@@ -464,3 +464,102 @@ def learn_batch(specs, bounds, lanes: int = 8, workspace_bytes: int = 8 << 30, d
     if st != LTL_OK:
         raise LTLError(st, "ltl_learn_batch")
     return [_convert(res[i]) for i in range(n)], [ms[2 * i] for i in range(n)], [ms[2 * i + 1] for i in range(n)]
+
+
+# ---------------------------------------------------------------- divide and conquer (Sec. 6)
+
+def holds_at_start(nodes, traces) -> np.ndarray:
+    """Position-0 truth of a postfix formula on each trace (lists of letters, bit k of a
+    letter = proposition k).  Host-side, for the language tests of the splitting driver;
+    finite-trace semantics of Sec. 2 (strong X, nothing holds past the end)."""
+    out = np.zeros(len(traces), dtype=bool)
+    for t, tr in enumerate(traces):
+        n = len(tr)
+        val = []
+        for op, a, b in nodes:
+            if op == ATOM:
+                v = np.array([(int(l) >> a) & 1 for l in tr], dtype=bool)
+            elif op == NOT:
+                v = ~val[a]
+            elif op == AND:
+                v = val[a] & val[b]
+            elif op == OR:
+                v = val[a] | val[b]
+            elif op == X:
+                v = np.zeros(n, dtype=bool); v[:-1] = val[a][1:]
+            elif op == F:
+                v = np.logical_or.accumulate(val[a][::-1])[::-1]
+            elif op == G:
+                v = np.logical_and.accumulate(val[a][::-1])[::-1]
+            else:     # U: psi now, or phi now and U at the next position
+                v = np.zeros(n, dtype=bool)
+                nxt = False
+                for i in range(n - 1, -1, -1):
+                    nxt = bool(val[b][i]) or (bool(val[a][i]) and nxt)
+                    v[i] = nxt
+            val.append(v)
+        out[t] = bool(val[-1][0])
+    return out
+
+
+def _join(op, f, g):
+    """f op g for postfix node lists (g's child indices shifted past f)."""
+    k = len(f)
+    g2 = [(o, a + k if o != ATOM else a, (b + k) if o in (AND, OR, U) else b) for o, a, b in g]
+    return f + g2 + [(op, k - 1, k + len(g) - 1)]
+
+
+def det_split(ctx: "Context", pos, neg, num_props: int, win: int, cost=None, ops=None, _depth=0):
+    """Deterministic splitting (Sec. 6) over the learner of Sec. 3 (`learn_complete` on the
+    context).  pos, neg: lists of traces (lists of letters).  Returns (status, nodes): LTL_OK
+    and a sound (not necessarily minimal) formula, or LTL_E_OOM when even the smallest window
+    runs out of memory.
+      (P, N) of at most `win` traces (or nothing left to split): the learner;
+      else P1/P2 and N1/N2 halves (in order) and, with L = L(phi11) and L(phi12) (both):
+        phi11 = split(P1, N1); phi12 = split(P1, N2 in L(phi11));
+        phi21 = split(P2 - L, N1); phi22 = split(P2 - L, N2 in L(phi21));
+        result (phi11 and phi12) or (phi21 and phi22);
+      a part with no positive trace contributes nothing, a conjunct with no negative trace
+      left is dropped; on out-of-memory in any part, the whole call again with win / 2."""
+    if not pos:
+        return LTL_OK, None               # nothing to accept: no disjunct
+    if len(pos) + len(neg) <= win or (len(pos) <= 1 and len(neg) <= 1):
+        from . import synth
+        inst = synth.from_traces(pos, neg, num_props)
+        r = learn_complete(ctx, inst, cost=cost, ops=ops)
+        if r.status == LTL_OK:
+            return LTL_OK, r.solution
+        if r.status == LTL_NOT_FOUND:     # overfitting costs more than the level range: use it
+            return LTL_OK, overfit(inst, cost, ops)[0]
+        return r.status, None
+    h, k = len(pos) // 2, len(neg) // 2
+    P1, P2, N1, N2 = pos[:h], pos[h:], neg[:k], neg[k:]
+
+    def sub(P, N):
+        return det_split(ctx, P, N, num_props, win, cost, ops, _depth + 1)
+
+    def conj(P, Na, Nb):
+        st, f1 = sub(P, Na)
+        if st != LTL_OK or f1 is None:
+            return st, f1
+        keep = [n for n, m in zip(Nb, holds_at_start(f1, Nb)) if m]
+        if not keep:
+            return LTL_OK, f1
+        st, f2 = sub(P, keep)
+        if st != LTL_OK:
+            return st, None
+        return LTL_OK, _join(AND, f1, f2)
+
+    st, a = conj(P1, N1, N2)
+    if st == LTL_OK:
+        rest = P2 if a is None else [p for p, m in zip(P2, holds_at_start(a, P2)) if not m]
+        st, b = conj(rest, N1, N2)
+    if st == LTL_E_OOM:
+        if win <= 1:
+            return LTL_E_OOM, None
+        return det_split(ctx, pos, neg, num_props, win // 2, cost, ops, _depth + 1)
+    if st != LTL_OK:
+        return st, None
+    if a is None:
+        return LTL_OK, b
+    return LTL_OK, a if b is None else _join(OR, a, b)

@@ -464,3 +464,26 @@ def test_learn_complete(ltl, ctx, monkeypatch):
     monkeypatch.setattr(ltl, "overfit", lambda i, cost=None, ops=None: (nodes, 2))
     r = ltl.learn_complete(ctx, inst)
     assert (r.status, r.cost, r.solution, r.solution_index, r.levels_done) == (ltl.LTL_OK, 2, nodes, None, 1)
+
+
+@pytest.mark.parametrize("cap", [0, 40], ids=["no-cap", "entry-cap-40"])
+def test_det_split_parity(ltl, cap):
+    """Deterministic splitting (Sec. 6) over the GPU learner equals the same splitting over
+    the oracle, formula for formula, for several windows; with an entry cap of 40 the large
+    windows run out of memory and are halved on both sides alike."""
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=20, max_entries=cap)
+    try:
+        for seed in range(6):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            offs = inst.offsets.astype(np.int64)
+            trs = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_traces)]
+            P, N = trs[:inst.num_pos], trs[inst.num_pos:]
+            for win in (3, 8, 32):
+                _say("det_split seed", seed, "win", win, "cap", cap)
+                g = ltl.det_split(c, P, N, inst.num_props, win)
+                o = O.det_split(P, N, inst.num_props, win, max_entries=cap)
+                assert g[0] == o[0] and g[1] == o[1], (seed, win, g, o)
+                if g[0] == ltl.LTL_OK:
+                    assert all(ltl.holds_at_start(g[1], P)) and not any(ltl.holds_at_start(g[1], N))
+    finally:
+        c.close()

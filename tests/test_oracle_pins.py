@@ -421,3 +421,24 @@ def test_overfit_language_is_exactly_P(seed):
     o2 = probe.offsets.astype(np.int64)
     assert all(cm2[o2[t]] for t in range(probe.num_pos))
     assert not any(cm2[o2[t]] for t in range(probe.num_pos, probe.num_traces))
+
+
+# ---------------------------------------------------------------- deterministic splitting (Sec. 6)
+
+@pytest.mark.parametrize("seed", range(6))
+def test_det_split_is_sound_and_plain_when_window_fits(seed):
+    # planted specifications: every sub-specification is separated by the planted formula
+    # (size 5), so each leaf stays cheap
+    inst, cfg = synth.preset_instance("tiny", seed)
+    offs = inst.offsets.astype(np.int64)
+    trs = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_traces)]
+    P, N = trs[:inst.num_pos], trs[inst.num_pos:]
+    for win in (3, 6, 12):
+        st, f = O.det_split(P, N, inst.num_props, win)
+        assert st == O.ST_OK and f is not None
+        cm = O.eval_formula(O.Spec.of(inst), f, O.MODE_QUANT)
+        assert all(cm[offs[t]] for t in range(inst.num_pos)), win
+        assert not any(cm[offs[t]] for t in range(inst.num_pos, inst.num_traces)), win
+    # a window holding the whole specification: the learner's minimal formula
+    st, f = O.det_split(P, N, inst.num_props, len(P) + len(N))
+    assert f == O.learn(inst, cfg["bound"], mode=O.MODE_EXPAND).solution
