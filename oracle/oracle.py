@@ -307,6 +307,96 @@ def det_split(pos, neg, num_props: int, win: int, cost=UNIT_COST, op_mask: int =
     return split(list(pos), list(neg), win)
 
 
+def rand_split(pos, neg, num_props: int, win: int, seed: int = 0, cost=UNIT_COST, op_mask: int = ALL_OPS,
+               max_entries: int = 0, threads: int = 1):
+    """Random splitting (Sec. 6) with the learner of Sec. 3 at the leaves.  The random
+    sub-specifications are the input sampler's (synth.sample_subset), consumed in call order
+    (two draws per sample: positives, then negatives).  Returns (status, nodes or None);
+    an empty node list stands for "true" (no negative trace left to reject)."""
+    from paper_2402_12373_amd import synth
+    draws = [0]
+
+    def accepted(nodes, traces):
+        if not traces:
+            return []
+        sp = Spec.of(synth.from_traces(traces, [], num_props))
+        cm = eval_formula(sp, nodes, MODE_EXPAND)
+        return [bool(cm[o]) for o in sp.offsets[:-1].astype(np.int64)]
+
+    def leaf(P, N):
+        inst = synth.from_traces(P, N, num_props)
+        of_nodes, of_cost = overfit(inst, cost)
+        r = learn(inst, min(of_cost - 1, 63), cost, op_mask, MODE_EXPAND, threads, max_entries)
+        if r.status == ST_OK:
+            return ST_OK, r.solution
+        if r.status == ST_NOT_FOUND:
+            return ST_OK, of_nodes
+        return r.status, None
+
+    def conj(f, g):
+        if f is None or g is None:
+            return None
+        if len(g) == 0:
+            return f
+        if len(f) == 0:
+            return g
+        k = len(f)
+        return f + [(o, a if o == ATOM else a + k, b + k if o in (AND, OR, U) else b) for o, a, b in g] + \
+            [(AND, k - 1, k + len(g) - 1)]
+
+    def disj(f, g):
+        if f is None:
+            return g
+        if g is None:
+            return f
+        k = len(f)
+        return f + [(o, a if o == ATOM else a + k, b + k if o in (AND, OR, U) else b) for o, a, b in g] + \
+            [(OR, k - 1, k + len(g) - 1)]
+
+    def split(P, N):
+        if len(P) == 0:
+            return ST_OK, None
+        if len(N) == 0:
+            return ST_OK, []
+        if len(P) + len(N) <= win:
+            return leaf(P, N)
+        w = win
+        while True:
+            if w < 2:
+                return ST_EOOM, None
+            total = min(w, len(P) + len(N))
+            kp = min(len(P), (total + 1) // 2)
+            kn = min(len(N), total - kp)
+            kp = min(len(P), total - kn)
+            call = draws[0]
+            draws[0] += 1
+            P0 = [P[i] for i in synth.sample_subset(seed, 2 * call, len(P), kp)]
+            N0 = [N[i] for i in synth.sample_subset(seed, 2 * call + 1, len(N), kn)]
+            st, f11 = leaf(P0, N0)
+            if st != ST_EOOM:
+                break
+            w //= 2
+        if st != ST_OK:
+            return st, None
+        aP, aN = accepted(f11, P), accepted(f11, N)
+        P_in = [p for p, a in zip(P, aP) if a]
+        P_out = [p for p, a in zip(P, aP) if not a]
+        N_in = [n for n, a in zip(N, aN) if a]
+        N_out = [n for n, a in zip(N, aN) if not a]
+        st, f12 = split(P_in, N_in)
+        if st != ST_OK:
+            return st, None
+        st, f21 = split(P_out, N_out)
+        if st != ST_OK:
+            return st, None
+        st, f22 = split(P_out, N_in)
+        if st != ST_OK:
+            return st, None
+        return ST_OK, disj(conj(f11, f12), conj(f21, f22))
+
+    return split(list(pos), list(neg))
+
+
 def learn(inst, bound: int, cost=UNIT_COST, op_mask: int = ALL_OPS, mode: int = MODE_QUANT, threads: int = 1,
           max_entries: int = 0) -> Result:
     spec = Spec.of(inst)

@@ -563,3 +563,83 @@ def det_split(ctx: "Context", pos, neg, num_props: int, win: int, cost=None, ops
     if a is None:
         return LTL_OK, b
     return LTL_OK, a if b is None else _join(OR, a, b)
+
+
+def rand_split(ctx: "Context", pos, neg, num_props: int, win: int, seed: int = 0, cost=None, ops=None):
+    """Random splitting (Sec. 6) over the learner of Sec. 3.  Returns (status, nodes).
+      fits in `win`: the learner on (P, N);
+      else phi11 = the learner on a random sub-specification (P0, N0) of at most `win` traces,
+      the two classes as equal in size as the window allows (window halved on out-of-memory),
+      and with A = L(phi11):
+        phi12 = split(P in A, N in A); phi21 = split(P - A, N - A); phi22 = split(P - A, N in A);
+        result (phi11 and phi12) or (phi21 and phi22).
+    The subsets come from synth.sample_subset(seed, call, ...), calls numbered in the order
+    the recursion makes them, so a run is reproducible."""
+    from . import synth
+    counter = [0]
+
+    def learn_leaf(P, N):
+        inst = synth.from_traces(P, N, num_props)
+        r = learn_complete(ctx, inst, cost=cost, ops=ops)
+        if r.status == LTL_OK:
+            return LTL_OK, r.solution
+        if r.status == LTL_NOT_FOUND:
+            return LTL_OK, overfit(inst, cost, ops)[0]
+        return r.status, None
+
+    def sample(P, N, w):
+        total = min(w, len(P) + len(N))
+        kp = min(len(P), (total + 1) // 2)
+        kn = min(len(N), total - kp)
+        kp = min(len(P), total - kn)
+        call = counter[0]
+        counter[0] += 1
+        ip = synth.sample_subset(seed, 2 * call, len(P), kp)
+        ineq = synth.sample_subset(seed, 2 * call + 1, len(N), kn)
+        return [P[i] for i in ip], [N[i] for i in ineq]
+
+    def split(P, N):
+        if not P:
+            return LTL_OK, None
+        if not N:                      # nothing to reject: true, which costs nothing to conjoin
+            return LTL_OK, []
+        if len(P) + len(N) <= win:
+            return learn_leaf(P, N)
+        w = win
+        while True:
+            if w < 2:              # a sample needs a trace of each class to make progress
+                return LTL_E_OOM, None
+            P0, N0 = sample(P, N, w)
+            st, f11 = learn_leaf(P0, N0)
+            if st != LTL_E_OOM:
+                break
+            w //= 2
+        if st != LTL_OK:
+            return st, None
+        inP, inN = holds_at_start(f11, P), holds_at_start(f11, N)
+        parts = []
+        for PP, NN in (([p for p, m in zip(P, inP) if m], [n for n, m in zip(N, inN) if m]),
+                       ([p for p, m in zip(P, inP) if not m], [n for n, m in zip(N, inN) if not m]),
+                       ([p for p, m in zip(P, inP) if not m], [n for n, m in zip(N, inN) if m])):
+            st, f = split(PP, NN)
+            if st != LTL_OK:
+                return st, None
+            parts.append(f)
+        f12, f21, f22 = parts
+
+        def conj(f, g):
+            if f is None or g is None:
+                return None            # a part without positives: false
+            if not g:
+                return f
+            if not f:
+                return g
+            return _join(AND, f, g)
+
+        first, second = conj(f11, f12), conj(f21, f22)
+        if first is None:
+            return LTL_OK, second
+        return LTL_OK, first if second is None else _join(OR, first, second)
+
+    st, f = split(list(pos), list(neg))
+    return st, f

@@ -322,3 +322,13 @@ def batched_jobs(master_seed: int = 0, njobs: int = 256):
                                 name=f"batched/{master_seed}/{j}")
         out.append((inst, size + 2))
     return out
+
+
+def sample_subset(seed: int, call: int, n: int, k: int) -> List[int]:
+    """The random choice of random splitting (Sec. 6), drawn here so that every driver that
+    replays the same calls sees the same subsets: k of range(n) without replacement, in
+    increasing order, from the stream (seed, call)."""
+    if k >= n:
+        return list(range(n))
+    rng = np.random.default_rng([seed, call, 0x5B1])
+    return sorted(int(x) for x in rng.choice(n, size=k, replace=False))

@@ -487,3 +487,25 @@ def test_det_split_parity(ltl, cap):
                     assert all(ltl.holds_at_start(g[1], P)) and not any(ltl.holds_at_start(g[1], N))
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("cap", [0, 40], ids=["no-cap", "entry-cap-40"])
+def test_rand_split_parity(ltl, cap):
+    """Random splitting (Sec. 6) over the GPU learner equals the same splitting over the
+    oracle (the random subsets come from the shared input sampler), formula for formula."""
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=20, max_entries=cap)
+    try:
+        for seed in range(6):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            offs = inst.offsets.astype(np.int64)
+            trs = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_traces)]
+            P, N = trs[:inst.num_pos], trs[inst.num_pos:]
+            for win, rs in ((4, 0), (8, 1), (32, 2)):
+                _say("rand_split seed", seed, "win", win, "cap", cap)
+                g = ltl.rand_split(c, P, N, inst.num_props, win, seed=rs)
+                o = O.rand_split(P, N, inst.num_props, win, seed=rs, max_entries=cap)
+                assert g[0] == o[0] and g[1] == o[1], (seed, win, g, o)
+                if g[0] == ltl.LTL_OK:
+                    assert all(ltl.holds_at_start(g[1], P)) and not any(ltl.holds_at_start(g[1], N))
+    finally:
+        c.close()

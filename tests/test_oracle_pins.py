@@ -442,3 +442,20 @@ def test_det_split_is_sound_and_plain_when_window_fits(seed):
     # a window holding the whole specification: the learner's minimal formula
     st, f = O.det_split(P, N, inst.num_props, len(P) + len(N))
     assert f == O.learn(inst, cfg["bound"], mode=O.MODE_EXPAND).solution
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rand_split_is_sound_and_reproducible(seed):
+    inst, cfg = synth.preset_instance("tiny", seed)
+    offs = inst.offsets.astype(np.int64)
+    trs = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_traces)]
+    P, N = trs[:inst.num_pos], trs[inst.num_pos:]
+    for win, rs in ((4, 0), (8, 1), (12, 2)):
+        st, f = O.rand_split(P, N, inst.num_props, win, seed=rs)
+        assert st == O.ST_OK and f
+        cm = O.eval_formula(O.Spec.of(inst), f, O.MODE_QUANT)
+        assert all(cm[offs[t]] for t in range(inst.num_pos)), win
+        assert not any(cm[offs[t]] for t in range(inst.num_pos, inst.num_traces)), win
+        assert O.rand_split(P, N, inst.num_props, win, seed=rs) == (st, f)
+    st, f = O.rand_split(P, N, inst.num_props, len(P) + len(N))
+    assert f == O.learn(inst, cfg["bound"], mode=O.MODE_EXPAND).solution
