@@ -233,6 +233,16 @@ typedef struct ltl_batch ltl_batch;
 int ltl_batch_create(const ltl_batch_opts *opts, ltl_batch **out);
 int ltl_batch_run(ltl_batch *batch, const ltl_batch_job *jobs, uint32_t njobs, ltl_result *results,
                   double *job_ms);
+
+/* Serving: as ltl_batch_run, but job i arrives arrival_ms[i] milliseconds after the
+ * call begins (non-decreasing, >= 0) and no lane starts it before then; free lanes
+ * take arrived jobs in arrival order, each within its lane's workspace slice (its share
+ * of device memory).  job_ms as in ltl_learn_batch (completion times count from the call's
+ * start, so a job's latency is job_ms[2*i+1] - arrival_ms[i]).  Each job's result equals
+ * that of ltl_learn on a lane's context.  Errors: LTL_E_INVAL (arrival times missing,
+ * negative or decreasing), else as ltl_batch_run. */
+int ltl_batch_serve(ltl_batch *batch, const ltl_batch_job *jobs, uint32_t njobs, const double *arrival_ms,
+                    ltl_result *results, double *job_ms);
 void ltl_batch_destroy(ltl_batch *batch);
 
 /* ---------------------------------------------------------------- level-by-level interface */

@@ -1344,6 +1344,7 @@ struct ltl_batch {
     uint32_t njobs = 0;
     ltl_result *results = nullptr;
     double *job_ms = nullptr;
+    const double *arrival_ms = nullptr;    // serving: job i may start arrival_ms[i] after t0
     std::atomic<uint32_t> next{0};
     std::chrono::steady_clock::time_point t0;
 };
@@ -1352,6 +1353,9 @@ static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
     for (;;) {
         const uint32_t i = b->next.fetch_add(1);
         if (i >= b->njobs) break;
+        if (b->arrival_ms && b->arrival_ms[i] > 0.0)      // not admitted before it arrives
+            std::this_thread::sleep_until(b->t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                                      std::chrono::duration<double, std::milli>(b->arrival_ms[i])));
         const auto a = std::chrono::steady_clock::now();
         ltl_learn(b->ctxs[lane], &b->jobs[i].spec, &b->jobs[i].ops, b->jobs[i].cost_bound, &b->results[i]);
         const auto e = std::chrono::steady_clock::now();
@@ -1454,8 +1458,24 @@ extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
     return LTL_OK;
 }
 
+static int batch_go(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, const double *arrival_ms,
+                    ltl_result *results, double *job_ms);
+
 extern "C" int ltl_batch_run(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, ltl_result *results,
                              double *job_ms) {
+    return batch_go(b, jobs, njobs, nullptr, results, job_ms);
+}
+
+extern "C" int ltl_batch_serve(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, const double *arrival_ms,
+                               ltl_result *results, double *job_ms) {
+    if (!arrival_ms && njobs) return LTL_E_INVAL;
+    for (uint32_t i = 0; i < njobs; ++i)
+        if (!(arrival_ms[i] >= 0.0) || (i && arrival_ms[i] < arrival_ms[i - 1])) return LTL_E_INVAL;
+    return batch_go(b, jobs, njobs, arrival_ms, results, job_ms);
+}
+
+static int batch_go(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, const double *arrival_ms,
+                    ltl_result *results, double *job_ms) {
     if (!b || (!jobs && njobs) || (!results && njobs)) return LTL_E_INVAL;
     if (b->running.exchange(true)) return LTL_E_STATE;
     if (hipSetDevice(b->o.device) != hipSuccess) {
@@ -1466,6 +1486,7 @@ extern "C" int ltl_batch_run(ltl_batch *b, const ltl_batch_job *jobs, uint32_t n
     b->njobs = njobs;
     b->results = results;
     b->job_ms = job_ms;
+    b->arrival_ms = arrival_ms;
     b->next = 0;
     b->t0 = std::chrono::steady_clock::now();
     {

@@ -31,7 +31,7 @@ KERNEL_KINDS = ("eval", "verify", "materialize", "compact", "fallback", "intake"
 EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", "ltl_batch_create", "ltl_batch_run",
            "ltl_batch_destroy", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
-           "ltl_status_str", "ltl_overfit")
+           "ltl_status_str", "ltl_overfit", "ltl_batch_serve")
 
 
 class LTLError(RuntimeError):
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
     L.ltl_batch_create.restype = C.c_int
     L.ltl_batch_run.argtypes = [C.c_void_p, P(BatchJob), C.c_uint32, P(Result), P(C.c_double)]
     L.ltl_batch_run.restype = C.c_int
+    L.ltl_batch_serve.argtypes = [C.c_void_p, P(BatchJob), C.c_uint32, P(C.c_double), P(Result), P(C.c_double)]
+    L.ltl_batch_serve.restype = C.c_int
     L.ltl_batch_destroy.argtypes = [C.c_void_p]
     L.ltl_batch_destroy.restype = None
     L.ltl_job_create.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(C.c_void_p)]
@@ -430,6 +432,19 @@ class Batch:
         st = self._L.ltl_batch_run(self._h, jobs, n, res, ms)
         if st != LTL_OK:
             raise LTLError(st, "ltl_batch_run")
+        return [_convert(res[i]) for i in range(n)], [ms[2 * i] for i in range(n)], [ms[2 * i + 1] for i in range(n)]
+
+    def serve(self, specs, bounds, arrival_ms, cost=None, ops=None):
+        """Serving (ltl_batch_serve): job i arrives arrival_ms[i] after the call begins; returns
+        (results, durations_ms, completion_ms); latency = completion - arrival."""
+        jobs, bufs = _batch_jobs(specs, bounds, cost, ops)
+        n = len(bufs)
+        res = (Result * n)()
+        ms = (C.c_double * (2 * n))()
+        arr = (C.c_double * max(1, n))(*[float(a) for a in arrival_ms])
+        st = self._L.ltl_batch_serve(self._h, jobs, n, arr, res, ms)
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_batch_serve")
         return [_convert(res[i]) for i in range(n)], [ms[2 * i] for i in range(n)], [ms[2 * i + 1] for i in range(n)]
 
     def close(self):

@@ -332,3 +332,10 @@ def sample_subset(seed: int, call: int, n: int, k: int) -> List[int]:
         return list(range(n))
     rng = np.random.default_rng([seed, call, 0x5B1])
     return sorted(int(x) for x in rng.choice(n, size=k, replace=False))
+
+
+def poisson_arrivals(seed: int, n: int, rate_per_s: float) -> List[float]:
+    """Arrival times (milliseconds from 0, non-decreasing) of n jobs of a Poisson process of
+    the given rate: exponential gaps from the stream `seed`."""
+    rng = np.random.default_rng([seed, 0xA77])
+    return [float(x) for x in np.cumsum(rng.exponential(1000.0 / rate_per_s, size=n))]

@@ -509,3 +509,25 @@ def test_rand_split_parity(ltl, cap):
                     assert all(ltl.holds_at_start(g[1], P)) and not any(ltl.holds_at_start(g[1], N))
     finally:
         c.close()
+
+
+def test_batch_serve_arrivals(ltl):
+    """ltl_batch_serve: jobs start no earlier than they arrive, and every result equals the
+    job's plain run, alone and in the mix."""
+    jobs = [synth.preset_instance("tiny", s) for s in range(80, 104)]
+    insts = [j[0] for j in jobs]
+    bounds = [j[1]["bound"] for j in jobs]
+    arrival = synth.poisson_arrivals(1, len(insts), 400.0)      # about 60 ms in all
+    ex = ltl.Batch(lanes=3, workspace_bytes=768 << 20, hash_slots_log2=16)
+    plain = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=16)
+    key = lambda r: (r.status, r.cost, r.level_new, r.level_candidates, r.solution_index, r.solution)
+    try:
+        res, dur, done = ex.serve(insts, bounds, arrival)
+        for i, (inst, b, g) in enumerate(zip(insts, bounds, res)):
+            assert key(g) == key(plain.learn(inst, b)), i
+            assert done[i] >= arrival[i] + dur[i] - 1e-3, (i, done[i], arrival[i], dur[i])
+        with pytest.raises(ltl.LTLError):
+            ex.serve(insts[:2], bounds[:2], [5.0, 1.0])                 # decreasing arrivals
+    finally:
+        ex.close()
+        plain.close()
