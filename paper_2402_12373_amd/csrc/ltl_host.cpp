@@ -505,7 +505,8 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
         HIP_TRY(hipMemcpyAsync(j->letters_d, spec->letters, j->TB * 4, hipMemcpyHostToDevice, j->s));
         HIP_TRY(hipMemcpyAsync(j->offsets_d, spec->offsets, ((uint64_t)T + 1) * 8, hipMemcpyHostToDevice, j->s));
     }
-    HIP_TRY(hipMemsetAsync(j->ctr, 0, sizeof(Counters), j->s));
+    static_assert(sizeof(Counters) % 4 == 0, "counters are cleared as words");
+    HIP_TRY(launch_zero2((uint32_t *)j->ctr, sizeof(Counters) / 4, nullptr, 0, j->s));
     {
         Timer tm(j, LTL_K_INTAKE, c->table_clean_log2 != sl ? 3u : 2u);
         if (c->table_clean_log2 != sl) HIP_TRY(launch_table_init(j->tkey, j->tval, nslots, j->s));
@@ -862,8 +863,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     HIP_TRY(hipMemcpyAsync(j->ctr, j->ctx->pinned,
                            256 + sizeof(Block) * (lv.blocks.size() + grouped.size() * (merged_eval ? 2 : 1)),
                            hipMemcpyHostToDevice, j->s));
-    HIP_TRY(hipMemsetAsync(bits3, 0, clear_bytes, j->s));
-    if (has_member) HIP_TRY(hipMemsetAsync(has_member, 0, (uint64_t)new_cap * 4, j->s));
+    HIP_TRY(launch_zero2(bits3, clear_bytes / 4, has_member, has_member ? (uint64_t)new_cap : 0, j->s));
 
     LevelArgs<T> A{};
     A.rows = make_rows<T>(j);
@@ -1007,8 +1007,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         // entry gets the matrix of its representative (the canonical-first member),
         // every other candidate is compared with it, and the ones that differ go to
         // the sequential fallback in canonical order.
-        HIP_TRY(hipMemsetAsync(coll_bits, 0, nwa * 4, j->s));
-        HIP_TRY(hipMemsetAsync(&j->ctr->n_coll, 0, sizeof(uint32_t), j->s));
+        HIP_TRY(launch_zero2(coll_bits, nwa, &j->ctr->n_coll, 1, j->s));
         A.verify_rep = 1;
         {
             Timer tm(j, LTL_K_MATERIALIZE);

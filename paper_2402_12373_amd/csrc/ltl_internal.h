@@ -150,6 +150,8 @@ hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32
                           const uint32_t *bitmap, const uint32_t *wordpre, uint32_t *recipe, uint32_t level_base,
                           uint32_t *entry_slot, uint32_t *new_owner, uint32_t *store, bool repass, uint32_t grid,
                           hipStream_t s);
+// zero words [0, na) of a and [0, nb) of b (either may be null) in one kernel
+hipError_t launch_zero2(uint32_t *a, uint64_t na, uint32_t *b, uint64_t nb, hipStream_t s);
 hipError_t launch_clear_slots(const uint32_t *entry_slot, uint32_t n, unsigned long long *tkey, uint32_t *tval,
                               hipStream_t s);
 hipError_t launch_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t nslots, hipStream_t s);

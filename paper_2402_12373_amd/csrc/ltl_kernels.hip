@@ -1412,6 +1412,26 @@ __global__ void k_scatter(const uint32_t *new_slots, const Counters *ctr, uint32
                     repass != 0);
 }
 
+// Zero two word ranges in one launch (a level's bitmaps and its member flags).  A
+// 16-byte-aligned range is cleared in 16-byte stores, its last n % 4 words one by one.
+__device__ inline void zero_words(uint32_t *p, uint64_t n, uint64_t t, uint64_t stride) {
+    uint64_t head = 0;
+    if ((reinterpret_cast<uintptr_t>(p) & 15u) == 0) {
+        const uint64_t n4 = n >> 2;
+        uint4 *q = reinterpret_cast<uint4 *>(p);
+        for (uint64_t i = t; i < n4; i += stride) q[i] = make_uint4(0u, 0u, 0u, 0u);
+        head = n4 << 2;
+    }
+    for (uint64_t i = head + t; i < n; i += stride) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_zero2(uint32_t *a, uint64_t na, uint32_t *b, uint64_t nb) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    zero_words(a, na, t, stride);
+    zero_words(b, nb, t, stride);
+}
+
 // return the slots of a finished job to the empty state
 __global__ void k_clear_slots(const uint32_t *entry_slot, uint32_t n, unsigned long long *tkey, uint32_t *tval) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1652,6 +1672,16 @@ hipError_t launch_scatter(const uint32_t *new_slots, const Counters *ctr, uint32
                           hipStream_t s) {
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(256), 0, s, new_slots, ctr, cap, tval, bitmap, wordpre, recipe,
                        level_base, entry_slot, new_owner, store, repass ? 1u : 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero2(uint32_t *a, uint64_t na, uint32_t *b, uint64_t nb, hipStream_t s) {
+    if (!a) na = 0;
+    if (!b) nb = 0;
+    const uint64_t n = std::max(na, nb);
+    if (!n) return hipSuccess;
+    const uint64_t g = std::min<uint64_t>((n / 4 + 255) / 256 + 1, 4096);
+    hipLaunchKernelGGL(k_zero2, dim3((uint32_t)g), dim3(256), 0, s, a, na, b, nb);
     return hipGetLastError();
 }
 
