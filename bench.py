@@ -30,16 +30,17 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2402_12373_amd", "csrc", "ltl_kernels.hip
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_scale.json")
 
 
-def measured_traffic(kind: str):
+def measured_traffic(kind: str, workload_key: str):
     """Calibrated HBM bytes per launch of a kernel kind, from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary -- only if the kernel source is unchanged since."""
+    FETCH_SIZE / WRITE_SIZE summary -- only for the workload the counters were taken on,
+    and only if the kernel source is unchanged since."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != src:
+    if rec.get("kernel_source_sha256") != src or rec.get("workload_key") != workload_key:
         return None
     k = rec.get("per_launch_bytes", {}).get(kind)
     return None if k is None else float(k)
@@ -80,8 +81,9 @@ def main():
     ap.add_argument("--jobs", type=int, default=256, help="batched workload: number of jobs")
     ap.add_argument("--lanes", type=int, default=0,
                     help="jobs in flight (lanes of a batch executor: own stream, workspace slice, hash table); "
-                         "default 4 for the fixed workloads, 8 for batched; 1 = one job after another")
-    ap.add_argument("--seeds", default="0-7")
+                         "default 4 for the fixed workloads, 1 for long (each long job needs the whole "
+                         "workspace), 8 for batched; 1 = one job after another")
+    ap.add_argument("--seeds", default="", help="job seeds, e.g. 0-7 (default: 0-3 for long, else 0-7)")
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
     ap.add_argument("--ucarry", action="store_true", help="U by carry-chain add instead of doubling")
@@ -114,6 +116,8 @@ def main():
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if not args.seeds:
+        args.seeds = "0-3" if args.workload == "long" else "0-7"
     seeds = parse_seeds(args.seeds)
     ops = None                       # every connective, negation anywhere
     if args.workload == "hamming":
@@ -150,7 +154,7 @@ def main():
     # pass: events around every kernel group (time per kernel kind)
     timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
     full_flags = (0 if args.no_timing else ltl.CTX_TIMING) | ucarry
-    lanes = args.lanes or 4
+    lanes = args.lanes or (1 if args.workload == "long" else 4)
     lanes = max(1, min(lanes, len(dev)))
     # lanes > 1: the batch executor takes the workspace; the one-stream comparison run gets a
     # workspace of one lane's size, so both see the same capacity per job
@@ -204,7 +208,9 @@ def main():
     geom = dict(R=int(info.rows), halves=int(info.rows) * (int(info.word_bits) // 32), k=int(info.doubling_steps),
                 cm_bytes=int(info.cm_bytes))
     roof, kern_ms, eval_tops, verify_gbs = roofline(ltl, results, geom, args.ucarry)
-    t = measured_traffic(roof["kind"])
+    wkey = (f"{args.workload} seeds {args.seeds} bound {cfg['bound']}" + (" ruc" if args.ruc else "")
+            + (" ucarry" if args.ucarry else ""))
+    t = measured_traffic(roof["kind"], wkey)
     roof["traffic"] = None if t is None else round(t / 1e6, 3)
     roof["traffic_unit"] = "MB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
 
@@ -293,6 +299,10 @@ def main():
         levels = args.cpu_levels or {"long": 4, "batched": 6, "hamming": 15}.get(args.workload, 8)
         out["cpu_baseline"] = cpu_baseline(insts, levels, ops)
     print(json.dumps(out), flush=True)
+    failed = [s for s, r in zip(seeds, results[:len(dev)]) if r.status < 0]
+    if failed:
+        print(f"warning: jobs of seeds {failed} ended in an error (statuses {out['statuses']}); "
+              "fewer lanes or a larger workspace give each job more memory", file=sys.stderr, flush=True)
     if lanes > 1:
         ex.close()
     ctx.close()
