@@ -72,8 +72,10 @@ FP_SEP_OPS = 6 + 2
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    # the first three or four steps of a process run slow (9-12 ms against about 5 on the
+    # scale workload), so the untimed warm-up covers them
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scale", choices=["tiny", "scale", "long", "batched", "hamming", "served"])
     ap.add_argument("--rate", type=float, default=10.0, help="served workload: Poisson arrival rate (jobs/s)")
     ap.add_argument("--ham-length", type=int, default=4, help="hamming workload: length of the positive trace")
