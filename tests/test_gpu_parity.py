@@ -531,3 +531,34 @@ def test_batch_serve_arrivals(ltl):
     finally:
         ex.close()
         plain.close()
+
+
+@pytest.mark.gpu
+def test_hamming_by_splitting(ltl):
+    """Hamming specifications that the plain learner cannot finish, solved by deterministic
+    and random splitting (Sec. 6) with the U-free operator set (negation anywhere: the
+    overfitting formula of the leaves negates X): formula for formula the oracle's, and
+    sound under the oracle's own evaluator."""
+    mask = 0xFF & ~(1 << ltl.U)
+    # room enough that no leaf runs out of memory (the oracle has no cap here)
+    c = ltl.Context(workspace_bytes=64 << 30, hash_slots_log2=26)
+    try:
+        for length in (5, 6):
+            inst = synth.hamming_instance(0, length, 2)
+            offs = inst.offsets.astype(np.int64)
+            trs = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_traces)]
+            P, N = trs[:1], trs[1:]
+            for kind in ("det", "rand"):
+                _say("hamming split", kind, "length", length)
+                if kind == "det":
+                    g = ltl.det_split(c, P, N, 2, 16, ops=mask)
+                    o = O.det_split(P, N, 2, 16, op_mask=mask)
+                else:
+                    g = ltl.rand_split(c, P, N, 2, 16, seed=0, ops=mask)
+                    o = O.rand_split(P, N, 2, 16, seed=0, op_mask=mask)
+                assert g[0] == ltl.LTL_OK and g[0] == o[0] and g[1] == o[1], (kind, length, g, o)
+                spec = O.Spec.of(synth.from_traces(P, N, 2))
+                assert O.holds(spec, 0, 0, g[1])
+                assert not any(O.holds(spec, t, 0, g[1]) for t in range(1, len(N) + 1))
+    finally:
+        c.close()
