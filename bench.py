@@ -112,7 +112,8 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2402_12373_amd import ltl, synth
+    from paper_2402_12373_amd import ltl
+    from ltl_inputs import synth
 
     if args.workload == "batched":
         return bench_batched(args)
@@ -315,7 +316,8 @@ def bench_batched(args):
     plain path (the same jobs one at a time, same per-job workspace)."""
     import numpy as np
     import torch
-    from paper_2402_12373_amd import ltl, synth
+    from paper_2402_12373_amd import ltl
+    from ltl_inputs import synth
     jobs = synth.batched_jobs(0, args.jobs)
     insts = [j[0] for j in jobs]
     bounds = [j[1] for j in jobs]
@@ -391,7 +393,8 @@ def bench_served(args):
     the whole run and the latency from arrival to completion."""
     import numpy as np
     import torch
-    from paper_2402_12373_amd import ltl, synth
+    from paper_2402_12373_amd import ltl
+    from ltl_inputs import synth
     n = args.jobs
     jobs = synth.batched_jobs(0, n)
     insts = [j[0] for j in jobs]

@@ -241,7 +241,7 @@ def det_split(pos, neg, num_props: int, win: int, cost=UNIT_COST, op_mask: int =
     the levels below the cost of overfitting, else the overfitting formula.  L = the traces
     accepted by both formulas of the first pair (their conjunction), R24.  Returns
     (status, postfix nodes or None)."""
-    from paper_2402_12373_amd import synth
+    from ltl_inputs import synth
 
     def accepted(nodes, traces):
         if not traces:
@@ -313,7 +313,7 @@ def rand_split(pos, neg, num_props: int, win: int, seed: int = 0, cost=UNIT_COST
     sub-specifications are the input sampler's (synth.sample_subset), consumed in call order
     (two draws per sample: positives, then negatives).  Returns (status, nodes or None);
     an empty node list stands for "true" (no negative trace left to reject)."""
-    from paper_2402_12373_amd import synth
+    from ltl_inputs import synth
     draws = [0]
 
     def accepted(nodes, traces):

@@ -539,7 +539,7 @@ def det_split(ctx: "Context", pos, neg, num_props: int, win: int, cost=None, ops
     if not pos:
         return LTL_OK, None               # nothing to accept: no disjunct
     if len(pos) + len(neg) <= win or (len(pos) <= 1 and len(neg) <= 1):
-        from . import synth
+        from ltl_inputs import synth
         inst = synth.from_traces(pos, neg, num_props)
         r = learn_complete(ctx, inst, cost=cost, ops=ops)
         if r.status == LTL_OK:
@@ -590,7 +590,7 @@ def rand_split(ctx: "Context", pos, neg, num_props: int, win: int, seed: int = 0
         result (phi11 and phi12) or (phi21 and phi22).
     The subsets come from synth.sample_subset(seed, call, ...), calls numbered in the order
     the recursion makes them, so a run is reproducible."""
-    from . import synth
+    from ltl_inputs import synth
     counter = [0]
 
     def learn_leaf(P, N):

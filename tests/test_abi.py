@@ -87,7 +87,7 @@ def test_context_without_gpu_fails_loudly():
 
 
 def test_generator_is_deterministic():
-    from paper_2402_12373_amd import synth
+    from ltl_inputs import synth
     a, _ = synth.preset_instance("tiny", 5)
     b, _ = synth.preset_instance("tiny", 5)
     assert (a.letters == b.letters).all() and (a.offsets == b.offsets).all() and a.planted == b.planted
@@ -100,7 +100,7 @@ def test_generator_is_deterministic():
 
 
 def test_hamming_generator_size():
-    from paper_2402_12373_amd import synth
+    from ltl_inputs import synth
     inst = synth.hamming_instance(0, 12, 2)
     assert inst.num_pos == 1 and inst.num_neg == 24 * 23 // 2
 

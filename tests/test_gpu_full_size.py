@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from paper_2402_12373_amd import synth
+from ltl_inputs import synth
 
 pytestmark = pytest.mark.gpu
 THREADS = min(16, os.cpu_count() or 1)

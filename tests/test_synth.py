@@ -12,8 +12,8 @@ from itertools import combinations
 import numpy as np
 import pytest
 
-from paper_2402_12373_amd import synth
-from paper_2402_12373_amd.synth import ATOM, NOT, AND, OR, X, F, G, U
+from ltl_inputs import synth
+from ltl_inputs.synth import ATOM, NOT, AND, OR, X, F, G, U
 
 
 def _all_trees(size, props):
