@@ -7,7 +7,7 @@ from typing import Dict, List, Tuple
 
 import numpy as np
 
-from paper_2402_12373_amd import synth
+from ltl_inputs import synth
 
 ATOM, NOT, AND, OR, X, F, G, U = range(8)
 _UN = {"!": NOT, "X": X, "F": F, "G": G}
@@ -119,3 +119,44 @@ def random_instance(rng: np.random.Generator, num_props: int, npos: int, nneg: i
         seen.add(key)
         traces.append(tr)
     return synth.from_traces(traces[:npos], traces[npos:], num_props)
+
+
+_CONN = {"F": F, "U": U, "G": G, "X": X, "&": AND, "|": OR, "!": NOT}
+
+
+def _letters(text: str, props: List[str]):
+    out = []
+    for let in text.split():
+        m = 0
+        if let != "-":
+            for p in let.split("+"):
+                m |= 1 << props.index(p)
+        out.append(m)
+    return out
+
+
+def load_canonical_cases():
+    """Hand-derived first solutions (tests/golden/canonical_order.txt): per case the
+    instance, op_mask, cost vector and the expected cost, first index and formula."""
+    out = []
+    with open(os.path.join(GOLDEN, "canonical_order.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, cite, props, conn, costs, P, N, cost, idx, formula = [x.strip() for x in line.split("::")]
+            props = props.split(",")
+            mask = 1
+            for c in (_CONN.values() if conn == "all" else [_CONN[c] for c in conn.split(",")]):
+                mask |= 1 << c
+            cvec = [1] * 8
+            if costs != "-":
+                for item in costs.split(","):
+                    k, v = item.split("=")
+                    cvec[_CONN[k]] = int(v)
+            pos = [_letters(t, props) for t in P.split(";")]
+            neg = [_letters(t, props) for t in N.split(";")]
+            out.append(dict(name=name, cite=cite, inst=synth.from_traces(pos, neg, len(props)), op_mask=mask,
+                            cost=cvec, expect_cost=int(cost), expect_index=int(idx),
+                            expect_formula=parse_prefix(formula, props)))
+    return out

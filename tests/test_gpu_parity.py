@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from paper_2402_12373_amd import synth
-from ltl_text import random_instance
+from ltl_inputs import synth
+from ltl_text import load_canonical_cases, random_instance
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +57,17 @@ def test_tiny_workload_parity(ctx, chunk):
         g = ctx.learn(inst, cfg["bound"])
         o = O.learn(inst, cfg["bound"])
         _same(g, o, f"tiny/{seed}")
+
+
+@pytest.mark.parametrize("case", load_canonical_cases(), ids=lambda c: c["name"])
+def test_canonical_order_cases(ctx, case):
+    """Hand-derived first solutions of the Sec. 3 order (tests/golden/canonical_order.txt):
+    the GPU returns the expected formula and canonical index."""
+    _say("canonical order case", case["name"])
+    g = ctx.learn(case["inst"], case["expect_cost"] + 1, cost=case["cost"], ops=case["op_mask"])
+    assert (g.status, g.cost) == (0, case["expect_cost"]), case["name"]
+    assert g.solution_index == case["expect_index"], (case["name"], g.solution_index)
+    assert g.solution == case["expect_formula"], (case["name"], g.solution)
 
 
 def _level_by_level(ltl, ctx, inst, bound, check_entries=True, max_entries_per_level=None):

@@ -20,9 +20,9 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from paper_2402_12373_amd import synth
-from ltl_text import (AND, ATOM, F, G, NOT, OR, U, X, all_traces, load_paper_examples, random_instance,
-                      single_trace_instance, trees_by_size)
+from ltl_inputs import synth
+from ltl_text import (AND, ATOM, F, G, NOT, OR, U, X, all_traces, load_canonical_cases, load_paper_examples,
+                      random_instance, single_trace_instance, trees_by_size)
 
 
 # ---------------------------------------------------------------- worked examples
@@ -339,6 +339,23 @@ def test_entry_formulas_reproduce_entry_matrices():
             f = run.entry_formula(c, i)
             assert len(f) == c
             np.testing.assert_array_equal(O.eval_formula(run.spec, f), run.entry_cm(c, i))
+
+
+# ---------------------------------------------------------------- canonical order (Sec. 3 listing)
+
+@pytest.mark.parametrize("case", load_canonical_cases(), ids=lambda c: c["name"])
+def test_canonical_order_first_solutions(case):
+    """Which minimal formula is returned: hand-derived first solutions for each pair of
+    neighbouring connectives in the Sec. 3 order, for the split order and for the pair
+    order (tests/golden/canonical_order.txt)."""
+    inst = case["inst"]
+    res = O.learn(inst, case["expect_cost"] + 1, cost=case["cost"], op_mask=case["op_mask"])
+    assert (res.status, res.cost) == (O.ST_OK, case["expect_cost"]), case["name"]
+    assert res.first_index == case["expect_index"], (case["name"], res.first_index)
+    assert res.solution == case["expect_formula"], (case["name"], res.solution)
+    spec = O.Spec.of(inst)
+    for t in range(inst.num_traces):
+        assert O.holds(spec, t, 0, res.solution) == (t < inst.num_pos)
 
 
 # ---------------------------------------------------------------- statuses
