@@ -43,6 +43,7 @@ extern "C" {
                                     entry cap; counts of the completed levels stay valid       */
 #define LTL_E_DEVICE       (-5)  /* a HIP runtime error                                        */
 #define LTL_E_STATE        (-6)  /* call out of order (e.g. levels not evaluated in order)     */
+#define LTL_E_BUFFER       (-7)  /* an output buffer is too small; the size needed is reported */
 
 #define LTL_MAX_TRACE_LEN  4096  /* positions per trace (64 words of 64 bits)                  */
 #define LTL_MAX_LEVELS     64    /* cost levels 0..63                                          */
@@ -92,7 +93,12 @@ typedef struct {
                                    or 32 / 64                                                   */
     uint32_t fp_bits;           /* debug: keep only this many fingerprint bits (1..64), forcing
                                    collisions that the exact compare must resolve; 0 = 64       */
-    uint32_t reserved;
+    uint32_t split_tiles;       /* a level of fewer than this many tiles (4 children a side) runs
+                                   the row-split kernels (several waves per tile), a larger one
+                                   the whole-row kernels (one wave per tile, one dispatch per
+                                   connective class); 0 = the library's default (8192).  1 forces
+                                   the whole-row kernels and 0xFFFFFFFF the row-split kernels at
+                                   every level; results do not depend on it                     */
     uint64_t max_entries;       /* cap on stored language-cache entries; 0 = derived from the
                                    hash table (half its slots)                                  */
 } ltl_ctx_opts;
@@ -247,9 +253,15 @@ void ltl_batch_destroy(ltl_batch *batch);
 
 /* ---------------------------------------------------------------- level-by-level interface */
 
-/* Validate and pack the specification (atom matrices, row layout) into the
- * context's workspace.  Errors: LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG,
- * LTL_E_OOM (workspace too small for the fixed tables), LTL_E_DEVICE. */
+/* Start a learning job (Sec. 3 enum, before its first level): validate the
+ * specification (Sec. 2: finite non-empty traces, P and N disjoint) and pack it
+ * into the context's workspace (row layout and the atom matrices, i.e. the
+ * characteristic matrices of the atomic propositions of Sec. 4); the job is then
+ * driven one cost level at a time by ltl_eval_level.  cost_bound (inclusive,
+ * 1..63) is the last level.  The job owns host state until ltl_job_destroy and
+ * uses the context exclusively (LTL_E_STATE while another job is open).
+ * Errors: LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG, LTL_E_OOM (workspace
+ * too small for the fixed tables), LTL_E_DEVICE, LTL_E_STATE. */
 int ltl_job_create(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
                    ltl_job **out);
 
@@ -296,12 +308,73 @@ int ltl_job_result(ltl_job *job, ltl_result *out);
 int ltl_overfit(const ltl_spec *spec, const ltl_opset *ops, ltl_node *buf, uint32_t cap, uint32_t *num_nodes,
                 uint64_t *cost);
 
-/* Formula of stored entry `entry` of level `cost` (postfix nodes into buf, at
- * most cap).  Errors: LTL_E_INVAL (no such entry, cap too small). */
+/* ---------------------------------------------------------------- formulas on traces, splitting */
+
+/* tr |= phi for every trace of a specification (Sec. 2: phi holds at position 0
+ * of tr under the finite-trace semantics: strong X, nothing holds past the end).
+ * nodes[0 .. num_nodes) is a postfix formula (children before parents, root
+ * last).  The formula's characteristic matrix is computed node by node on the
+ * device with the learner's own connective kernels, in the context's workspace
+ * (num_nodes matrices); out[t] = 1 if trace t (P first, then N; the classes play
+ * no other part and may overlap) satisfies it, else 0.  The caller owns out
+ * (num_pos + num_neg bytes).  Uses the context like a job (LTL_E_STATE while one
+ * is open).  Errors: LTL_E_INVAL (null pointer, a node naming a later node or a
+ * missing proposition, a bad spec), LTL_E_TOO_LONG, LTL_E_OOM (the matrices do
+ * not fit the workspace), LTL_E_DEVICE. */
+int ltl_holds(ltl_ctx *ctx, const ltl_spec *spec, const ltl_node *nodes, uint32_t num_nodes, uint8_t *out);
+
+/* Deterministic splitting (Sec. 6, detSplit): a specification of at most `win`
+ * traces (or of at most one trace per class) goes to the learner of Sec. 3
+ * (ltl_learn below the cost of the overfitting formula, else that formula; see
+ * ltl_overfit).  A larger one is split into halves P1 | P2 and N1 | N2 (in the
+ * given order, first floor(n/2) traces) and learned as
+ *   phi11 = split(P1, N1),  phi12 = split(P1, N2 accepted by phi11),
+ *   phi21 = split(P2 - L, N1),  phi22 = split(P2 - L, N2 accepted by phi21),
+ *   (phi11 and phi12) or (phi21 and phi22),
+ * with L the P2 traces that phi11 and phi12 both accept (the traces the first
+ * disjunct accepts; the paper's union would drop traces the conjunction rejects,
+ * making the result unsound).  A part with no positive trace contributes no
+ * disjunct; a conjunct with no negative trace left is dropped.  If any part runs
+ * out of memory, the whole call is repeated with win / 2.  The result is sound
+ * (accepts P, rejects N), not necessarily minimal.  The spec must be host
+ * buffers with at least one trace per class; the leaves run on ctx.  The formula
+ * goes to buf[0 .. cap) as postfix nodes, its size to *num_nodes.  Errors:
+ * LTL_E_INVAL, LTL_E_OOM (out of memory even at a window of 1),
+ * LTL_E_BUFFER (more than cap nodes; *num_nodes holds the size), and the
+ * learner's errors. */
+int ltl_det_split(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t win, ltl_node *buf,
+                  uint32_t cap, uint32_t *num_nodes);
+
+/* Random splitting (Sec. 6, randSplit): phi11 = the learner of Sec. 3 on a
+ * random sub-specification (P0, N0) of at most w traces, as large as possible
+ * and with the classes as equal in size as possible (|P0| = min(|P|,
+ * ceil(t/2)), |N0| = min(|N|, t - |P0|), then |P0| = min(|P|, t - |N0|), with
+ * t = min(w, |P| + |N|)), starting at w = win and halving w while the learner
+ * runs out of memory (a specification that fits is drawn whole); then, with
+ * A the traces phi11 accepts,
+ *   phi12 = split(P in A, N in A), phi21 = split(P - A, N - A), phi22 = split(P - A, N in A),
+ *   (phi11 and phi12) or (phi21 and phi22)
+ * (a part with no positive trace is false and drops its disjunct; a part with no
+ * negative trace is true and drops out of its conjunction).  The random subsets:
+ * the q-th draw of the recursion (q = 0, 1, ... in call order) takes the P0
+ * indices from stream 2q and the N0 indices from stream 2q + 1, where stream c
+ * is the SplitMix64 sequence (Steele, Lea and Flood, OOPSLA 2014) started at
+ * state seed * 2^32 + c: index i gets the output mix(state + (i + 1) * gamma),
+ * and the k indices with the smallest outputs are taken.  seed < 2^32.  Output,
+ * requirements and errors as ltl_det_split (LTL_E_OOM: a window below 2). */
+int ltl_rand_split(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t win, uint64_t seed,
+                   ltl_node *buf, uint32_t cap, uint32_t *num_nodes);
+
+/* Formula of stored entry `entry` of level `cost`: the recipe of the entry's
+ * representative (the first candidate of its language in the canonical order of
+ * Sec. 3's enumeration), expanded into its children's recipes down to the atoms
+ * (postfix nodes into buf, at most cap).  Errors: LTL_E_INVAL (no such entry, cap
+ * too small). */
 int ltl_job_formula(ltl_job *job, uint32_t cost, uint64_t entry, ltl_node *buf, uint32_t cap,
                     uint32_t *num_nodes);
 
-/* Characteristic matrix of stored entry `entry` of level `cost`, one byte (0/1)
+/* Characteristic matrix (Sec. 4: the characteristic sequences of all traces, in
+ * the order P then N) of stored entry `entry` of level `cost`, one byte (0/1)
  * per position, traces in order P then N, positions 0..|tr|-1 of each.  cap must
  * be >= the total number of positions.  Only stored levels keep their matrices
  * (a level with a solution, or at the cost bound, is not stored): LTL_E_STATE

@@ -307,6 +307,43 @@ def hamming_instance(seed: int, length: int, delta: int) -> Instance:
     return from_traces([tr.tolist()], [t.tolist() for t in negs], 2, name=f"hamming/{length}/{delta}/{seed}")
 
 
+UNTIL_CHAINS = (64, 127, 128, 129, 255, 256, 257, 511)
+
+
+def until_chain_instance(seed: int = 0, chains: Sequence[int] = UNTIL_CHAINS, extra: int = 4) -> Instance:
+    """Traces over 2 propositions whose p0 U p1 needs long until-chains (App. B doubling
+    across words of 64 positions).  For every d in `chains`:
+      P gets p0^d p1       (p1 first at position d, p0 everywhere before it);
+      N gets p0^d {}       (the same run with no p1 after it).
+    P also gets one trace of runs p0^d p1 for the chains up to 129 back to back.  Both
+    classes get `extra` random traces of length 64..512 with p0 ~ Bernoulli(0.95) and
+    p1 ~ Bernoulli(0.03) (long runs of p0, rare p1), drawn from `seed`."""
+    p0, p1 = 1, 2
+    pos = [[p0] * d + [p1] for d in chains]
+    neg = [[p0] * d + [0] for d in chains]
+    runs = []
+    for d in chains:
+        if d <= 129:
+            runs += [p0] * d + [p1]
+    if runs:
+        pos.append(runs)
+    rng = np.random.default_rng([seed, 0xC4A1])
+    seen = {tuple(t) for t in pos + neg}
+    for cls in (pos, neg):
+        added = 0
+        while added < extra:
+            n = int(rng.integers(64, 513))
+            a = rng.random(n) < 0.95
+            b = rng.random(n) < 0.03
+            tr = tuple(int(x) for x in (a * p0 + b * p1))
+            if tr in seen:
+                continue
+            seen.add(tr)
+            cls.append(list(tr))
+            added += 1
+    return from_traces(pos, neg, 2, name=f"until-chains/{seed}")
+
+
 def batched_jobs(master_seed: int = 0, njobs: int = 256):
     """The batched workload: independent jobs of uneven size.  Job j: propositions
     uniform in {2..5}, traces per class log-uniform in [16, 2048], lengths uniform in
@@ -322,16 +359,6 @@ def batched_jobs(master_seed: int = 0, njobs: int = 256):
                                 name=f"batched/{master_seed}/{j}")
         out.append((inst, size + 2))
     return out
-
-
-def sample_subset(seed: int, call: int, n: int, k: int) -> List[int]:
-    """The random choice of random splitting (Sec. 6), drawn here so that every driver that
-    replays the same calls sees the same subsets: k of range(n) without replacement, in
-    increasing order, from the stream (seed, call)."""
-    if k >= n:
-        return list(range(n))
-    rng = np.random.default_rng([seed, call, 0x5B1])
-    return sorted(int(x) for x in rng.choice(n, size=k, replace=False))
 
 
 def poisson_arrivals(seed: int, n: int, rate_per_s: float) -> List[float]:

@@ -307,12 +307,39 @@ def det_split(pos, neg, num_props: int, win: int, cost=UNIT_COST, op_mask: int =
     return split(list(pos), list(neg), win)
 
 
+_M64 = (1 << 64) - 1
+SPLITMIX_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64_output(state: int) -> int:
+    """SplitMix64's output function (Steele, Lea and Flood, "Fast splittable pseudorandom
+    number generators", OOPSLA 2014): the generator adds GAMMA to its state and returns
+    this mix of the new state."""
+    z = state & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def sample_subset(seed: int, stream: int, n: int, k: int):
+    """The random subset of random splitting: k of range(n), those whose draws from the
+    SplitMix64 sequence started at state seed * 2^32 + stream are smallest (draw i is the
+    output after i + 1 steps), in increasing order; all of range(n) when k >= n."""
+    if k >= n:
+        return list(range(n))
+    s0 = (seed << 32) + stream
+    keys = [splitmix64_output(s0 + (i + 1) * SPLITMIX_GAMMA) for i in range(n)]
+    return sorted(sorted(range(n), key=lambda i: (keys[i], i))[:k])
+
+
 def rand_split(pos, neg, num_props: int, win: int, seed: int = 0, cost=UNIT_COST, op_mask: int = ALL_OPS,
                max_entries: int = 0, threads: int = 1):
-    """Random splitting (Sec. 6) with the learner of Sec. 3 at the leaves.  The random
-    sub-specifications are the input sampler's (synth.sample_subset), consumed in call order
-    (two draws per sample: positives, then negatives).  Returns (status, nodes or None);
-    an empty node list stands for "true" (no negative trace left to reject)."""
+    """Random splitting (Sec. 6) with the learner of Sec. 3 at the leaves.  The q-th random
+    sub-specification of the recursion (in call order) draws its positives from stream 2q
+    and its negatives from stream 2q + 1 of `sample_subset`.  randAux halves the window
+    while the learner runs out of memory; a specification that fits the window is drawn
+    whole.  Returns (status, nodes or None); an empty node list stands for "true" (no
+    negative trace left to reject)."""
     from ltl_inputs import synth
     draws = [0]
 
@@ -358,8 +385,6 @@ def rand_split(pos, neg, num_props: int, win: int, seed: int = 0, cost=UNIT_COST
             return ST_OK, None
         if len(N) == 0:
             return ST_OK, []
-        if len(P) + len(N) <= win:
-            return leaf(P, N)
         w = win
         while True:
             if w < 2:
@@ -370,8 +395,8 @@ def rand_split(pos, neg, num_props: int, win: int, seed: int = 0, cost=UNIT_COST
             kp = min(len(P), total - kn)
             call = draws[0]
             draws[0] += 1
-            P0 = [P[i] for i in synth.sample_subset(seed, 2 * call, len(P), kp)]
-            N0 = [N[i] for i in synth.sample_subset(seed, 2 * call + 1, len(N), kn)]
+            P0 = [P[i] for i in sample_subset(seed, 2 * call, len(P), kp)]
+            N0 = [N[i] for i in sample_subset(seed, 2 * call + 1, len(N), kn)]
             st, f11 = leaf(P0, N0)
             if st != ST_EOOM:
                 break

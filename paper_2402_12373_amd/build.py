@@ -1,5 +1,6 @@
 """Builds the gfx950 shared library libltl.so in-tree with hipcc.
 
+Every source is compiled to an object of its own (in parallel), then linked.
 Usage: python -m paper_2402_12373_amd.build   (or __graft_entry__.build())
 """
 from __future__ import annotations
@@ -10,8 +11,9 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", "ltl_kernels.hip"), os.path.join(PKG, "csrc", "ltl_host.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ltl_kernels.hip", "ltl_host.cpp", "ltl_split.cpp")]
 LIB = os.path.join(PKG, "libltl.so")
+OBJDIR = os.path.join(PKG, "_build")
 ARCH = os.environ.get("LTL_OFFLOAD_ARCH", "gfx950")
 
 
@@ -22,16 +24,32 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def flags(extra=None):
+    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+            # no packed-FP32 instruction selection: some of its forms are unreliable on this target
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-result",
+            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")] + list(extra or [])
+
+
 def build(verbose: bool = True, extra=None) -> str:
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # no packed-FP32 instruction selection: some of its forms are unreliable on this target
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-result",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           "-o", LIB + ".tmp"] + SOURCES + list(extra or [])
+    os.makedirs(OBJDIR, exist_ok=True)
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+        cmd = [hipcc()] + flags(extra) + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    for p, cmd in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -37,11 +37,8 @@ constexpr uint32_t MAX_GRID = 8192;
 constexpr uint64_t TARGET_WAVES = 8192;
 // Levels with fewer tiles than this are row-split (waves take chunks of row
 // blocks), so that small levels are not one long chain of dependent row-block
-// loads per wave (a tuning constant).
-#ifndef LTL_SPLIT_TILES
-#define LTL_SPLIT_TILES 8192
-#endif
-constexpr uint64_t SPLIT_TILES = LTL_SPLIT_TILES;
+// loads per wave (a tuning constant; ltl_ctx_opts.split_tiles overrides it).
+constexpr uint64_t SPLIT_TILES = 8192;
 constexpr uint64_t MIN_CHUNK = 4;        // row blocks per work item at least (per-item fixed cost)
 // per-level upload, one copy: [counters init (256 B) | canonical blocks | blocks by
 // class | all blocks, one tile numbering]
@@ -333,6 +330,7 @@ extern "C" const char *ltl_status_str(int st) {
     case LTL_E_OOM: return "out of workspace or entry cap";
     case LTL_E_DEVICE: return "HIP device error";
     case LTL_E_STATE: return "call out of order";
+    case LTL_E_BUFFER: return "output buffer too small";
     default: return "unknown status";
     }
 }
@@ -738,7 +736,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         return j->ws + top;
     };
     const uint64_t nwa = align_up(nw, 64);                 // words, so the bitmaps stay aligned
-    const bool split = ntiles < SPLIT_TILES;
+    const bool split = ntiles < (j->ctx->o.split_tiles ? (uint64_t)j->ctx->o.split_tiles : SPLIT_TILES);
     // batch lanes that take turns for whole-row levels: held until the level's work is done
     std::unique_lock<std::mutex> big_turn;
     if (!split && j->ctx->big_mu) big_turn = std::unique_lock<std::mutex>(*j->ctx->big_mu);
@@ -1316,6 +1314,64 @@ extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *op
         if (st != LTL_OK || !j->searching) break;
     }
     st = ltl_job_result(j, out);
+    ltl_job_destroy(j);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// Formula evaluation: tr |= phi (Sec. 2) for every trace of a specification
+// ---------------------------------------------------------------------------
+template <typename T>
+static int holds_t(ltl_job *j, const ltl_node *nodes, uint32_t n, uint8_t *out) {
+    // node matrices in the arena (atoms are the packed atom matrices), then the answer bytes
+    const uint64_t cmb = j->cm_bytes;
+    const uint64_t need = (uint64_t)n * cmb + align_up(j->T, 256) + 256;
+    if (need > j->arena_region) return LTL_E_OOM;
+    std::vector<const T *> cm(n);
+    Rows<T> rw = make_rows<T>(j);
+    for (uint32_t k = 0; k < n; ++k) {
+        const ltl_node &v = nodes[k];
+        if (v.op == LTL_ATOM) {
+            cm[k] = (const T *)j->atoms + (uint64_t)v.a * j->R;
+            continue;
+        }
+        T *dst = (T *)(j->arena + (uint64_t)k * cmb);
+        const bool bin = v.op == LTL_AND || v.op == LTL_OR || v.op == LTL_U;
+        HIP_TRY(Launch<T>::formula_node(rw, j->mw, (int)v.op, cm[v.a], bin ? cm[v.b] : nullptr, dst, j->s));
+        cm[k] = dst;
+    }
+    uint8_t *bits_d = (uint8_t *)(j->arena + align_up((uint64_t)n * cmb, 256));
+    HIP_TRY(Launch<T>::first_bits(cm[n - 1], j->row_trace, j->row_word, j->R, bits_d, j->s));
+    HIP_TRY(hipMemcpyAsync(out, bits_d, j->T, hipMemcpyDeviceToHost, j->s));
+    HIP_TRY(hipStreamSynchronize(j->s));
+    return LTL_OK;
+}
+
+extern "C" int ltl_holds(ltl_ctx *ctx, const ltl_spec *spec, const ltl_node *nodes, uint32_t num_nodes,
+                         uint8_t *out) {
+    if (!ctx || !spec || !nodes || !out || num_nodes < 1) return LTL_E_INVAL;
+    if ((uint64_t)spec->num_pos + spec->num_neg > 0x7FFFFFFFull) return LTL_E_INVAL;
+    for (uint32_t k = 0; k < num_nodes; ++k) {
+        const ltl_node &v = nodes[k];
+        if (v.op > LTL_U) return LTL_E_INVAL;
+        if (v.op == LTL_ATOM) {
+            if (v.a >= spec->num_props) return LTL_E_INVAL;
+        } else {
+            const bool bin = v.op == LTL_AND || v.op == LTL_OR || v.op == LTL_U;
+            if (v.a >= k || (bin && v.b >= k)) return LTL_E_INVAL;
+        }
+    }
+    // every trace in one class: the classes play no part here (and need not be disjoint)
+    ltl_spec all = *spec;
+    all.num_pos = spec->num_pos + spec->num_neg;
+    all.num_neg = 0;
+    ltl_opset ops{};
+    ops.op_mask = 1u;
+    ops.cost[LTL_ATOM] = 1;
+    ltl_job *j = nullptr;
+    int st = ltl_job_create(ctx, &all, &ops, 1, &j);
+    if (st != LTL_OK) return st;
+    st = (j->wbits == 64) ? holds_t<uint64_t>(j, nodes, num_nodes, out) : holds_t<uint32_t>(j, nodes, num_nodes, out);
     ltl_job_destroy(j);
     return st;
 }

@@ -133,6 +133,12 @@ struct Launch {
     static hipError_t pack(const uint32_t *letters, const uint64_t *offsets, const uint32_t *row_trace,
                            const uint32_t *row_word, uint32_t R, uint32_t nprops, T *atoms, Counters *ctr,
                            hipStream_t s);
+    // formula evaluation: one node's matrix from its children's (op NOT .. U)
+    static hipError_t formula_node(const Rows<T> &rw, bool mw, int op, const T *pa, const T *pb, T *dst,
+                                   hipStream_t s);
+    // position 0 of every trace of a matrix, one byte per trace
+    static hipError_t first_bits(const T *cm, const uint32_t *row_trace, const uint32_t *row_word, uint32_t R,
+                                 uint8_t *out, hipStream_t s);
 };
 
 hipError_t launch_scan(const uint32_t *bits, uint32_t nw, uint32_t *chunk_sums, uint32_t *wordpre, hipStream_t s);

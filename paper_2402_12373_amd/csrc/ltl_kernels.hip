@@ -56,6 +56,8 @@ struct RowMeta {
     T v, sm, sw;
     uint64_t nx, hn;
     uint32_t k0, k1;
+    uint32_t cont;     // multi-word rows: all ones if the next lane holds the next word of this
+                       // lane's trace, else 0
 };
 
 // Global-address-space views: loads through them become global_load with a
@@ -118,41 +120,56 @@ __device__ __forceinline__ RowMeta<T> load_meta(const Rows<T> &rw, uint32_t r, i
         m.nx = 0;
     }
     m.hn = 0;
+    m.cont = 0;
     return m;
 }
 
 // Wave-uniform part of the metadata, computed once the loads have landed.
 template <typename T, bool MW>
 __device__ __forceinline__ void finish_meta(RowMeta<T> &m, int lane) {
-    if constexpr (MW) m.hn = __ballot((m.nx & (2ull << lane)) != 0ull);
+    if constexpr (MW) {
+        const bool c = (m.nx & (2ull << lane)) != 0ull;
+        m.hn = __ballot(c);
+        m.cont = c ? ~0u : 0u;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Connectives
 // ---------------------------------------------------------------------------
 
-// The value of the next lane (lane 63 reads 0): a DPP whole-wave shift by one
-// lane, one VALU move per 32-bit half instead of a permute through LDS.  Every
-// lane of the wave must be active (rows are padded to whole 64-row blocks).
-__device__ __forceinline__ uint64_t from_next_lane(uint64_t x) {
+// 32-bit half of the next lane (lane 63 reads 0): one DPP whole-wave move.
+__device__ __forceinline__ uint32_t next_lane32(uint32_t x) {
     constexpr int WAVE_SHL1 = 0x130;
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)x, WAVE_SHL1, 0xF, 0xF, true);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), WAVE_SHL1, 0xF, 0xF, true);
-    return ((uint64_t)hi << 32) | lo;
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, WAVE_SHL1, 0xF, 0xF, true);
 }
 
 // Shift toward earlier positions by s within each trace: bits of later words of
-// the same trace move in; nothing crosses into another trace.
+// the same trace move in; nothing crosses into another trace.  Below 64 positions
+// the word is a pair of 32-bit halves and each half of the result is one funnel
+// shift (v_alignbit) of two neighbouring halves of this word and the next one
+// (only the halves that reach the result are moved across lanes); the next word's
+// halves are masked to 0 where the trace ends at this lane.
 template <typename T, bool MW>
 __device__ __forceinline__ T shl_pos(T x, uint32_t s, const RowMeta<T> &m, int lane) {
     if constexpr (!MW) {
         return x << s;
     } else {
-        if (s <= 64) {
-            // the move runs in every lane; lanes whose trace ends here drop it
-            const uint64_t nx = from_next_lane(x);
-            const uint64_t nw = (m.nx & (2ull << lane)) ? nx : 0ull;
-            return s < 64 ? (x << s) | (nw >> (64u - s)) : (T)nw;
+        const uint32_t hi = (uint32_t)(x >> 32), lo = (uint32_t)x;
+        if (s < 32) {
+            // the moves run in every lane; lanes whose trace ends here drop the value
+            const uint32_t nhi = next_lane32(hi) & m.cont;
+            const uint32_t sh = 32u - s;
+            return ((uint64_t)__builtin_amdgcn_alignbit(hi, lo, sh) << 32) | __builtin_amdgcn_alignbit(lo, nhi, sh);
+        } else if (s == 32) {
+            const uint32_t nhi = next_lane32(hi) & m.cont;
+            return ((uint64_t)lo << 32) | nhi;
+        } else if (s <= 64) {
+            const uint32_t nhi = next_lane32(hi) & m.cont;
+            const uint32_t nlo = next_lane32(lo) & m.cont;
+            if (s == 64) return ((uint64_t)nhi << 32) | nlo;
+            const uint32_t sh = 64u - s;
+            return ((uint64_t)__builtin_amdgcn_alignbit(lo, nhi, sh) << 32) | __builtin_amdgcn_alignbit(nhi, nlo, sh);
         } else {
             uint32_t q = s >> 6;
             uint32_t src = (uint32_t)lane + q;
@@ -1501,6 +1518,52 @@ __global__ void k_trace_fp(const uint32_t *letters, const uint64_t *offsets, uin
 }
 
 // ---------------------------------------------------------------------------
+// Formula evaluation (position-0 truth of a given formula on every trace)
+// ---------------------------------------------------------------------------
+// One node of a formula: its whole matrix from its children's, one row block per
+// wave (traces never straddle a row block, so the blocks are independent).
+template <typename T, bool MW, int OP>
+__device__ __forceinline__ void node_block(const Rows<T> &rw, const T *pa, const T *pb, T *dst, uint32_t blk,
+                                           int lane) {
+    constexpr bool BIN = (OP == LTL_AND || OP == LTL_OR || OP == LTL_U);
+    const uint32_t r = blk * 64u + (uint32_t)lane;
+    RowMeta<T> m = load_meta<T, MW, false>(rw, r, lane);
+    finish_meta<T, MW>(m, lane);
+    const T a = ldg(as_global<T>(pa), r);
+    const T b = BIN ? ldg(as_global<T>(pb), r) : (T)0;
+    stg(dst, r, apply<T, MW, OP>(a, b, m, rw, lane));
+}
+
+template <typename T, bool MW>
+__global__ __launch_bounds__(256) void k_formula_node(Rows<T> rw, int op, const T *pa, const T *pb, T *dst) {
+    const int lane = (int)__lane_id();
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t blk = wave; blk < rw.NB; blk += nwaves) {
+        switch (op) {
+        case LTL_NOT: node_block<T, MW, LTL_NOT>(rw, pa, pb, dst, blk, lane); break;
+        case LTL_AND: node_block<T, MW, LTL_AND>(rw, pa, pb, dst, blk, lane); break;
+        case LTL_OR:  node_block<T, MW, LTL_OR>(rw, pa, pb, dst, blk, lane); break;
+        case LTL_X:   node_block<T, MW, LTL_X>(rw, pa, pb, dst, blk, lane); break;
+        case LTL_F:   node_block<T, MW, LTL_F>(rw, pa, pb, dst, blk, lane); break;
+        case LTL_G:   node_block<T, MW, LTL_G>(rw, pa, pb, dst, blk, lane); break;
+        default:      node_block<T, MW, LTL_U>(rw, pa, pb, dst, blk, lane); break;
+        }
+    }
+}
+
+// Position 0 of each trace (the top bit of its first word) -> one byte per trace.
+template <typename T>
+__global__ void k_first_bits(const T *cm, const uint32_t *row_trace, const uint32_t *row_word, uint32_t R,
+                             uint8_t *out) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const uint32_t t = row_trace[r];
+    if (t == 0xFFFFFFFFu || row_word[r] != 0u) return;
+    out[t] = (uint8_t)((cm[r] >> (Word<T>::BITS - 1)) & (T)1);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers (host side of this translation unit)
 // ---------------------------------------------------------------------------
 // Multi-word kernels (lanes of one trace exchange bits) exist for 64-bit words only.
@@ -1630,6 +1693,27 @@ hipError_t Launch<T>::pack(const uint32_t *letters, const uint64_t *offsets, con
     const uint64_t threads = (uint64_t)R * Word<T>::BITS;
     hipLaunchKernelGGL((k_pack<T>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, letters, offsets, row_trace,
                        row_word, R, nprops, atoms, ctr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::formula_node(const Rows<T> &rw, bool mw, int op, const T *pa, const T *pb, T *dst,
+                                   hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((rw.NB + 3) / 4, 4096));
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            hipLaunchKernelGGL((k_formula_node<T, true>), dim3(grid), dim3(256), 0, s, rw, op, pa, pb, dst);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_formula_node<T, false>), dim3(grid), dim3(256), 0, s, rw, op, pa, pb, dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::first_bits(const T *cm, const uint32_t *row_trace, const uint32_t *row_word, uint32_t R,
+                                 uint8_t *out, hipStream_t s) {
+    hipLaunchKernelGGL((k_first_bits<T>), dim3((R + 255) / 256), dim3(256), 0, s, cm, row_trace, row_word, R, out);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(PKG, "libltl.so")
 
 LTL_OK, LTL_NOT_FOUND = 0, 1
 LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG, LTL_E_OOM, LTL_E_DEVICE, LTL_E_STATE = -1, -2, -3, -4, -5, -6
+LTL_E_BUFFER = -7
 ATOM, NOT, AND, OR, X, F, G, U = range(8)
 CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL, CTX_RUC = 0x1, 0x2, 0x4, 0x8
 BATCH_BIG_ALONE = 0x100    # batch flag: whole-row levels of different lanes take turns
@@ -31,7 +32,7 @@ KERNEL_KINDS = ("eval", "verify", "materialize", "compact", "fallback", "intake"
 EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", "ltl_batch_create", "ltl_batch_run",
            "ltl_batch_destroy", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
-           "ltl_status_str", "ltl_overfit", "ltl_batch_serve")
+           "ltl_status_str", "ltl_overfit", "ltl_batch_serve", "ltl_holds", "ltl_det_split", "ltl_rand_split")
 
 
 class LTLError(RuntimeError):
@@ -44,7 +45,7 @@ class LTLError(RuntimeError):
 class CtxOpts(C.Structure):
     _fields_ = [("device", C.c_int32), ("flags", C.c_uint32), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_uint64), ("stream", C.c_void_p), ("hash_slots_log2", C.c_uint32),
-                ("word_bits", C.c_uint32), ("fp_bits", C.c_uint32), ("reserved", C.c_uint32),
+                ("word_bits", C.c_uint32), ("fp_bits", C.c_uint32), ("split_tiles", C.c_uint32),
                 ("max_entries", C.c_uint64)]
 
 
@@ -128,6 +129,13 @@ def load_library(path: str = LIB_PATH):
     L.ltl_job_result.restype = C.c_int
     L.ltl_overfit.argtypes = [P(Spec), P(OpSet), P(Node), C.c_uint32, P(C.c_uint32), P(C.c_uint64)]
     L.ltl_overfit.restype = C.c_int
+    L.ltl_holds.argtypes = [C.c_void_p, P(Spec), P(Node), C.c_uint32, C.c_void_p]
+    L.ltl_holds.restype = C.c_int
+    L.ltl_det_split.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(Node), C.c_uint32, P(C.c_uint32)]
+    L.ltl_det_split.restype = C.c_int
+    L.ltl_rand_split.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, C.c_uint64, P(Node), C.c_uint32,
+                                 P(C.c_uint32)]
+    L.ltl_rand_split.restype = C.c_int
     L.ltl_job_formula.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P(Node), C.c_uint32, P(C.c_uint32)]
     L.ltl_job_formula.restype = C.c_int
     L.ltl_job_dump_cm.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, C.c_void_p, C.c_uint64]
@@ -269,7 +277,8 @@ class Context:
     """An ltl_ctx over a torch-allocated device workspace."""
 
     def __init__(self, workspace_bytes: int = 1 << 30, device: int = 0, flags: int = 0, hash_slots_log2: int = 0,
-                 word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0, stream=None, workspace=None):
+                 word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0, stream=None, workspace=None,
+                 split_tiles: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
@@ -291,6 +300,7 @@ class Context:
         o.hash_slots_log2 = hash_slots_log2
         o.word_bits = word_bits
         o.fp_bits = fp_bits
+        o.split_tiles = split_tiles
         o.max_entries = max_entries
         self.opts = o
         h = C.c_void_p()
@@ -481,180 +491,66 @@ def learn_batch(specs, bounds, lanes: int = 8, workspace_bytes: int = 8 << 30, d
     return [_convert(res[i]) for i in range(n)], [ms[2 * i] for i in range(n)], [ms[2 * i + 1] for i in range(n)]
 
 
-# ---------------------------------------------------------------- divide and conquer (Sec. 6)
+# ---------------------------------------------------------------- formulas on traces, divide and conquer (Sec. 6)
 
-def holds_at_start(nodes, traces) -> np.ndarray:
-    """Position-0 truth of a postfix formula on each trace (lists of letters, bit k of a
-    letter = proposition k).  Host-side, for the language tests of the splitting driver;
-    finite-trace semantics of Sec. 2 (strong X, nothing holds past the end)."""
-    out = np.zeros(len(traces), dtype=bool)
-    for t, tr in enumerate(traces):
-        n = len(tr)
-        val = []
-        for op, a, b in nodes:
-            if op == ATOM:
-                v = np.array([(int(l) >> a) & 1 for l in tr], dtype=bool)
-            elif op == NOT:
-                v = ~val[a]
-            elif op == AND:
-                v = val[a] & val[b]
-            elif op == OR:
-                v = val[a] | val[b]
-            elif op == X:
-                v = np.zeros(n, dtype=bool); v[:-1] = val[a][1:]
-            elif op == F:
-                v = np.logical_or.accumulate(val[a][::-1])[::-1]
-            elif op == G:
-                v = np.logical_and.accumulate(val[a][::-1])[::-1]
-            else:     # U: psi now, or phi now and U at the next position
-                v = np.zeros(n, dtype=bool)
-                nxt = False
-                for i in range(n - 1, -1, -1):
-                    nxt = bool(val[b][i]) or (bool(val[a][i]) and nxt)
-                    v[i] = nxt
-            val.append(v)
-        out[t] = bool(val[-1][0])
-    return out
+class _Traces:
+    """An (instance-like) host specification built from explicit traces."""
+
+    def __init__(self, pos, neg, num_props: int):
+        traces = [list(t) for t in pos] + [list(t) for t in neg]
+        self.num_props, self.num_pos, self.num_neg = int(num_props), len(pos), len(neg)
+        self.offsets = np.zeros(len(traces) + 1, dtype=np.uint64)
+        self.offsets[1:] = np.cumsum([len(t) for t in traces], dtype=np.uint64)
+        self.letters = np.asarray([x for t in traces for x in t], dtype=np.uint32)
+        self.total_positions = int(self.offsets[-1])
 
 
-def _join(op, f, g):
-    """f op g for postfix node lists (g's child indices shifted past f)."""
-    k = len(f)
-    g2 = [(o, a + k if o != ATOM else a, (b + k) if o in (AND, OR, U) else b) for o, a, b in g]
-    return f + g2 + [(op, k - 1, k + len(g) - 1)]
+def _node_array(nodes):
+    arr = (Node * max(1, len(nodes)))()
+    for k, (op, a, b) in enumerate(nodes):
+        arr[k].op, arr[k].a, arr[k].b = op, a, b
+    return arr
 
 
-def det_split(ctx: "Context", pos, neg, num_props: int, win: int, cost=None, ops=None, _depth=0):
-    """Deterministic splitting (Sec. 6) over the learner of Sec. 3 (`learn_complete` on the
-    context).  pos, neg: lists of traces (lists of letters).  Returns (status, nodes): LTL_OK
-    and a sound (not necessarily minimal) formula, or LTL_E_OOM when even the smallest window
-    runs out of memory.
-      (P, N) of at most `win` traces (or nothing left to split): the learner;
-      else P1/P2 and N1/N2 halves (in order) and, with L = L(phi11) and L(phi12) (both):
-        phi11 = split(P1, N1); phi12 = split(P1, N2 in L(phi11));
-        phi21 = split(P2 - L, N1); phi22 = split(P2 - L, N2 in L(phi21));
-        result (phi11 and phi12) or (phi21 and phi22);
-      a part with no positive trace contributes nothing, a conjunct with no negative trace
-      left is dropped; on out-of-memory in any part, the whole call again with win / 2."""
-    if not pos:
-        return LTL_OK, None               # nothing to accept: no disjunct
-    if len(pos) + len(neg) <= win or (len(pos) <= 1 and len(neg) <= 1):
-        from ltl_inputs import synth
-        inst = synth.from_traces(pos, neg, num_props)
-        r = learn_complete(ctx, inst, cost=cost, ops=ops)
-        if r.status == LTL_OK:
-            return LTL_OK, r.solution
-        if r.status == LTL_NOT_FOUND:     # overfitting costs more than the level range: use it
-            return LTL_OK, overfit(inst, cost, ops)[0]
-        return r.status, None
-    h, k = len(pos) // 2, len(neg) // 2
-    P1, P2, N1, N2 = pos[:h], pos[h:], neg[:k], neg[k:]
+def holds(ctx: "Context", traces, nodes, num_props: int) -> np.ndarray:
+    """tr |= phi for each trace (ltl_holds: the formula evaluated on the device)."""
+    if not traces:
+        return np.zeros(0, dtype=bool)
+    sb = SpecBuffers(_Traces(traces, [], num_props))
+    out = np.zeros(len(traces), dtype=np.uint8)
+    st = ctx.L.ltl_holds(ctx.h, C.byref(sb.c), _node_array(nodes), len(nodes), out.ctypes.data)
+    if st != LTL_OK:
+        raise LTLError(st, "ltl_holds")
+    return out.astype(bool)
 
-    def sub(P, N):
-        return det_split(ctx, P, N, num_props, win, cost, ops, _depth + 1)
 
-    def conj(P, Na, Nb):
-        st, f1 = sub(P, Na)
-        if st != LTL_OK or f1 is None:
-            return st, f1
-        keep = [n for n, m in zip(Nb, holds_at_start(f1, Nb)) if m]
-        if not keep:
-            return LTL_OK, f1
-        st, f2 = sub(P, keep)
+def _split_call(fn, args, what):
+    n = C.c_uint32(0)
+    cap = 1024
+    while True:
+        buf = (Node * cap)()
+        st = fn(*args, buf, cap, C.byref(n))
+        if st == LTL_E_BUFFER:
+            cap = int(n.value)
+            continue
         if st != LTL_OK:
             return st, None
-        return LTL_OK, _join(AND, f1, f2)
+        return LTL_OK, [(int(buf[k].op), int(buf[k].a), int(buf[k].b)) for k in range(n.value)]
 
-    st, a = conj(P1, N1, N2)
-    if st == LTL_OK:
-        rest = P2 if a is None else [p for p, m in zip(P2, holds_at_start(a, P2)) if not m]
-        st, b = conj(rest, N1, N2)
-    if st == LTL_E_OOM:
-        if win <= 1:
-            return LTL_E_OOM, None
-        return det_split(ctx, pos, neg, num_props, win // 2, cost, ops, _depth + 1)
-    if st != LTL_OK:
-        return st, None
-    if a is None:
-        return LTL_OK, b
-    return LTL_OK, a if b is None else _join(OR, a, b)
+
+def det_split(ctx: "Context", pos, neg, num_props: int, win: int, cost=None, ops=None):
+    """Deterministic splitting (ltl_det_split, Sec. 6).  Returns (status, postfix nodes or
+    None): LTL_OK and a sound formula, or LTL_E_OOM when even a window of 1 runs out of
+    memory."""
+    sb = SpecBuffers(_Traces(pos, neg, num_props))
+    o = opset(cost, ops)
+    return _split_call(ctx.L.ltl_det_split, (ctx.h, C.byref(sb.c), C.byref(o), int(win)), "ltl_det_split")
 
 
 def rand_split(ctx: "Context", pos, neg, num_props: int, win: int, seed: int = 0, cost=None, ops=None):
-    """Random splitting (Sec. 6) over the learner of Sec. 3.  Returns (status, nodes).
-      fits in `win`: the learner on (P, N);
-      else phi11 = the learner on a random sub-specification (P0, N0) of at most `win` traces,
-      the two classes as equal in size as the window allows (window halved on out-of-memory),
-      and with A = L(phi11):
-        phi12 = split(P in A, N in A); phi21 = split(P - A, N - A); phi22 = split(P - A, N in A);
-        result (phi11 and phi12) or (phi21 and phi22).
-    The subsets come from synth.sample_subset(seed, call, ...), calls numbered in the order
-    the recursion makes them, so a run is reproducible."""
-    from ltl_inputs import synth
-    counter = [0]
-
-    def learn_leaf(P, N):
-        inst = synth.from_traces(P, N, num_props)
-        r = learn_complete(ctx, inst, cost=cost, ops=ops)
-        if r.status == LTL_OK:
-            return LTL_OK, r.solution
-        if r.status == LTL_NOT_FOUND:
-            return LTL_OK, overfit(inst, cost, ops)[0]
-        return r.status, None
-
-    def sample(P, N, w):
-        total = min(w, len(P) + len(N))
-        kp = min(len(P), (total + 1) // 2)
-        kn = min(len(N), total - kp)
-        kp = min(len(P), total - kn)
-        call = counter[0]
-        counter[0] += 1
-        ip = synth.sample_subset(seed, 2 * call, len(P), kp)
-        ineq = synth.sample_subset(seed, 2 * call + 1, len(N), kn)
-        return [P[i] for i in ip], [N[i] for i in ineq]
-
-    def split(P, N):
-        if not P:
-            return LTL_OK, None
-        if not N:                      # nothing to reject: true, which costs nothing to conjoin
-            return LTL_OK, []
-        if len(P) + len(N) <= win:
-            return learn_leaf(P, N)
-        w = win
-        while True:
-            if w < 2:              # a sample needs a trace of each class to make progress
-                return LTL_E_OOM, None
-            P0, N0 = sample(P, N, w)
-            st, f11 = learn_leaf(P0, N0)
-            if st != LTL_E_OOM:
-                break
-            w //= 2
-        if st != LTL_OK:
-            return st, None
-        inP, inN = holds_at_start(f11, P), holds_at_start(f11, N)
-        parts = []
-        for PP, NN in (([p for p, m in zip(P, inP) if m], [n for n, m in zip(N, inN) if m]),
-                       ([p for p, m in zip(P, inP) if not m], [n for n, m in zip(N, inN) if not m]),
-                       ([p for p, m in zip(P, inP) if not m], [n for n, m in zip(N, inN) if m])):
-            st, f = split(PP, NN)
-            if st != LTL_OK:
-                return st, None
-            parts.append(f)
-        f12, f21, f22 = parts
-
-        def conj(f, g):
-            if f is None or g is None:
-                return None            # a part without positives: false
-            if not g:
-                return f
-            if not f:
-                return g
-            return _join(AND, f, g)
-
-        first, second = conj(f11, f12), conj(f21, f22)
-        if first is None:
-            return LTL_OK, second
-        return LTL_OK, first if second is None else _join(OR, first, second)
-
-    st, f = split(list(pos), list(neg))
-    return st, f
+    """Random splitting (ltl_rand_split, Sec. 6) with the library's counter-based subset
+    draws from `seed`.  Returns (status, postfix nodes or None)."""
+    sb = SpecBuffers(_Traces(pos, neg, num_props))
+    o = opset(cost, ops)
+    return _split_call(ctx.L.ltl_rand_split, (ctx.h, C.byref(sb.c), C.byref(o), int(win), int(seed)),
+                       "ltl_rand_split")

@@ -1,5 +1,9 @@
 """Parity at the benchmark's full sizes, in the configuration bench.py times.
 
+* long workload, whole jobs to the minimal cost, seeds 0-3: status, minimal cost,
+  every level's counts, the canonical index and formula of the first solution equal
+  the oracle's stored results (tests/golden/long_workload.txt, written by
+  tests/golden/make_long_golden.py, which calls only the oracle);
 * scale workload (3 props, 1024+1024 traces, len 16..32, bound 11, 2^26 hash
   slots), the eight benchmark seeds: status, minimal cost, every level's counts
   and the first solution equal the oracle's (the oracle runs every level);
@@ -67,3 +71,36 @@ def test_long_workload_levels(ltl, big_ctx, seed):
                 np.testing.assert_array_equal(job.dump_cm(c, e), run.entry_cm(c, e), err_msg=f"{c}/{e}")
     finally:
         job.close()
+
+
+def _long_golden():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "long_workload.txt")
+    out = {}
+    if os.path.exists(path):
+        for ln in open(path):
+            if not ln.strip() or ln.startswith("#"):
+                continue
+            f = [x.strip() for x in ln.split("::")]
+            seed, st, cost, done = (int(x) for x in f[:4])
+            E = [int(x) for x in f[4].split(",")]
+            Cn = [int(x) for x in f[5].split(",")]
+            sol = None if f[7] == "-" else [tuple(int(v) for v in nd.split(",")) for nd in f[7].split(";")]
+            out[seed] = dict(status=st, cost=cost, done=done, E=E, C=Cn, first=int(f[6]), sol=sol)
+    return out
+
+
+LONG_GOLDEN = _long_golden()
+
+
+@pytest.mark.parametrize("seed", sorted(LONG_GOLDEN))
+def test_long_workload_golden(ltl, big_ctx, seed):
+    """Whole long-workload jobs (multi-word rows, U doubling across words, whole-row levels)
+    against the oracle's results."""
+    want = LONG_GOLDEN[seed]
+    inst, cfg = synth.preset_instance("long", seed)
+    print("long golden seed", seed, flush=True)
+    g = big_ctx.learn(ltl.spec_to_device(inst), cfg["bound"])
+    assert (g.status, g.levels_done) == (want["status"], want["done"])
+    assert g.level_new[1:] == want["E"] and g.level_candidates[1:] == want["C"]
+    if want["status"] == 0:
+        assert (g.cost, g.solution_index, g.solution) == (want["cost"], want["first"], want["sol"])

@@ -119,9 +119,28 @@ LENGTH_SETS = [
 ]
 
 
+@pytest.fixture(scope="module")
+def ctx_whole(ltl):
+    """Every level on the whole-row kernels (one wave per tile, one dispatch per class,
+    separate write pass, member marking on levels that are not stored)."""
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, split_tiles=1)
+    yield c
+    c.close()
+
+
+PATHS = ["row-split", "whole-row"]
+
+
+def _pick(ctx, ctx_whole, path):
+    return ctx_whole if path == "whole-row" else ctx
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("lengths", LENGTH_SETS, ids=lambda l: "len" + "-".join(map(str, l)))
-def test_word_boundaries(ltl, ctx, lengths):
-    """Traces straddling word boundaries (single and multi-word rows), all matrices to level 4."""
+def test_word_boundaries(ltl, ctx, ctx_whole, lengths, path):
+    """Traces straddling word boundaries (single and multi-word rows), all matrices to level 4,
+    on the row-split kernels (what these small levels use by default) and forced onto the
+    whole-row kernels."""
     rng = np.random.default_rng(sum(lengths))
     pos, neg = [], []
     for k in range(8):
@@ -129,8 +148,29 @@ def test_word_boundaries(ltl, ctx, lengths):
         tr = [int(x) for x in rng.integers(0, 4, size=n)]
         (pos if k % 2 == 0 else neg).append(tr)
     inst = synth.from_traces(pos, neg, 2)
-    _say("boundaries", lengths)
-    _level_by_level(ltl, ctx, inst, 4, max_entries_per_level=200)
+    _say("boundaries", lengths, path)
+    _level_by_level(ltl, _pick(ctx, ctx_whole, path), inst, 4, max_entries_per_level=200)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_until_chains_every_doubling_step(ltl, ctx, ctx_whole, path):
+    """p0 U p1 over runs of 64, 127-129, 255-257 and 511 positions (App. B doubling across
+    64-position words; each step s = 64, 128, 256 is the first to set some bit, checked on
+    the CPU in test_until_chains.py): every stored matrix of levels 1-4 and every entry
+    formula of level 5 equal the oracle's."""
+    inst = synth.until_chain_instance(0)
+    _say("until chains", path)
+    g, _ = _level_by_level(ltl, _pick(ctx, ctx_whole, path), inst, 5, max_entries_per_level=400)
+    assert g.level_new[1] == 2
+
+
+@pytest.mark.parametrize("seed", [0, 5, 9])
+def test_whole_row_tiny(ltl, ctx_whole, seed):
+    """Tiny 32-bit levels forced onto the whole-row kernels: the learned result and every
+    stored matrix equal the oracle's."""
+    inst, cfg = synth.preset_instance("tiny", seed)
+    _say("whole-row tiny", seed)
+    _level_by_level(ltl, ctx_whole, inst, cfg["bound"])
 
 
 def test_single_word_u64_rows(ltl):
@@ -176,8 +216,11 @@ def test_forced_fingerprint_collisions(ltl, fp_bits):
         c.close()
 
 
-def test_forced_collisions_multiword(ltl):
-    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, fp_bits=6)
+@pytest.mark.parametrize("split_tiles", [0, 1], ids=PATHS)
+def test_forced_collisions_multiword(ltl, split_tiles):
+    """6-bit fingerprints on multi-word rows: the exact re-check (representatives'
+    matrices, verification against them, the sequential fallback) on both kernel paths."""
+    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, fp_bits=6, split_tiles=split_tiles)
     try:
         rng = np.random.default_rng(11)
         inst = random_instance(rng, 2, 3, 3, 70, 140)
@@ -477,6 +520,35 @@ def test_learn_complete(ltl, ctx, monkeypatch):
     assert (r.status, r.cost, r.solution, r.solution_index, r.levels_done) == (ltl.LTL_OK, 2, nodes, None, 1)
 
 
+def _sound_by_oracle(inst, nodes):
+    """The formula accepts every P trace and no N trace under the oracle's evaluator."""
+    cm = O.eval_formula(O.Spec.of(inst), nodes, O.MODE_EXPAND)
+    offs = inst.offsets.astype(np.int64)
+    assert all(cm[offs[t]] for t in range(inst.num_pos))
+    assert not any(cm[offs[t]] for t in range(inst.num_pos, inst.num_traces))
+
+
+def test_holds_matches_oracle(ltl, ctx):
+    """ltl_holds (a given formula evaluated on the device) equals the oracle's position-0
+    truth on single- and multi-word traces, for formulas of every connective."""
+    rng = np.random.default_rng(42)
+    for lo, hi in ((4, 8), (30, 70), (200, 512)):
+        inst = random_instance(rng, 3, 12, 12, lo, hi)
+        spec = O.Spec.of(inst)
+        offs = inst.offsets.astype(np.int64)
+        trs = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_traces)]
+        for size in (1, 3, 5, 7, 9):
+            for k in range(6):
+                nodes = synth.draw_formula(rng, size, 3)
+                want = O.eval_formula(spec, nodes, O.MODE_QUANT)[offs[:-1]].astype(bool)
+                got = ltl.holds(ctx, trs, nodes, 3)
+                assert (got == want).all(), (lo, hi, nodes)
+    with pytest.raises(ltl.LTLError):
+        ltl.holds(ctx, [[1, 0]], [(ltl.ATOM, 5, 0)], 3)             # a missing proposition
+    with pytest.raises(ltl.LTLError):
+        ltl.holds(ctx, [[1, 0]], [(ltl.NOT, 0, 0)], 3)              # a child that is not earlier
+
+
 @pytest.mark.parametrize("cap", [0, 40], ids=["no-cap", "entry-cap-40"])
 def test_det_split_parity(ltl, cap):
     """Deterministic splitting (Sec. 6) over the GPU learner equals the same splitting over
@@ -495,15 +567,16 @@ def test_det_split_parity(ltl, cap):
                 o = O.det_split(P, N, inst.num_props, win, max_entries=cap)
                 assert g[0] == o[0] and g[1] == o[1], (seed, win, g, o)
                 if g[0] == ltl.LTL_OK:
-                    assert all(ltl.holds_at_start(g[1], P)) and not any(ltl.holds_at_start(g[1], N))
+                    _sound_by_oracle(inst, g[1])
     finally:
         c.close()
 
 
 @pytest.mark.parametrize("cap", [0, 40], ids=["no-cap", "entry-cap-40"])
 def test_rand_split_parity(ltl, cap):
-    """Random splitting (Sec. 6) over the GPU learner equals the same splitting over the
-    oracle (the random subsets come from the shared input sampler), formula for formula."""
+    """Random splitting (Sec. 6) in the library equals the oracle's driver formula for
+    formula: both draw the random subsets from their own SplitMix64 streams (the same
+    published generator); with an entry cap of 40 windows are halved on both sides alike."""
     c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=20, max_entries=cap)
     try:
         for seed in range(6):
@@ -517,7 +590,7 @@ def test_rand_split_parity(ltl, cap):
                 o = O.rand_split(P, N, inst.num_props, win, seed=rs, max_entries=cap)
                 assert g[0] == o[0] and g[1] == o[1], (seed, win, g, o)
                 if g[0] == ltl.LTL_OK:
-                    assert all(ltl.holds_at_start(g[1], P)) and not any(ltl.holds_at_start(g[1], N))
+                    _sound_by_oracle(inst, g[1])
     finally:
         c.close()
 

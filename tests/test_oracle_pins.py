@@ -476,3 +476,47 @@ def test_rand_split_is_sound_and_reproducible(seed):
         assert O.rand_split(P, N, inst.num_props, win, seed=rs) == (st, f)
     st, f = O.rand_split(P, N, inst.num_props, len(P) + len(N))
     assert f == O.learn(inst, cfg["bound"], mode=O.MODE_EXPAND).solution
+
+
+# ---------------------------------------------------------------- random splitting's subsets
+
+def test_splitmix64_published_outputs():
+    # SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the first output of the generator
+    # seeded with 0 is 0xE220A8397B1DCDAF and with 1234567 is 6457827717110365317 (the
+    # values its reference implementation prints)
+    assert O.splitmix64_output(0 + O.SPLITMIX_GAMMA) == 0xE220A8397B1DCDAF
+    assert O.splitmix64_output(1234567 + O.SPLITMIX_GAMMA) == 6457827717110365317
+
+
+def test_sample_subset():
+    from collections import Counter
+    a = O.sample_subset(3, 0, 100, 10)
+    assert a == O.sample_subset(3, 0, 100, 10)                   # replayable
+    assert a == sorted(set(a)) and len(a) == 10 and 0 <= a[0] and a[-1] < 100
+    assert a != O.sample_subset(3, 1, 100, 10)                   # another stream, another subset
+    assert O.sample_subset(3, 0, 5, 5) == [0, 1, 2, 3, 4]
+    assert O.sample_subset(3, 0, 5, 9) == [0, 1, 2, 3, 4]
+    # the k smallest draws of the stream, by brute force over the definition
+    s0 = (7 << 32) + 4
+    draws = [O.splitmix64_output(s0 + (i + 1) * O.SPLITMIX_GAMMA) for i in range(30)]
+    assert O.sample_subset(7, 4, 30, 6) == sorted(sorted(range(30), key=lambda i: draws[i])[:6])
+    # every element equally likely: k/n = 1/4 over 4000 draws of 5 of 20
+    hits = Counter(x for c in range(4000) for x in O.sample_subset(1, c, 20, 5))
+    assert all(abs(v - 1000) < 150 for v in hits.values()) and len(hits) == 20
+
+
+def test_rand_split_halves_a_fitting_window_on_oom():
+    # Sec. 6: randAux halves the window while the enumerator runs out of memory, also when
+    # the whole specification fits the window (it is then drawn whole).  An entry cap of 12
+    # makes the whole tiny specification run out of memory; the halved windows still
+    # give a sound formula.
+    inst, cfg = synth.preset_instance("tiny", 0)
+    offs = inst.offsets.astype(np.int64)
+    trs = [list(map(int, inst.letters[offs[t]:offs[t + 1]])) for t in range(inst.num_traces)]
+    P, N = trs[:inst.num_pos], trs[inst.num_pos:]
+    assert O.learn(inst, cfg["bound"], mode=O.MODE_EXPAND, max_entries=12).status == O.ST_EOOM
+    st, f = O.rand_split(P, N, inst.num_props, len(P) + len(N), seed=0, max_entries=12)
+    assert st == O.ST_OK and f
+    cm = O.eval_formula(O.Spec.of(inst), f, O.MODE_QUANT)
+    assert all(cm[offs[t]] for t in range(inst.num_pos))
+    assert not any(cm[offs[t]] for t in range(inst.num_pos, inst.num_traces))

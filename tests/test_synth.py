@@ -136,18 +136,6 @@ def test_hamming_instance_is_the_full_sphere(length, delta):
     assert len(seen) == inst.num_neg
 
 
-def test_sample_subset():
-    a = synth.sample_subset(3, 0, 100, 10)
-    assert a == synth.sample_subset(3, 0, 100, 10)               # replayable
-    assert a == sorted(set(a)) and len(a) == 10 and 0 <= a[0] and a[-1] < 100
-    assert a != synth.sample_subset(3, 1, 100, 10)               # another call, another subset
-    assert synth.sample_subset(3, 0, 5, 5) == [0, 1, 2, 3, 4]
-    assert synth.sample_subset(3, 0, 5, 9) == [0, 1, 2, 3, 4]
-    # every element equally likely: k/n = 1/4 over 4000 draws of 5 of 20
-    hits = Counter(x for c in range(4000) for x in synth.sample_subset(1, c, 20, 5))
-    assert all(abs(v - 1000) < 150 for v in hits.values()) and len(hits) == 20
-
-
 def test_poisson_arrivals():
     t = synth.poisson_arrivals(2, 20000, 10.0)
     assert t == synth.poisson_arrivals(2, 20000, 10.0)
