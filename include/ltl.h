@@ -188,6 +188,28 @@ typedef struct {
 int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
               ltl_result *out);
 
+/* ---------------------------------------------------------------- learning without allocation */
+
+/* For callers that cannot allocate device memory or call allocating HIP routines
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): ltl_learn on the library's own fixed device scratch array of
+ * LTL_NOALLOC_SCRATCH_BYTES per GPU (a static device array of the library's code
+ * object, held by each GPU the library runs on until the process ends) instead
+ * of a caller workspace.  No hipMalloc, hipHostMalloc, hipFree, stream or event
+ * is created; the caller passes the device, a stream (NULL = the null stream),
+ * the inputs and *out.  The hash table is 2^LTL_NOALLOC_SLOTS_LOG2 slots; U by
+ * doubling; no timing.  A specification or a level that does not fit the array
+ * returns LTL_E_OOM (nothing is allocated instead).  Calls on one GPU share its
+ * array, which keeps the last call's contents (the call clears what must start at
+ * zero); overlapping calls on one GPU would race, so the library runs them one at
+ * a time (the call returns when its work on the stream has ended).  Results
+ * equal ltl_learn's on a context with the same hash table size.  Errors as
+ * ltl_learn, and LTL_E_DEVICE if the array's address cannot be found. */
+#define LTL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define LTL_NOALLOC_SLOTS_LOG2    18
+int ltl_learn_noalloc(int32_t device, void *stream, const ltl_spec *spec, const ltl_opset *ops,
+                      uint32_t cost_bound, ltl_result *out);
+
 /* ---------------------------------------------------------------- batched learning */
 
 /* Many independent learning jobs of uneven sizes, run `lanes` at a time.  Each

@@ -11,7 +11,8 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ltl_kernels.hip", "ltl_host.cpp", "ltl_split.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ltl_kernels.hip", "ltl_host.cpp", "ltl_split.cpp",
+                                                     "ltl_noalloc.hip")]
 LIB = os.path.join(PKG, "libltl.so")
 OBJDIR = os.path.join(PKG, "_build")
 ARCH = os.environ.get("LTL_OFFLOAD_ARCH", "gfx950")

@@ -77,6 +77,10 @@ struct ltl_ctx {
     char *jpin = nullptr;            // page-locked staging of a job's row tables (grown on demand)
     uint64_t jpin_bytes = 0;
     uint32_t table_clean_log2 = 0;   // the hash table at the start of the workspace is empty (this size)
+    // allocation-free contexts (ltl_learn_noalloc): host staging in ordinary memory instead
+    // of page-locked buffers
+    bool noalloc = false;
+    std::vector<char> heap_pinned, heap_jpin;
 };
 
 struct LevelInfo {
@@ -409,7 +413,11 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     const uint64_t tables_bytes = o_rwd + R * 4;
     const uint64_t o_tfp = align_up(tables_bytes, 256);
     const uint64_t jpin_need = o_tfp + (uint64_t)T * 8;
-    if (c->jpin_bytes < jpin_need) {
+    if (c->noalloc) {
+        if (c->heap_jpin.size() < jpin_need) c->heap_jpin.resize(jpin_need);
+        c->jpin = c->heap_jpin.data();
+        c->jpin_bytes = c->heap_jpin.size();
+    } else if (c->jpin_bytes < jpin_need) {
         if (c->jpin) (void)hipHostFree(c->jpin);
         c->jpin = nullptr;
         c->jpin_bytes = 0;
@@ -1315,6 +1323,43 @@ extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *op
     }
     st = ltl_job_result(j, out);
     ltl_job_destroy(j);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// Learning without allocation: the library's static device scratch as workspace
+// ---------------------------------------------------------------------------
+namespace ltl {
+void *noalloc_scratch(int device, hipError_t *err);
+std::mutex &noalloc_lock(int device);
+}  // namespace ltl
+
+extern "C" int ltl_learn_noalloc(int32_t device, void *stream, const ltl_spec *spec, const ltl_opset *ops,
+                                 uint32_t cost_bound, ltl_result *out) {
+    if (!out) return LTL_E_INVAL;
+    memset(out, 0, sizeof(*out));
+    out->solution_index = LTL_NO_SOLUTION;
+    if (device < 0 || device >= 64) return out->status = LTL_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return out->status = LTL_E_DEVICE;
+    std::lock_guard<std::mutex> turn(noalloc_lock(device));
+    hipError_t err = hipSuccess;
+    void *ws = noalloc_scratch(device, &err);
+    if (!ws) return out->status = LTL_E_DEVICE;
+    ltl_ctx c;
+    c.o = ltl_ctx_opts{};
+    c.o.device = device;
+    c.o.workspace = ws;
+    c.o.workspace_bytes = LTL_NOALLOC_SCRATCH_BYTES;
+    c.o.stream = stream;
+    c.o.hash_slots_log2 = LTL_NOALLOC_SLOTS_LOG2;
+    c.s = (hipStream_t)stream;
+    c.noalloc = true;
+    c.heap_pinned.resize(PINNED_BYTES);
+    c.pinned = c.heap_pinned.data();
+    // table_clean_log2 = 0: the job initialises the hash table (the array holds the last
+    // call's contents)
+    const int st = ltl_learn(&c, spec, ops, cost_bound, out);
+    if (c.s) (void)hipStreamSynchronize(c.s); else (void)hipDeviceSynchronize();
     return st;
 }
 

@@ -32,7 +32,8 @@ KERNEL_KINDS = ("eval", "verify", "materialize", "compact", "fallback", "intake"
 EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", "ltl_batch_create", "ltl_batch_run",
            "ltl_batch_destroy", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
-           "ltl_status_str", "ltl_overfit", "ltl_batch_serve", "ltl_holds", "ltl_det_split", "ltl_rand_split")
+           "ltl_status_str", "ltl_overfit", "ltl_batch_serve", "ltl_holds", "ltl_det_split", "ltl_rand_split",
+           "ltl_learn_noalloc")
 
 
 class LTLError(RuntimeError):
@@ -129,6 +130,8 @@ def load_library(path: str = LIB_PATH):
     L.ltl_job_result.restype = C.c_int
     L.ltl_overfit.argtypes = [P(Spec), P(OpSet), P(Node), C.c_uint32, P(C.c_uint32), P(C.c_uint64)]
     L.ltl_overfit.restype = C.c_int
+    L.ltl_learn_noalloc.argtypes = [C.c_int32, C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(Result)]
+    L.ltl_learn_noalloc.restype = C.c_int
     L.ltl_holds.argtypes = [C.c_void_p, P(Spec), P(Node), C.c_uint32, C.c_void_p]
     L.ltl_holds.restype = C.c_int
     L.ltl_det_split.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(Node), C.c_uint32, P(C.c_uint32)]
@@ -263,6 +266,25 @@ def learn_complete(ctx: "Context", inst_or_spec, inst=None, cost=None, ops=None)
     if r.status == LTL_NOT_FOUND and bound == co - 1:
         return replace(r, status=LTL_OK, cost=co, solution=nodes, solution_index=None)
     return r
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # LTL_NOALLOC_SCRATCH_BYTES
+NOALLOC_SLOTS_LOG2 = 18              # LTL_NOALLOC_SLOTS_LOG2
+
+
+def learn_noalloc(inst_or_spec, bound: int, device: int = 0, stream=None, cost=None, ops=None) -> LearnResult:
+    """ltl_learn_noalloc: learning on the library's fixed device scratch array (no workspace,
+    no allocation); `stream` is a torch stream (default: the device's current stream)."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
+    L = load_library()
+    spec = inst_or_spec if isinstance(inst_or_spec, SpecBuffers) else SpecBuffers(inst_or_spec)
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    r = Result()
+    L.ltl_learn_noalloc(device, stream.cuda_stream, C.byref(spec.c), C.byref(opset(cost, ops)), bound, C.byref(r))
+    return _convert(r)
 
 
 def spec_to_device(inst, device="cuda"):
