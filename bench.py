@@ -98,11 +98,20 @@ def main():
     ap.add_argument("--seeds", default="", help="job seeds, e.g. 0-7 (default: 0-3 for long, else 0-7)")
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
-    ap.add_argument("--ucarry", action="store_true", help="U by carry-chain add instead of doubling")
+    ap.add_argument("--ucarry", action="store_true", help="U by the carry adder at every level (LTL_CTX_U_CARRY)")
+    ap.add_argument("--udoubling", action="store_true",
+                    help="U by the doubling of App. B at every level (LTL_CTX_U_DOUBLING); default: doubling on "
+                         "one-word rows, the carry adder on multi-word rows")
+    ap.add_argument("--split-tiles", type=int, default=0,
+                    help="levels of fewer tiles run the row-split kernels (ltl_ctx_opts.split_tiles; "
+                         "0 = the library default, 1 = whole-row kernels at every level)")
     ap.add_argument("--ruc", action="store_true",
                     help="relaxed uniqueness check (LTL_CTX_RUC): fingerprint match taken as equality, no compare")
     ap.add_argument("--big-alone", action="store_true",
                     help="batch lanes take turns for whole-row levels (LTL_BATCH_BIG_ALONE)")
+    ap.add_argument("--slices", action="store_true",
+                    help="batched/served: equal workspace slices per lane instead of one shared budget "
+                         "with regions sized per job (LTL_BATCH_SHARED_BUDGET)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="no per-kernel HIP events (no kernel times, no roofline)")
@@ -179,7 +188,8 @@ def bench_fixed(args):
     free, total = torch.cuda.mem_get_info()
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     slots = 26 if args.workload != "tiny" else 20
-    ucarry = (ltl.CTX_U_CARRY if args.ucarry else 0) | (ltl.CTX_RUC if args.ruc else 0)
+    ucarry = (ltl.CTX_U_CARRY if args.ucarry else 0) | (ltl.CTX_U_DOUBLING if args.udoubling else 0) | \
+        (ltl.CTX_RUC if args.ruc else 0)
     # timed steps: one event pair per level (level GPU time, for the roofline); the one-stream
     # pass: events around every kernel group (time per kernel kind)
     timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
@@ -189,7 +199,8 @@ def bench_fixed(args):
     # lanes > 1: the batch executor takes the workspace; the one-stream comparison run gets a
     # workspace of one lane's size, so both see the same capacity per job
     ctx_bytes = ws_bytes if lanes == 1 else (ws_bytes // (lanes + 1)) & ~255
-    ctx = ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots, flags=full_flags if lanes > 1 else timed_flags)
+    ctx = ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots, flags=full_flags if lanes > 1 else timed_flags,
+                      split_tiles=args.split_tiles)
     if lanes > 1:
         ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots,
                        flags=timed_flags | (ltl.BATCH_BIG_ALONE if args.big_alone else 0))
@@ -237,13 +248,16 @@ def bench_fixed(args):
     job.close()
     geom = dict(R=int(info.rows), halves=int(info.rows) * (int(info.word_bits) // 32), k=int(info.doubling_steps),
                 cm_bytes=int(info.cm_bytes))
+    # the U method the library used: forced by a flag, else by row layout (multi-word rows: carry)
+    multiword = int(info.word_bits) == 64 and max(i.max_len for i in insts) > 64
+    u_carry = args.ucarry or (not args.udoubling and multiword)
     # lanes > 1: the levels of different jobs overlap on the device, so their summed event
     # time counts overlapping intervals more than once; the wall time of the timed steps is
     # the basis then (a lower bound of the fraction)
-    roof, kern_ms, eval_tops, verify_gbs = roofline(ltl, results, geom, args.ucarry,
+    roof, kern_ms, eval_tops, verify_gbs = roofline(ltl, results, geom, u_carry,
                                                     wall_ms=wall * 1e3 if lanes > 1 else None)
     wkey = (f"{args.workload} seeds {args.seeds} bound {cfg['bound']}" + (" ruc" if args.ruc else "")
-            + (" ucarry" if args.ucarry else ""))
+            + (" ucarry" if args.ucarry else "") + (" udoubling" if args.udoubling else ""))
     t = measured_traffic(roof["kind"], wkey)
     roof["traffic"] = None if t is None else round(t / 1e6, 3)
     roof["traffic_unit"] = "MB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
@@ -260,7 +274,7 @@ def bench_fixed(args):
         gc.enable()
         same = all((x.status, x.cost, x.level_new, x.solution_index) == (y.status, y.cost, y.level_new, y.solution_index)
                    for x, y in zip(sres, results[:len(dev)]))
-        sroof, skern, _, _ = roofline(ltl, sres, geom, args.ucarry)
+        sroof, skern, _, _ = roofline(ltl, sres, geom, u_carry)
         seq = {"candidates_per_s": round(sum(r.candidates for r in sres) / sw, 1), "ms_per_step": round(sw * 1e3, 3),
                "roofline_frac": sroof["frac"], "avg_launch_ms": sroof["avg_launch_ms"],
                "kernel_ms_per_step": {k: round(v, 3) for k, v in skern.items()},
@@ -310,7 +324,8 @@ def bench_fixed(args):
         "data": "synthetic",
         "config": {"workload": f"{workload_desc}, cost bound {cfg['bound']}, seeds {args.seeds}",
                    "jobs_per_step": len(dev), "lanes": lanes, "hash_slots_log2": slots,
-                   "u_operator": "carry" if args.ucarry else "doubling",
+                   "u_operator": ("carry adder" if u_carry else "doubling (App. B)")
+                   + ("" if args.ucarry or args.udoubling else " (chosen by row layout)"),
                    "dedup": "relaxed (fingerprint only)" if args.ruc else "exact (fingerprint + full compare)"},
         "trace_bits_per_s": round(value * tb_mean, 1),
         "jobs_per_s": round(len(results) / wall, 3),
@@ -359,8 +374,10 @@ def bench_batched(args):
     lanes = args.lanes or 8
     slice_bytes = (ws_bytes // lanes) & ~255
     slots = 22
-    # plain path: one job per call, one at a time, in a workspace of one lane's size
-    ctx = ltl.Context(workspace=ws[:slice_bytes], hash_slots_log2=slots)
+    # plain path: one job per call, one at a time, in a workspace of one lane's size (slices)
+    # or the whole workspace (shared budget: a job's region grows up to it)
+    ctx = ltl.Context(workspace=ws[:slice_bytes], hash_slots_log2=slots) if args.slices else \
+        ltl.Context(workspace=ws)
     for d, b in zip(dev[:lanes], bounds[:lanes]):           # warm-up
         ctx.learn(d, b)
     torch.cuda.synchronize()
@@ -375,14 +392,22 @@ def bench_batched(args):
     ctx.close()
     print(f"plain path: {len(plain)} jobs in {t_plain:.2f} s", file=sys.stderr, flush=True)
     # batched: a batch executor (lanes created once, outside the timed region)
-    ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots,
-                   flags=ltl.BATCH_BIG_ALONE if args.big_alone else 0)
+    big = ltl.BATCH_BIG_ALONE if args.big_alone else 0
+    if args.slices:
+        ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots, flags=big)
+    else:      # one budget: regions sized by each job's estimated footprint
+        ex = ltl.Batch(lanes=lanes, workspace=ws, flags=big | ltl.BATCH_SHARED_BUDGET)
     ex.run(dev[:lanes], bounds[:lanes])                     # warm-up: one job per lane
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res, dur, done = ex.run(dev, bounds)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    mem = None
+    if not args.slices:
+        st = ex.stats()
+        mem = {"budget_gb": round(st.budget_bytes / 2 ** 30, 2), "peak_gb": round(st.peak_bytes / 2 ** 30, 2),
+               "admissions": int(st.admissions), "reruns": int(st.reruns), "max_in_flight": int(st.max_in_flight)}
     ex.close()
     same = sum(1 for g, p in zip(res, plain) if (g.status, g.cost, g.level_new, g.level_candidates,
                                                  g.solution_index, g.solution) ==
@@ -412,6 +437,8 @@ def bench_batched(args):
                   "job_duration_ms_p50": round(float(np.percentile(plain_ms, 50)), 3),
                   "job_duration_ms_p99": round(float(np.percentile(plain_ms, 99)), 3)},
         "speedup_vs_plain": round(t_plain / t_batch, 3),
+        "memory": mem,
+        "admission": "equal slices" if args.slices else "shared budget, regions by estimated footprint",
         "identical_to_plain": f"{same}/{len(res)}",
         "statuses": statuses,
     }
@@ -437,8 +464,11 @@ def bench_served(args):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     lanes = args.lanes or 4
     slice_bytes = (ws_bytes // lanes) & ~255
-    ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=22,
-                   flags=ltl.BATCH_BIG_ALONE if args.big_alone else 0)
+    big = ltl.BATCH_BIG_ALONE if args.big_alone else 0
+    if args.slices:
+        ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=22, flags=big)
+    else:      # one budget: regions sized by each job's estimated footprint
+        ex = ltl.Batch(lanes=lanes, workspace=ws, flags=big | ltl.BATCH_SHARED_BUDGET)
     ex.run(dev[:lanes], bounds[:lanes])                     # warm-up: one job per lane
     torch.cuda.synchronize()
     print(f"serving {n} jobs arriving at {args.rate} jobs/s over {arrival[-1] / 1e3:.1f} s", file=sys.stderr,
@@ -448,6 +478,11 @@ def bench_served(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ex.close()
+    mem = None
+    if not args.slices:
+        st = ex.stats()
+        mem = {"budget_gb": round(st.budget_bytes / 2 ** 30, 2), "peak_gb": round(st.peak_bytes / 2 ** 30, 2),
+               "admissions": int(st.admissions), "reruns": int(st.reruns), "max_in_flight": int(st.max_in_flight)}
     lat = [d - a for d, a in zip(done, arrival)]
     statuses = {}
     for r in res:
@@ -461,7 +496,10 @@ def bench_served(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"served: {n} jobs of the batched mix, Poisson arrivals at {args.rate} jobs/s "
                                f"(seed 1), lanes {lanes}", "lanes": lanes,
-                   "slice_gb": round(slice_bytes / 2 ** 30, 2), "arrival_span_s": round(arrival[-1] / 1e3, 3)},
+                   "admission": "equal slices" if args.slices else "shared budget, regions by estimated footprint",
+                   "slice_gb": round(slice_bytes / 2 ** 30, 2) if args.slices else None,
+                   "arrival_span_s": round(arrival[-1] / 1e3, 3)},
+        "memory": mem,
         "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
         "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
         "job_duration_ms_p50": round(float(np.percentile(dur, 50)), 3),

@@ -66,9 +66,16 @@ enum {
 typedef struct ltl_ctx ltl_ctx;
 typedef struct ltl_job ltl_job;
 
-#define LTL_CTX_U_CARRY   0x1u   /* compute U by a carry-propagating add (one add per word)
-                                    instead of the log2(n) shift-doubling of App. B; both give
-                                    identical matrices                                         */
+#define LTL_CTX_U_CARRY   0x1u   /* compute U by a carry-propagating add (one add per word and
+                                    a prefix over the words of a trace) instead of the log2(n)
+                                    shift-doubling of App. B, at every level; both give
+                                    identical matrices.  Without this flag or LTL_CTX_U_DOUBLING
+                                    the library picks by row layout: doubling when every trace
+                                    fits one machine word (the paper's regime), the carry adder
+                                    when traces span several words                             */
+#define LTL_CTX_U_DOUBLING 0x10u /* compute U by the shift-doubling of App. B at every level
+                                    (overrides the choice by row layout; LTL_CTX_U_CARRY wins
+                                    if both are set)                                           */
 #define LTL_CTX_TIMING    0x2u   /* record GPU time per kernel kind and per level (HIP events
                                     around each kernel group)                                  */
 #define LTL_CTX_TIMING_LEVEL 0x4u /* record only the GPU time of each level: one event pair from
@@ -221,6 +228,17 @@ int ltl_learn_noalloc(int32_t device, void *stream, const ltl_spec *spec, const 
  * one at a time; smaller levels still overlap.  For mixes dominated by large jobs,
  * whose big levels slow each other down when they share the device. */
 #define LTL_BATCH_BIG_ALONE 0x100u
+/* Batch flag: one shared device-memory budget (the whole workspace) instead of equal
+ * slices.  Each job is admitted with a region of the workspace sized by its estimated
+ * language-cache footprint (fixed tables plus the modelled matrices of its first
+ * levels); free lanes take arrived jobs in arrival order, the first one whose region
+ * fits the free memory (a job passed over 4 * lanes times is admitted next).  A job that
+ * runs out of memory in a region smaller than the workspace is run again, at the head
+ * of the queue, in a region four times larger, so its result equals that of ltl_learn
+ * on a context with enough memory (or with the whole workspace).  Hash tables are
+ * sized from each region (hash_slots_log2 and max_entries must be 0).  The regions in
+ * use never exceed the workspace (ltl_batch_get_stats reports the peak). */
+#define LTL_BATCH_SHARED_BUDGET 0x200u
 
 typedef struct {
     int32_t  device;
@@ -272,6 +290,21 @@ int ltl_batch_run(ltl_batch *batch, const ltl_batch_job *jobs, uint32_t njobs, l
 int ltl_batch_serve(ltl_batch *batch, const ltl_batch_job *jobs, uint32_t njobs, const double *arrival_ms,
                     ltl_result *results, double *job_ms);
 void ltl_batch_destroy(ltl_batch *batch);
+
+/* Memory accounting of the last run of a shared-budget batch (LTL_BATCH_SHARED_BUDGET):
+ * the budget, the peak bytes of regions in use at once, admissions (runs started,
+ * re-runs included), re-runs after out-of-memory, the most jobs in flight at once and
+ * the summed region bytes of the finished jobs.  Zero for a batch with slices. */
+typedef struct {
+    uint64_t budget_bytes;
+    uint64_t peak_bytes;
+    uint32_t admissions;
+    uint32_t reruns;
+    uint32_t max_in_flight;
+    uint32_t pad;
+    uint64_t region_bytes_total;
+} ltl_batch_stats;
+int ltl_batch_get_stats(ltl_batch *batch, ltl_batch_stats *out);
 
 /* ---------------------------------------------------------------- level-by-level interface */
 

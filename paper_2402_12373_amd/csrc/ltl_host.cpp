@@ -18,6 +18,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -780,7 +782,11 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     Block *pin_grouped = pin_blocks + lv.blocks.size();
     memcpy(pin_blocks, lv.blocks.data(), sizeof(Block) * lv.blocks.size());
     // the same blocks grouped by connective class, each class with its own tile numbering
-    const bool ucarry = (j->ctx->o.flags & LTL_CTX_U_CARRY) != 0;
+    // U by doubling (App. B) on one-word rows, where its log2(n) steps are few shifts of
+    // one register; by the carry adder on multi-word rows, where each doubling step moves
+    // words across lanes (measured 2x on the long workload); either can be forced
+    const uint32_t fl = j->ctx->o.flags;
+    const bool ucarry = (fl & LTL_CTX_U_CARRY) != 0 || (!(fl & LTL_CTX_U_DOUBLING) && j->mw);
     auto cls_of = [&](uint32_t op) {
         if (op == LTL_AND || op == LTL_OR) return 1;
         if (op == LTL_U) return ucarry ? 3 : 2;
@@ -1447,7 +1453,86 @@ struct ltl_batch {
     const double *arrival_ms = nullptr;    // serving: job i may start arrival_ms[i] after t0
     std::atomic<uint32_t> next{0};
     std::chrono::steady_clock::time_point t0;
+    // LTL_BATCH_SHARED_BUDGET: regions of the whole workspace, sized per job
+    bool shared = false;
+    std::mutex pool_mu;
+    std::condition_variable pool_cv;
+    std::map<uint64_t, uint64_t> free_regions;    // offset -> size, coalesced
+    uint64_t in_use = 0;
+    std::deque<std::pair<uint32_t, uint64_t>> queue;   // (job, region bytes requested), arrival order
+    uint32_t jobs_left = 0;
+    uint32_t in_flight = 0;
+    uint32_t head_bypassed = 0;            // admissions that passed over the job at the queue's head
+    ltl_batch_stats stats{};
 };
+
+// ---------------------------------------------------------------------------
+// Shared budget: first-fit regions of the batch workspace
+// ---------------------------------------------------------------------------
+static bool pool_alloc(ltl_batch *b, uint64_t size, uint64_t &off) {
+    for (auto it = b->free_regions.begin(); it != b->free_regions.end(); ++it) {
+        if (it->second < size) continue;
+        off = it->first;
+        const uint64_t rest = it->second - size;
+        b->free_regions.erase(it);
+        if (rest) b->free_regions[off + size] = rest;
+        b->in_use += size;
+        b->stats.peak_bytes = std::max(b->stats.peak_bytes, b->in_use);
+        return true;
+    }
+    return false;
+}
+
+static void pool_release(ltl_batch *b, uint64_t off, uint64_t size) {
+    b->in_use -= size;
+    auto it = b->free_regions.emplace(off, size).first;
+    auto nx = std::next(it);
+    if (nx != b->free_regions.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        b->free_regions.erase(nx);
+    }
+    if (it != b->free_regions.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            b->free_regions.erase(it);
+        }
+    }
+}
+
+// Estimated workspace bytes of a job (its language-cache footprint): the fixed tables
+// of a region of that size plus the matrices of the stored levels up to cost 5 (or
+// the bound), with level sizes modelled as A * 5^(c-1) (about the growth of the
+// workloads' first levels), at least LTL_MIN_WORKSPACE.  Too small an estimate costs
+// a re-run in a larger region, never a different result.
+static uint64_t footprint_estimate(const ltl_batch_job &jb) {
+    const ltl_spec &sp = jb.spec;
+    const uint32_t T = sp.num_pos + sp.num_neg;
+    std::vector<uint64_t> off((size_t)T + 1, 0);
+    if (sp.flags & LTL_SPEC_DEVICE) {
+        if (hipMemcpy(off.data(), sp.offsets, off.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return LTL_MIN_WORKSPACE;
+    } else {
+        memcpy(off.data(), sp.offsets, off.size() * 8);
+    }
+    uint64_t maxlen = 1;
+    for (uint32_t t = 0; t < T; ++t) maxlen = std::max<uint64_t>(maxlen, off[t + 1] - off[t]);
+    const uint64_t W = maxlen <= 32 ? 32 : 64;
+    uint64_t r = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint64_t w = (off[t + 1] - off[t] + W - 1) / W;
+        if ((r & 63u) + w > 64u) r = align_up(r, 64);
+        r += w;
+    }
+    const uint64_t R = align_up(std::max<uint64_t>(r, 1), 64);
+    const uint64_t cmb = R * (W / 8);
+    uint64_t entries = 0, e = sp.num_props;
+    for (uint32_t c = 1; c < std::min<uint32_t>(jb.cost_bound, 6); ++c, e *= 5) entries += e;
+    const uint64_t tables = R * 64 + (uint64_t)sp.num_props * cmb + off[T] * 4 + (uint64_t)T * 16 + (4u << 20);
+    const uint64_t levels = entries * cmb + entries * 5 * 32;    // matrices + per-candidate scratch
+    // the hash table takes a quarter of the region
+    return std::max<uint64_t>(LTL_MIN_WORKSPACE, align_up((tables + levels) * 4 / 3 + (8u << 20), 1u << 20));
+}
 
 static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
     for (;;) {
@@ -1463,6 +1548,79 @@ static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
             b->job_ms[2 * (size_t)i] = std::chrono::duration<double, std::milli>(e - a).count();
             b->job_ms[2 * (size_t)i + 1] = std::chrono::duration<double, std::milli>(e - b->t0).count();
         }
+    }
+}
+
+// Shared-budget lanes: each lane takes the first arrived job (in arrival order) whose
+// requested region fits the free workspace, binds its context to that region and runs
+// it; a job that runs out of memory in a region smaller than the whole workspace goes
+// back to the head of the queue with a region four times larger.  To keep a large job
+// at the head from waiting forever, at most 4 * lanes admissions may pass over it.
+static void batch_lane_shared(ltl_batch *b, uint32_t lane) {
+    ltl_ctx *c = b->ctxs[lane];
+    const uint64_t total = b->o.workspace_bytes & ~255ull;
+    for (;;) {
+        uint32_t i = 0;
+        uint64_t req = 0, off = 0;
+        {
+            std::unique_lock<std::mutex> lk(b->pool_mu);
+            for (;;) {
+                if (b->jobs_left == 0) return;
+                const double now_ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - b->t0).count();
+                bool found = false;
+                double next_arrival = -1.0;
+                size_t k = 0;
+                for (auto it = b->queue.begin(); it != b->queue.end(); ++it, ++k) {
+                    const double arr = b->arrival_ms ? b->arrival_ms[it->first] : 0.0;
+                    if (arr > now_ms) {
+                        next_arrival = arr;
+                        break;
+                    }
+                    if (k > 0 && b->head_bypassed >= 4 * b->o.lanes) break;   // the head job's turn
+                    if (pool_alloc(b, it->second, off)) {
+                        i = it->first;
+                        req = it->second;
+                        b->head_bypassed = (k > 0) ? b->head_bypassed + 1 : 0;
+                        b->queue.erase(it);
+                        found = true;
+                        break;
+                    }
+                }
+                if (found) break;
+                // a finished job notifies; otherwise the next arrival is the next event
+                if (next_arrival >= 0.0)
+                    b->pool_cv.wait_until(lk, b->t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                                          std::chrono::duration<double, std::milli>(next_arrival)));
+                else
+                    b->pool_cv.wait(lk);
+            }
+            ++b->in_flight;
+            b->stats.max_in_flight = std::max(b->stats.max_in_flight, b->in_flight);
+            ++b->stats.admissions;
+        }
+        // the lane's context on the job's region: its hash table is sized from the region
+        // and initialised by the job (the region held other jobs' data before)
+        c->o.workspace = (char *)b->o.workspace + off;
+        c->o.workspace_bytes = req;
+        c->table_clean_log2 = 0;
+        const auto a = std::chrono::steady_clock::now();
+        ltl_result &res = b->results[i];
+        const int st = ltl_learn(c, &b->jobs[i].spec, &b->jobs[i].ops, b->jobs[i].cost_bound, &res);
+        const auto e = std::chrono::steady_clock::now();
+        std::lock_guard<std::mutex> lk(b->pool_mu);
+        pool_release(b, off, req);
+        --b->in_flight;
+        if (b->job_ms) b->job_ms[2 * (size_t)i] += std::chrono::duration<double, std::milli>(e - a).count();
+        if (st == LTL_E_OOM && req < total) {
+            b->queue.emplace_front(i, std::min<uint64_t>(total, req * 4));
+            ++b->stats.reruns;
+        } else {
+            if (b->job_ms) b->job_ms[2 * (size_t)i + 1] = std::chrono::duration<double, std::milli>(e - b->t0).count();
+            b->stats.region_bytes_total += req;
+            --b->jobs_left;
+        }
+        b->pool_cv.notify_all();
     }
 }
 
@@ -1490,7 +1648,8 @@ static void batch_worker(ltl_batch *b, uint32_t lane) {
         }
         if (b->quit.load()) return;
         seen = b->generation.load();
-        batch_lane_jobs(b, lane);
+        if (b->shared) batch_lane_shared(b, lane);
+        else batch_lane_jobs(b, lane);
         {
             std::lock_guard<std::mutex> lk(b->mu);
             if (b->lanes_busy.fetch_sub(1) == 1) b->cv_done.notify_all();
@@ -1521,12 +1680,16 @@ extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
     *out = nullptr;
     if (!o || !o->workspace) return LTL_E_INVAL;
     if (o->lanes < 1 || o->lanes > 64) return LTL_E_INVAL;
+    const bool shared = (o->flags & LTL_BATCH_SHARED_BUDGET) != 0;
     const uint64_t slice = (o->workspace_bytes / o->lanes) & ~255ull;
-    if (slice < LTL_MIN_WORKSPACE) return LTL_E_INVAL;
+    if (shared ? o->workspace_bytes < LTL_MIN_WORKSPACE : slice < LTL_MIN_WORKSPACE) return LTL_E_INVAL;
+    if (((uintptr_t)o->workspace) & 255u) return LTL_E_INVAL;
+    if (shared && (o->hash_slots_log2 || o->max_entries)) return LTL_E_INVAL;   // sized per region
     if (hipSetDevice(o->device) != hipSuccess) return LTL_E_DEVICE;
     ltl_batch *b = new (std::nothrow) ltl_batch();
     if (!b) return LTL_E_INVAL;
     b->o = *o;
+    b->shared = shared;
     const uint32_t lanes = o->lanes;
     b->streams.assign(lanes, nullptr);
     b->ctxs.assign(lanes, nullptr);
@@ -1538,9 +1701,11 @@ extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
         }
         ltl_ctx_opts co{};
         co.device = o->device;
-        co.flags = o->flags & ~LTL_BATCH_BIG_ALONE;
-        co.workspace = (char *)o->workspace + (uint64_t)l * slice;
-        co.workspace_bytes = slice;
+        co.flags = o->flags & ~(LTL_BATCH_BIG_ALONE | LTL_BATCH_SHARED_BUDGET);
+        // shared budget: a lane's context is bound to a region per job (set when the job
+        // is admitted); until then it names the start of the workspace
+        co.workspace = (char *)o->workspace + (shared ? 0 : (uint64_t)l * slice);
+        co.workspace_bytes = shared ? LTL_MIN_WORKSPACE : slice;
         co.stream = b->streams[l];
         co.hash_slots_log2 = o->hash_slots_log2;
         co.word_bits = o->word_bits;
@@ -1588,6 +1753,21 @@ static int batch_go(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, con
     b->job_ms = job_ms;
     b->arrival_ms = arrival_ms;
     b->next = 0;
+    if (b->shared) {      // every job starts with its footprint estimate
+        b->stats = ltl_batch_stats{};
+        b->stats.budget_bytes = b->o.workspace_bytes & ~255ull;
+        b->free_regions.clear();
+        b->free_regions[0] = b->stats.budget_bytes;
+        b->in_use = 0;
+        b->queue.clear();
+        for (uint32_t i = 0; i < njobs; ++i)
+            b->queue.emplace_back(i, std::min<uint64_t>(b->stats.budget_bytes, footprint_estimate(jobs[i])));
+        b->jobs_left = njobs;
+        b->in_flight = 0;
+        b->head_bypassed = 0;
+        if (job_ms)
+            for (uint32_t i = 0; i < 2 * njobs; ++i) job_ms[i] = 0.0;
+    }
     b->t0 = std::chrono::steady_clock::now();
     {
         std::lock_guard<std::mutex> lk(b->mu);
@@ -1595,12 +1775,20 @@ static int batch_go(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, con
         b->generation.fetch_add(1);
     }
     b->cv_start.notify_all();
-    batch_lane_jobs(b, 0);
+    if (b->shared) batch_lane_shared(b, 0);
+    else batch_lane_jobs(b, 0);
     if (!spin_for([&] { return b->lanes_busy.load() == 0; }, BATCH_SPIN_US)) {
         std::unique_lock<std::mutex> lk(b->mu);
         b->cv_done.wait(lk, [&] { return b->lanes_busy.load() == 0; });
     }
     b->running = false;
+    return LTL_OK;
+}
+
+extern "C" int ltl_batch_get_stats(ltl_batch *b, ltl_batch_stats *out) {
+    if (!b || !out) return LTL_E_INVAL;
+    std::lock_guard<std::mutex> lk(b->pool_mu);
+    *out = b->stats;
     return LTL_OK;
 }
 
@@ -1610,7 +1798,8 @@ extern "C" int ltl_learn_batch(const ltl_batch_opts *o, const ltl_batch_job *job
     ltl_batch_opts oo = *o;
     if (oo.lanes >= 1 && oo.lanes <= 64) oo.lanes = std::min<uint32_t>(oo.lanes, std::max<uint32_t>(njobs, 1u));
     // the slice size is that of the requested lane count, so results do not depend on njobs
-    if (o->lanes >= 1 && o->lanes <= 64) oo.workspace_bytes = ((o->workspace_bytes / o->lanes) & ~255ull) * oo.lanes;
+    if (o->lanes >= 1 && o->lanes <= 64 && !(o->flags & LTL_BATCH_SHARED_BUDGET))
+        oo.workspace_bytes = ((o->workspace_bytes / o->lanes) & ~255ull) * oo.lanes;
     ltl_batch *b = nullptr;
     int st = ltl_batch_create(&oo, &b);
     if (st != LTL_OK) return st;

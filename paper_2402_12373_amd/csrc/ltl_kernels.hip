@@ -43,6 +43,13 @@ constexpr int OP_UC = 8;   // U computed by the carry-chain adder
 #ifndef LTL_EVAL_PIPE
 #define LTL_EVAL_PIPE 2
 #endif
+// Waves per SIMD the 64-bit level kernels are register-allocated for (tuning constants)
+#ifndef LTL_WAVES_U64
+#define LTL_WAVES_U64 2
+#endif
+#ifndef LTL_WAVES_U64_WG
+#define LTL_WAVES_U64_WG 1
+#endif
 
 template <typename T> struct Word;
 template <> struct Word<uint32_t> { static constexpr int BITS = 32; };
@@ -228,9 +235,15 @@ __device__ __forceinline__ T op_UC(T phi, T psi, const RowMeta<T> &m, uint32_t m
         uint64_t S = A + B;
         bool g = S < A;                    // carry out without carry in
         bool p = (S == ~0ull);             // carry out iff carry in
-        uint64_t Gm = __ballot(g), Pm = __ballot(p);
-        uint64_t Cm = 0;                   // carry into each lane from the next word of its trace
-        for (uint32_t it = 1; it < maxw; ++it) Cm = ((Gm | (Pm & Cm)) >> 1) & m.hn;
+        // carry out of each lane with the carries of the later words of its trace: a
+        // prefix over the lanes (Kogge-Stone doubling on the wave masks), from the last
+        // word of a trace toward its first; Pm is cut where a trace ends (m.hn clear)
+        uint64_t Gm = __ballot(g), Pm = __ballot(p) & m.hn;
+        for (uint32_t d = 1; d < maxw; d <<= 1) {
+            Gm |= Pm & (Gm >> d);
+            Pm &= Pm >> d;
+        }
+        const uint64_t Cm = (Gm >> 1) & m.hn;   // carry into each lane from the next word of its trace
         uint64_t cin = (Cm >> lane) & 1ull;
         uint64_t S2 = S + cin;
         uint64_t cout = (uint64_t)g | ((uint64_t)p & cin);
@@ -677,7 +690,9 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
         }
       } else {
         uint64_t acc[NP];
-        T viol[NP];
+        // separation violations: only the position-0 bit (the top bit of a trace's first
+        // word) counts, so 64-bit rows keep the top halves alone
+        uint32_t viol[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) { acc[p] = 0; viol[p] = 0; }
         Rowset cur[PIPE], nxt[PIPE];
@@ -694,8 +709,9 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                     for (int p = 0; p < NP; ++p) {
                         // one word per trace (32-bit layout): every live row is a first word and
                         // dead rows are zero, so the position-0 bit is masked once, after the loop
-                        if constexpr (!MW && sizeof(T) == 4) viol[p] |= w[p] ^ cur[u].m.sw;
-                        else viol[p] |= (w[p] ^ cur[u].m.sw) & cur[u].m.sm;
+                        if constexpr (!MW && sizeof(T) == 4) viol[p] |= (uint32_t)(w[p] ^ cur[u].m.sw);
+                        else viol[p] |= (uint32_t)((w[p] ^ cur[u].m.sw) >> (8 * sizeof(T) - 32)) &
+                                        (uint32_t)(cur[u].m.sm >> (8 * sizeof(T) - 32));
                         fp_add<T>(acc[p], w[p], cur[u].m);
                     }
                 }
@@ -708,7 +724,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
         bool my_bad = false;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            if constexpr (!MW && sizeof(T) == 4) viol[p] &= (T)0x80000000u;
+            if constexpr (!MW && sizeof(T) == 4) viol[p] &= 0x80000000u;
             const bool bad = __ballot(viol[p] != 0) != 0ull;
             if (lane == p) { my_idx = idx[p]; my_bad = bad; }
         }
@@ -850,7 +866,7 @@ __device__ __forceinline__ Block uniform_block(const Block &in) {
 enum { CLS_UNARY = 0, CLS_ANDOR = 1, CLS_U = 2, CLS_UC = 3 };
 
 template <typename T, bool MW, bool VERIFY, int CLS, bool WONLY = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : LTL_WAVES_U64))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
                                                uint32_t ntiles, uint32_t chunk) {
     const int lane = (int)__lane_id();
     if constexpr (VERIFY || WONLY) {
@@ -940,7 +956,7 @@ __global__ __launch_bounds__(256) void k_level_all(LevelArgs<T> A, const Block *
 template <bool MW> constexpr int wg_waves() { return MW ? WG_WAVES / 2 : WG_WAVES; }
 
 template <typename T, bool MW>
-__global__ __launch_bounds__(64 * wg_waves<MW>()) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+__global__ __launch_bounds__(64 * wg_waves<MW>()) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : LTL_WAVES_U64_WG)))
 void k_level_wg(LevelArgs<T> A, const Block *blocks,
                                                                   uint32_t nblocks, uint32_t ntiles) {
     __shared__ WgShare sh;

@@ -15,14 +15,16 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libltl.so")
+# the in-tree build; LTL_LIBRARY names another build of the same sources
+LIB_PATH = os.environ.get("LTL_LIBRARY") or os.path.join(PKG, "libltl.so")
 
 LTL_OK, LTL_NOT_FOUND = 0, 1
 LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG, LTL_E_OOM, LTL_E_DEVICE, LTL_E_STATE = -1, -2, -3, -4, -5, -6
 LTL_E_BUFFER = -7
 ATOM, NOT, AND, OR, X, F, G, U = range(8)
-CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL, CTX_RUC = 0x1, 0x2, 0x4, 0x8
+CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL, CTX_RUC, CTX_U_DOUBLING = 0x1, 0x2, 0x4, 0x8, 0x10
 BATCH_BIG_ALONE = 0x100    # batch flag: whole-row levels of different lanes take turns
+BATCH_SHARED_BUDGET = 0x200   # batch flag: one memory budget, regions sized per job
 SPEC_DEVICE = 0x1
 MAX_LEVELS, MAX_NODES, K_KINDS = 64, 64, 6
 NO_SOLUTION = (1 << 64) - 1
@@ -33,7 +35,7 @@ EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", 
            "ltl_batch_destroy", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
            "ltl_status_str", "ltl_overfit", "ltl_batch_serve", "ltl_holds", "ltl_det_split", "ltl_rand_split",
-           "ltl_learn_noalloc")
+           "ltl_learn_noalloc", "ltl_batch_get_stats")
 
 
 class LTLError(RuntimeError):
@@ -82,6 +84,12 @@ class Result(C.Structure):
                 ("pad", C.c_uint32), ("level_bytes", C.c_uint64 * MAX_LEVELS)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("peak_bytes", C.c_uint64), ("admissions", C.c_uint32),
+                ("reruns", C.c_uint32), ("max_in_flight", C.c_uint32), ("pad", C.c_uint32),
+                ("region_bytes_total", C.c_uint64)]
+
+
 class LevelStats(C.Structure):
     _fields_ = [("cost", C.c_uint32), ("stored", C.c_uint32), ("candidates", C.c_uint64),
                 ("new_entries", C.c_uint64), ("first_solution", C.c_uint64), ("colliders", C.c_uint64),
@@ -120,6 +128,8 @@ def load_library(path: str = LIB_PATH):
     L.ltl_batch_run.restype = C.c_int
     L.ltl_batch_serve.argtypes = [C.c_void_p, P(BatchJob), C.c_uint32, P(C.c_double), P(Result), P(C.c_double)]
     L.ltl_batch_serve.restype = C.c_int
+    L.ltl_batch_get_stats.argtypes = [C.c_void_p, P(BatchStats)]
+    L.ltl_batch_get_stats.restype = C.c_int
     L.ltl_batch_destroy.argtypes = [C.c_void_p]
     L.ltl_batch_destroy.restype = None
     L.ltl_job_create.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(C.c_void_p)]
@@ -478,6 +488,14 @@ class Batch:
         if st != LTL_OK:
             raise LTLError(st, "ltl_batch_serve")
         return [_convert(res[i]) for i in range(n)], [ms[2 * i] for i in range(n)], [ms[2 * i + 1] for i in range(n)]
+
+    def stats(self) -> BatchStats:
+        """Memory accounting of the last run (shared-budget batches)."""
+        st = BatchStats()
+        rc = self._L.ltl_batch_get_stats(self._h, C.byref(st))
+        if rc != LTL_OK:
+            raise LTLError(rc, "ltl_batch_get_stats")
+        return st
 
     def close(self):
         if getattr(self, "_h", None):

@@ -32,7 +32,8 @@ def ltl():
 
 @pytest.fixture(scope="module")
 def big_ctx(ltl):
-    c = ltl.Context(workspace_bytes=24 << 30, hash_slots_log2=26)
+    # a long job's solution level (110 710 new languages of 327 KB at level 7) needs 36 GB
+    c = ltl.Context(workspace_bytes=64 << 30, hash_slots_log2=26)
     yield c
     c.close()
 

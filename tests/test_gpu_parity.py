@@ -128,19 +128,36 @@ def ctx_whole(ltl):
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_dbl(ltl):
+    """U by the doubling of App. B at every level (multi-word rows default to the carry adder)."""
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, flags=ltl.CTX_U_DOUBLING)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_whole_dbl(ltl):
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, split_tiles=1, flags=ltl.CTX_U_DOUBLING)
+    yield c
+    c.close()
+
+
 PATHS = ["row-split", "whole-row"]
+PATHS_U = ["row-split", "whole-row", "row-split-doubling", "whole-row-doubling"]
 
 
-def _pick(ctx, ctx_whole, path):
-    return ctx_whole if path == "whole-row" else ctx
+def _pick(ctx, ctx_whole, path, ctx_dbl=None, ctx_whole_dbl=None):
+    return {"row-split": ctx, "whole-row": ctx_whole, "row-split-doubling": ctx_dbl,
+            "whole-row-doubling": ctx_whole_dbl}[path]
 
 
-@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("path", PATHS_U)
 @pytest.mark.parametrize("lengths", LENGTH_SETS, ids=lambda l: "len" + "-".join(map(str, l)))
-def test_word_boundaries(ltl, ctx, ctx_whole, lengths, path):
+def test_word_boundaries(ltl, ctx, ctx_whole, ctx_dbl, ctx_whole_dbl, lengths, path):
     """Traces straddling word boundaries (single and multi-word rows), all matrices to level 4,
     on the row-split kernels (what these small levels use by default) and forced onto the
-    whole-row kernels."""
+    whole-row kernels, each with the U method chosen by row layout and with doubling forced."""
     rng = np.random.default_rng(sum(lengths))
     pos, neg = [], []
     for k in range(8):
@@ -149,18 +166,21 @@ def test_word_boundaries(ltl, ctx, ctx_whole, lengths, path):
         (pos if k % 2 == 0 else neg).append(tr)
     inst = synth.from_traces(pos, neg, 2)
     _say("boundaries", lengths, path)
-    _level_by_level(ltl, _pick(ctx, ctx_whole, path), inst, 4, max_entries_per_level=200)
+    _level_by_level(ltl, _pick(ctx, ctx_whole, path, ctx_dbl, ctx_whole_dbl), inst, 4, max_entries_per_level=200)
 
 
-@pytest.mark.parametrize("path", PATHS)
-def test_until_chains_every_doubling_step(ltl, ctx, ctx_whole, path):
+@pytest.mark.parametrize("path", PATHS_U)
+def test_until_chains_every_doubling_step(ltl, ctx, ctx_whole, ctx_dbl, ctx_whole_dbl, path):
     """p0 U p1 over runs of 64, 127-129, 255-257 and 511 positions (App. B doubling across
     64-position words; each step s = 64, 128, 256 is the first to set some bit, checked on
-    the CPU in test_until_chains.py): every stored matrix of levels 1-4 and every entry
-    formula of level 5 equal the oracle's."""
+    the CPU in test_until_chains.py; the carry adder's prefix over up to 8 words of a
+    trace): every stored matrix of levels 1-4 and every entry formula of level 5 equal the
+    oracle's, with doubling forced and with the method chosen by row layout (the carry
+    adder here)."""
     inst = synth.until_chain_instance(0)
     _say("until chains", path)
-    g, _ = _level_by_level(ltl, _pick(ctx, ctx_whole, path), inst, 5, max_entries_per_level=400)
+    g, _ = _level_by_level(ltl, _pick(ctx, ctx_whole, path, ctx_dbl, ctx_whole_dbl), inst, 5,
+                           max_entries_per_level=400)
     assert g.level_new[1] == 2
 
 
@@ -184,9 +204,13 @@ def test_single_word_u64_rows(ltl):
         c64.close()
 
 
+@pytest.mark.parametrize("flags", ["carry", "doubling"])
 @pytest.mark.parametrize("word_bits", [32, 64])
-def test_u_carry_variant_matches(ltl, word_bits):
-    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, flags=ltl.CTX_U_CARRY, word_bits=word_bits)
+def test_u_carry_variant_matches(ltl, word_bits, flags):
+    """Both U methods forced at every level, on 32-bit and 64-bit rows (and multi-word 64-bit
+    rows of up to 200 positions): the oracle's results."""
+    fl = ltl.CTX_U_CARRY if flags == "carry" else ltl.CTX_U_DOUBLING
+    c = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, flags=fl, word_bits=word_bits)
     try:
         for seed in range(16):
             inst, cfg = synth.preset_instance("tiny", seed)
@@ -614,6 +638,39 @@ def test_batch_serve_arrivals(ltl):
             ex.serve(insts[:2], bounds[:2], [5.0, 1.0])                 # decreasing arrivals
     finally:
         ex.close()
+        plain.close()
+
+
+def test_batch_shared_budget_admission(ltl):
+    """LTL_BATCH_SHARED_BUDGET serving: jobs get regions of one 2 GiB budget sized by their
+    estimated footprint; the regions in use never exceed the budget; a job that outgrows its
+    region runs again in a larger one (the Hamming job of bound 12 needs about 1 GB, its
+    estimate is 16 MB); every result equals the job's plain run alone on a context with the
+    whole budget."""
+    budget = 2 << 30
+    specs = [synth.preset_instance("tiny", s) for s in range(12)]
+    insts = [i for i, _ in specs] + [synth.hamming_instance(0, 4, 2), synth.until_chain_instance(0),
+                                     synth.preset_instance("scale", 0)[0]]
+    bounds = [c["bound"] for _, c in specs] + [12, 5, 11]
+    arrival = synth.poisson_arrivals(3, len(insts), 200.0)
+    ex = ltl.Batch(lanes=3, workspace_bytes=budget, flags=ltl.BATCH_SHARED_BUDGET)
+    key = lambda r: (r.status, r.cost, r.levels_done, r.level_new, r.level_candidates, r.solution_index, r.solution)
+    try:
+        res, dur, done = ex.serve(insts, bounds, arrival)
+        st = ex.stats()
+        _say("shared budget: peak", st.peak_bytes, "reruns", st.reruns, "in flight", st.max_in_flight)
+        assert st.budget_bytes == budget and 0 < st.peak_bytes <= budget
+        assert st.reruns >= 1 and st.admissions == len(insts) + st.reruns
+        assert st.max_in_flight >= 2
+        for i in range(len(insts)):
+            assert done[i] >= arrival[i], i
+    finally:
+        ex.close()
+    plain = ltl.Context(workspace_bytes=budget)
+    try:
+        for i, (inst, b) in enumerate(zip(insts, bounds)):
+            assert key(res[i]) == key(plain.learn(inst, b)), i
+    finally:
         plain.close()
 
 
