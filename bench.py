@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--udoubling", action="store_true",
                     help="U by the doubling of App. B at every level (LTL_CTX_U_DOUBLING); default: doubling on "
                          "one-word rows, the carry adder on multi-word rows")
+    ap.add_argument("--lds-tiles", action="store_true",
+                    help="binary tiles of whole-row levels stage 8 x 8 groups of child words in LDS instead of "
+                         "reading 4 x 4 tiles into registers (LTL_CTX_LDS_TILES)")
     ap.add_argument("--split-tiles", type=int, default=0,
                     help="levels of fewer tiles run the row-split kernels (ltl_ctx_opts.split_tiles; "
                          "0 = the library default, 1 = whole-row kernels at every level)")
@@ -109,6 +112,9 @@ def main():
                     help="relaxed uniqueness check (LTL_CTX_RUC): fingerprint match taken as equality, no compare")
     ap.add_argument("--big-alone", action="store_true",
                     help="batch lanes take turns for whole-row levels (LTL_BATCH_BIG_ALONE)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: skip the autotuner (ltl_autotune on the largest of the first 16 jobs chooses "
+                         "the binary tile shape and the whole-row level size for the plain and batched runs)")
     ap.add_argument("--slices", action="store_true",
                     help="batched/served: equal workspace slices per lane instead of one shared budget "
                          "with regions sized per job (LTL_BATCH_SHARED_BUDGET)")
@@ -189,7 +195,7 @@ def bench_fixed(args):
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     slots = 26 if args.workload != "tiny" else 20
     ucarry = (ltl.CTX_U_CARRY if args.ucarry else 0) | (ltl.CTX_U_DOUBLING if args.udoubling else 0) | \
-        (ltl.CTX_RUC if args.ruc else 0)
+        (ltl.CTX_RUC if args.ruc else 0) | (ltl.CTX_LDS_TILES if args.lds_tiles else 0)
     # timed steps: one event pair per level (level GPU time, for the roofline); the one-stream
     # pass: events around every kernel group (time per kernel kind)
     timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
@@ -326,7 +332,8 @@ def bench_fixed(args):
                    "jobs_per_step": len(dev), "lanes": lanes, "hash_slots_log2": slots,
                    "u_operator": ("carry adder" if u_carry else "doubling (App. B)")
                    + ("" if args.ucarry or args.udoubling else " (chosen by row layout)"),
-                   "dedup": "relaxed (fingerprint only)" if args.ruc else "exact (fingerprint + full compare)"},
+                   "dedup": "relaxed (fingerprint only)" if args.ruc else "exact (fingerprint + full compare)",
+                   "binary_tiles": "LDS-staged 8 x 8 groups" if args.lds_tiles else "register 4 x 4"},
         "trace_bits_per_s": round(value * tb_mean, 1),
         "jobs_per_s": round(len(results) / wall, 3),
         "job_ms_p50": round(statistics.median(job_ms), 3),
@@ -374,10 +381,20 @@ def bench_batched(args):
     lanes = args.lanes or 8
     slice_bytes = (ws_bytes // lanes) & ~255
     slots = 22
+    # autotuner: tile shape and level schedule from the largest of the first 16 jobs
+    tune_flags, tune_split, tuning = 0, 0, None
+    if not args.no_autotune:
+        probe = max(range(min(16, len(insts))), key=lambda i: int(insts[i].total_positions))
+        tctx = ltl.Context(workspace=ws)
+        (tune_flags, tune_split), rows = tctx.autotune(dev[probe], bounds[probe])
+        tctx.close()
+        tuning = {"job": probe, "chosen": {"flags": tune_flags, "split_tiles": tune_split},
+                  "tried_ms": [{"flags": f, "split_tiles": t, "ms": round(ms, 3)} for f, t, ms in rows]}
     # plain path: one job per call, one at a time, in a workspace of one lane's size (slices)
     # or the whole workspace (shared budget: a job's region grows up to it)
-    ctx = ltl.Context(workspace=ws[:slice_bytes], hash_slots_log2=slots) if args.slices else \
-        ltl.Context(workspace=ws)
+    ctx = ltl.Context(workspace=ws[:slice_bytes], hash_slots_log2=slots, flags=tune_flags,
+                      split_tiles=tune_split) if args.slices else \
+        ltl.Context(workspace=ws, flags=tune_flags, split_tiles=tune_split)
     for d, b in zip(dev[:lanes], bounds[:lanes]):           # warm-up
         ctx.learn(d, b)
     torch.cuda.synchronize()
@@ -394,9 +411,11 @@ def bench_batched(args):
     # batched: a batch executor (lanes created once, outside the timed region)
     big = ltl.BATCH_BIG_ALONE if args.big_alone else 0
     if args.slices:
-        ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots, flags=big)
+        ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots,
+                       flags=big | tune_flags, split_tiles=tune_split)
     else:      # one budget: regions sized by each job's estimated footprint
-        ex = ltl.Batch(lanes=lanes, workspace=ws, flags=big | ltl.BATCH_SHARED_BUDGET)
+        ex = ltl.Batch(lanes=lanes, workspace=ws, flags=big | tune_flags | ltl.BATCH_SHARED_BUDGET,
+                       split_tiles=tune_split)
     ex.run(dev[:lanes], bounds[:lanes])                     # warm-up: one job per lane
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -438,6 +457,7 @@ def bench_batched(args):
                   "job_duration_ms_p99": round(float(np.percentile(plain_ms, 99)), 3)},
         "speedup_vs_plain": round(t_plain / t_batch, 3),
         "memory": mem,
+        "autotune": tuning,
         "admission": "equal slices" if args.slices else "shared budget, regions by estimated footprint",
         "identical_to_plain": f"{same}/{len(res)}",
         "statuses": statuses,
@@ -477,12 +497,12 @@ def bench_served(args):
     res, dur, done = ex.serve(dev, bounds, arrival)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ex.close()
     mem = None
     if not args.slices:
         st = ex.stats()
         mem = {"budget_gb": round(st.budget_bytes / 2 ** 30, 2), "peak_gb": round(st.peak_bytes / 2 ** 30, 2),
                "admissions": int(st.admissions), "reruns": int(st.reruns), "max_in_flight": int(st.max_in_flight)}
+    ex.close()
     lat = [d - a for d, a in zip(done, arrival)]
     statuses = {}
     for r in res:

@@ -73,6 +73,12 @@ typedef struct ltl_job ltl_job;
                                     the library picks by row layout: doubling when every trace
                                     fits one machine word (the paper's regime), the carry adder
                                     when traces span several words                             */
+#define LTL_CTX_LDS_TILES 0x20u  /* binary connectives of whole-row levels stage their child
+                                    operands in LDS: a workgroup of 4 waves loads the words of
+                                    8 + 8 children once per row block for an 8 x 8 group of
+                                    pairs, instead of each wave reading its 4 + 4 children
+                                    into registers for a 4 x 4 tile (the default); a tile
+                                    shape for ltl_autotune, results are identical               */
 #define LTL_CTX_U_DOUBLING 0x10u /* compute U by the shift-doubling of App. B at every level
                                     (overrides the choice by row layout; LTL_CTX_U_CARRY wins
                                     if both are set)                                           */
@@ -195,6 +201,28 @@ typedef struct {
 int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
               ltl_result *out);
 
+/* ---------------------------------------------------------------- autotuning */
+
+/* The project's autotuner for tile shapes and level schedules: runs the job (spec,
+ * ops, cost_bound) on ctx once untimed, then once per configuration, timing each whole
+ * job on the host clock, and reports the configurations, their times and the fastest
+ * (index `best`).  A configuration is a binary tile shape (child operands read into
+ * registers for 4 x 4 pairs, flags 0, or staged in LDS for 8 x 8 pairs,
+ * LTL_CTX_LDS_TILES) and the level size in tiles from which levels run the
+ * whole-row kernels (ltl_ctx_opts.split_tiles).  The caller applies the choice to its
+ * contexts or batches; ctx's options are restored.  Every configuration must give the
+ * same result (status, counts, solution): LTL_E_STATE if one does not.  Errors as
+ * ltl_learn (a job that runs out of memory is timed like any other). */
+#define LTL_TUNE_CONFIGS 5
+typedef struct {
+    uint32_t tried;                          /* configurations timed                     */
+    uint32_t best;                           /* index of the fastest                      */
+    uint32_t flags[LTL_TUNE_CONFIGS];        /* LTL_CTX_LDS_TILES or 0                    */
+    uint32_t split_tiles[LTL_TUNE_CONFIGS];  /* ltl_ctx_opts.split_tiles                  */
+    double   ms[LTL_TUNE_CONFIGS];           /* wall time of the job (milliseconds)       */
+} ltl_tuning;
+int ltl_autotune(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound, ltl_tuning *out);
+
 /* ---------------------------------------------------------------- learning without allocation */
 
 /* For callers that cannot allocate device memory or call allocating HIP routines
@@ -231,13 +259,17 @@ int ltl_learn_noalloc(int32_t device, void *stream, const ltl_spec *spec, const 
 /* Batch flag: one shared device-memory budget (the whole workspace) instead of equal
  * slices.  Each job is admitted with a region of the workspace sized by its estimated
  * language-cache footprint (fixed tables plus the modelled matrices of its first
- * levels); free lanes take arrived jobs in arrival order, the first one whose region
- * fits the free memory (a job passed over 4 * lanes times is admitted next).  A job that
- * runs out of memory in a region smaller than the workspace is run again, at the head
- * of the queue, in a region four times larger, so its result equals that of ltl_learn
- * on a context with enough memory (or with the whole workspace).  Hash tables are
- * sized from each region (hash_slots_log2 and max_entries must be 0).  The regions in
- * use never exceed the workspace (ltl_batch_get_stats reports the peak). */
+ * levels, at least a quarter of workspace / lanes); free lanes take arrived jobs in
+ * arrival order, the first one whose region fits the free memory (a job passed over
+ * 4 * lanes times is admitted next).  A job that runs out of memory in a region smaller
+ * than the workspace is run again, at the head of the queue, in a region sized from its
+ * completed levels (at least four times larger), so its result equals that of ltl_learn
+ * on a context with enough memory (or with the whole workspace).  Each lane keeps its
+ * own language-cache tables (hash table and entry tables, 24 bytes a slot) at the start
+ * of the workspace, emptied by every job, with the slots a context of the whole
+ * workspace would have (fewer if the lanes' tables would take more than half of it;
+ * hash_slots_log2 and max_entries must be 0); the rest is the pool of regions, whose use
+ * never exceeds it (ltl_batch_get_stats reports the pool and the peak). */
 #define LTL_BATCH_SHARED_BUDGET 0x200u
 
 typedef struct {
@@ -250,6 +282,8 @@ typedef struct {
     uint32_t word_bits;          /* as in ltl_ctx_opts                                       */
     uint32_t fp_bits;
     uint64_t max_entries;        /* per job; 0 = derived from the lane's hash table          */
+    uint32_t split_tiles;        /* as in ltl_ctx_opts (e.g. from ltl_autotune)              */
+    uint32_t reserved;
 } ltl_batch_opts;
 
 typedef struct {
@@ -292,7 +326,7 @@ int ltl_batch_serve(ltl_batch *batch, const ltl_batch_job *jobs, uint32_t njobs,
 void ltl_batch_destroy(ltl_batch *batch);
 
 /* Memory accounting of the last run of a shared-budget batch (LTL_BATCH_SHARED_BUDGET):
- * the budget, the peak bytes of regions in use at once, admissions (runs started,
+ * the pool of job regions, the peak bytes of regions in use at once, admissions (runs started,
  * re-runs included), re-runs after out-of-memory, the most jobs in flight at once and
  * the summed region bytes of the finished jobs.  Zero for a batch with slices. */
 typedef struct {

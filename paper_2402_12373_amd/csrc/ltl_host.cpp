@@ -42,6 +42,12 @@ constexpr uint64_t TARGET_WAVES = 8192;
 // loads per wave (a tuning constant; ltl_ctx_opts.split_tiles overrides it).
 constexpr uint64_t SPLIT_TILES = 8192;
 constexpr uint64_t MIN_CHUNK = 4;        // row blocks per work item at least (per-item fixed cost)
+// Whole-row levels: the waves the verification and the write pass aim for (a tuning constant)
+#ifndef LTL_PASS_WAVES
+#define LTL_PASS_WAVES 65536
+#endif
+constexpr uint64_t PASS_WAVES = LTL_PASS_WAVES;
+constexpr uint64_t PASS_MIN_CHUNK = 16;  // row blocks per chunk at least (per-item owner and claim lookups)
 // per-level upload, one copy: [counters init (256 B) | canonical blocks | blocks by
 // class | all blocks, one tile numbering]
 constexpr uint64_t UPLOAD_BYTES = 256 + 3 * sizeof(Block) * MAX_BLOCKS;
@@ -79,6 +85,10 @@ struct ltl_ctx {
     char *jpin = nullptr;            // page-locked staging of a job's row tables (grown on demand)
     uint64_t jpin_bytes = 0;
     uint32_t table_clean_log2 = 0;   // the hash table at the start of the workspace is empty (this size)
+    // batch lanes with a shared budget: the lane's own hash table and entry tables (24
+    // bytes a slot), kept clean across jobs, outside the job regions
+    char *cache = nullptr;
+    uint32_t cache_slots_log2 = 0;
     // allocation-free contexts (ltl_learn_noalloc): host staging in ordinary memory instead
     // of page-locked buffers
     bool noalloc = false;
@@ -156,6 +166,11 @@ struct ltl_job {
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[LTL_K_KINDS] = {0};
     uint32_t kernel_launches[LTL_K_KINDS] = {0};
+    // why the job ran out of memory: 0 not, 1 tables or level scratch did not fit (or the
+    // hash table overflowed), 2 a level's new entries did not fit the arena (oom_new of
+    // them), 3 the stored entries exceeded the entry cap
+    int oom_kind = 0;
+    uint64_t oom_new = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -461,20 +476,28 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
 
     // workspace carve: the language-cache hash table first (12 bytes per slot), at
     // a fixed place so that a context can hand an emptied table to its next job
-    uint32_t sl = c->o.hash_slots_log2;
+    uint32_t sl = c->cache ? c->cache_slots_log2 : c->o.hash_slots_log2;
     if (!sl) {
         sl = 26;
         while (sl > 10 && (24ull << sl) > j->wsb / 4) --sl;
     }
     j->slots_log2 = sl;
     const uint64_t nslots = 1ull << sl;
-    j->tkey = (unsigned long long *)ws_take(j, nslots * 8);
-    j->tval = (uint32_t *)ws_take(j, nslots * 4);
     j->max_entries = c->o.max_entries ? c->o.max_entries : nslots / 2;
     j->recipe_cap = nslots;
-    j->recipe = (uint32_t *)ws_take(j, nslots * 4);
-    j->entry_slot = (uint32_t *)ws_take(j, nslots * 4);
-    j->store = (uint32_t *)ws_take(j, nslots * 4);
+    if (c->cache) {       // the context's own language cache (batch lanes with a shared budget)
+        j->tkey = (unsigned long long *)c->cache;
+        j->tval = (uint32_t *)(c->cache + nslots * 8);
+        j->recipe = j->tval + nslots;
+        j->entry_slot = j->recipe + nslots;
+        j->store = j->entry_slot + nslots;
+    } else {
+        j->tkey = (unsigned long long *)ws_take(j, nslots * 8);
+        j->tval = (uint32_t *)ws_take(j, nslots * 4);
+        j->recipe = (uint32_t *)ws_take(j, nslots * 4);
+        j->entry_slot = (uint32_t *)ws_take(j, nslots * 4);
+        j->store = (uint32_t *)ws_take(j, nslots * 4);
+    }
     if (!j->tkey || !j->tval || !j->recipe || !j->entry_slot || !j->store) return LTL_E_OOM;
 
     char *upload = (char *)ws_take(j, UPLOAD_BYTES);   // counters, then the level's block tables
@@ -754,7 +777,8 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     // bitmap | coll_bits | fb_bits | cand_viol | cand_fp (row-split levels whose tiles
     // span several workgroups); cleared at once
     uint64_t clear_bytes = nwa * 4 * 3;
-    uint32_t *bits3 = (uint32_t *)take_top(align_up(nwa * 4 * 4 + (split ? (uint64_t)nc * 8 : 0), 256));
+    uint32_t *bits3 = (uint32_t *)take_top(
+        align_up(nwa * 4 * 4 + (split ? (uint64_t)nc * 8 : 0), 256));
     uint32_t *cand_slot = (uint32_t *)take_top((uint64_t)nc * 4);
     uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
@@ -829,6 +853,23 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         cls_tiles[k] = tb;
     }
     cls_first[4] = (uint32_t)grouped.size();
+    // whole-row binary classes with LTL_CTX_LDS_TILES stage their child operands in LDS:
+    // groups of 2 x 2 tiles (8 x 8 pairs), numbered per class like the tiles
+    const bool staged = !split && (j->ctx->o.flags & LTL_CTX_LDS_TILES);
+    uint32_t cls_groups[4] = {0, 0, 0, 0};
+    if (staged) {
+        for (int k = 1; k < 4; ++k) {
+            uint32_t gb = 0;
+            for (uint32_t q = cls_first[k]; q < cls_first[k + 1]; ++q) {
+                Block &g = grouped[q];
+                const uint32_t ngi = (g.nti + 1) / 2, ngj = (g.ntj + 1) / 2;
+                g.st_base = gb;
+                g.nst = g.tri ? ngi * (ngi + 1) / 2 : ngi * ngj;
+                gb += g.nst;
+            }
+            cls_groups[k] = gb;
+        }
+    }
     {   // algorithmic bytes: every candidate's matrix written or compared once, each child
         // matrix read once per tile (tiles of TILE children a side; fused unary tiles read a
         // child once for its four connectives)
@@ -947,12 +988,33 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         for (int q = 0; q < 4; ++q) {
             const int k = order[q];
             if (!cls_tiles[k]) continue;
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(((uint64_t)cls_tiles[k] + 3) / 4, MAX_GRID);
+            // the evaluation needs a tile's whole rows (its fingerprints); verification and
+            // the write pass treat row blocks independently, so they take chunks of a tile's
+            // rows, enough for PASS_WAVES waves (one wave per tile leaves most SIMDs with one
+            // or two waves on long rows, too few to keep the owners' loads in flight)
+            // binary classes staged in LDS: work items are groups of 4 tiles, one workgroup each
+            const bool stg = staged && k != 0;
+            const uint64_t units = stg ? (uint64_t)cls_groups[k] : (uint64_t)cls_tiles[k];
+            const uint64_t waves_per_unit = stg ? 4 : 1;
+            uint32_t chunk = j->NB;
+            if (verify || write) {
+                const uint64_t per = std::max<uint64_t>(
+                    1, std::min<uint64_t>(j->NB / PASS_MIN_CHUNK, PASS_WAVES / (units * waves_per_unit)));
+                chunk = (uint32_t)((j->NB + per - 1) / per);
+            }
+            const uint64_t items = units * ((j->NB + chunk - 1) / chunk);
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(stg ? items : (items + 3) / 4, MAX_GRID);
             hipStream_t st = (fork && k == ucls) ? j->ctx->aux : j->s;
-            hipError_t e = write ? Launch<T>::write_pass(A, j->mw, k, grouped_d + cls_first[k],
-                                                         cls_first[k + 1] - cls_first[k], cls_tiles[k], grid, st)
-                                 : Launch<T>::level(A, j->mw, verify, k, grouped_d + cls_first[k],
-                                                    cls_first[k + 1] - cls_first[k], cls_tiles[k], j->NB, grid, st);
+            const Block *cb = grouped_d + cls_first[k];
+            const uint32_t nb = cls_first[k + 1] - cls_first[k];
+            hipError_t e;
+            if (stg)
+                e = Launch<T>::level_staged(A, j->mw, write ? 2 : (verify ? 1 : 0), k, cb, nb, cls_groups[k], chunk,
+                                            grid, st);
+            else if (write)
+                e = Launch<T>::write_pass(A, j->mw, k, cb, nb, cls_tiles[k], chunk, grid, st);
+            else
+                e = Launch<T>::level(A, j->mw, verify, k, cb, nb, cls_tiles[k], chunk, grid, st);
             if (e != hipSuccess) return e;
         }
         if (fork) {
@@ -1005,7 +1067,11 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     span.end();
     Counters hc;
     if (int e = sync_read_counters(j, &hc)) return e;
-    if (hc.overflow || hc.n_new > arena_cap) return LTL_E_OOM;
+    if (hc.overflow || hc.n_new > arena_cap) {
+        j->oom_kind = hc.overflow ? 1 : 2;
+        j->oom_new = hc.n_new;
+        return LTL_E_OOM;
+    }
     lv.first = (hc.first_sol == ~0ull) ? LTL_NO_SOLUTION : (uint64_t)hc.first_sol;
     lv.stored = lv.first == LTL_NO_SOLUTION && c < j->bound;
     uint32_t n_new = hc.n_new;
@@ -1107,6 +1173,7 @@ extern "C" int ltl_eval_level(ltl_job *j, uint32_t c, ltl_level_stats *stats) {
     if (j->stored_entries > j->max_entries) {
         j->status = LTL_E_OOM;
         j->searching = false;
+        j->oom_kind = 3;
         return LTL_E_OOM;
     }
     return LTL_OK;
@@ -1312,15 +1379,20 @@ extern "C" int ltl_job_result(ltl_job *j, ltl_result *out) {
     return out->status;
 }
 
-extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
-                         ltl_result *out) {
+// The whole learner on one job; *oom_kind / *oom_new tell why it ran out of memory
+// (see ltl_job::oom_kind; 1 when the job could not even be laid out).
+static int learn_job(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
+                     ltl_result *out, int *oom_kind, uint64_t *oom_new) {
     if (!out) return LTL_E_INVAL;
     memset(out, 0, sizeof(*out));
     out->solution_index = LTL_NO_SOLUTION;
+    *oom_kind = 0;
+    *oom_new = 0;
     ltl_job *j = nullptr;
     int st = ltl_job_create(ctx, spec, ops, cost_bound, &j);
     if (st != LTL_OK) {
         out->status = st;
+        if (st == LTL_E_OOM) *oom_kind = 1;
         return st;
     }
     for (uint32_t c = 1; c <= cost_bound; ++c) {
@@ -1328,8 +1400,64 @@ extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *op
         if (st != LTL_OK || !j->searching) break;
     }
     st = ltl_job_result(j, out);
+    if (st == LTL_E_OOM) {
+        *oom_kind = j->oom_kind ? j->oom_kind : 1;
+        *oom_new = j->oom_new;
+    }
     ltl_job_destroy(j);
     return st;
+}
+
+extern "C" int ltl_learn(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
+                         ltl_result *out) {
+    int kind = 0;
+    uint64_t nn = 0;
+    return learn_job(ctx, spec, ops, cost_bound, out, &kind, &nn);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: tile shape and level schedule of a workload, by timing whole jobs
+// ---------------------------------------------------------------------------
+extern "C" int ltl_autotune(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound,
+                            ltl_tuning *out) {
+    if (!ctx || !spec || !ops || !out) return LTL_E_INVAL;
+    if (ctx->busy) return LTL_E_STATE;
+    memset(out, 0, sizeof(*out));
+    // candidate configurations: binary tiles in registers (4 x 4) or staged in LDS (8 x 8),
+    // and the level size (in tiles) from which levels run the whole-row kernels
+    static const uint32_t kFlags[LTL_TUNE_CONFIGS] = {0, LTL_CTX_LDS_TILES, 0, 0, LTL_CTX_LDS_TILES};
+    static const uint32_t kSplit[LTL_TUNE_CONFIGS] = {8192, 8192, 2048, 32768, 32768};
+    const ltl_ctx_opts saved = ctx->o;
+    const uint32_t keep = LTL_CTX_U_CARRY | LTL_CTX_U_DOUBLING | LTL_CTX_RUC;
+    ltl_result ref{}, r{};
+    int status = LTL_OK;
+    double best = 1e300;
+    for (int k = -1; k < LTL_TUNE_CONFIGS; ++k) {
+        const int q = k < 0 ? 0 : k;          // k = -1: an untimed warm-up run
+        ctx->o.flags = (saved.flags & keep) | kFlags[q];
+        ctx->o.split_tiles = kSplit[q];
+        const auto t0 = std::chrono::steady_clock::now();
+        const int st = ltl_learn(ctx, spec, ops, cost_bound, &r);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (st < 0 && st != LTL_E_OOM) { status = st; break; }
+        if (k < 0) { ref = r; continue; }
+        // every configuration must give the same result
+        bool same = r.status == ref.status && r.cost == ref.cost && r.levels_done == ref.levels_done &&
+                    r.solution_index == ref.solution_index && r.num_nodes == ref.num_nodes;
+        for (uint32_t c = 0; same && c <= r.levels_done && c < LTL_MAX_LEVELS; ++c)
+            same = r.level_new[c] == ref.level_new[c] && r.level_candidates[c] == ref.level_candidates[c];
+        if (!same) { status = LTL_E_STATE; break; }
+        out->ms[k] = ms;
+        out->flags[k] = kFlags[k];
+        out->split_tiles[k] = kSplit[k];
+        ++out->tried;
+        if (ms < best) {
+            best = ms;
+            out->best = (uint32_t)k;
+        }
+    }
+    ctx->o = saved;
+    return status;
 }
 
 // ---------------------------------------------------------------------------
@@ -1433,6 +1561,14 @@ extern "C" int ltl_holds(ltl_ctx *ctx, const ltl_spec *spec, const ltl_node *nod
 // A batch executor: `lanes` contexts (stream, workspace slice, hash table) and
 // lanes-1 worker threads that sleep between runs.  The calling thread works as
 // lane 0 of each run.
+// Language-cache footprint of a job: the fixed tables of its row layout, the bytes per
+// matrix, and an estimate of the workspace region it needs.
+struct Footprint {
+    uint64_t fixed = 0;    // row tables, atom matrices, letters, counters
+    uint64_t cmb = 0;      // bytes per characteristic matrix
+    uint64_t request = 0;  // region to start with
+};
+
 struct ltl_batch {
     ltl_batch_opts o{};
     std::mutex big_mu;                     // LTL_BATCH_BIG_ALONE: turns for whole-row levels
@@ -1455,6 +1591,7 @@ struct ltl_batch {
     std::chrono::steady_clock::time_point t0;
     // LTL_BATCH_SHARED_BUDGET: regions of the whole workspace, sized per job
     bool shared = false;
+    uint64_t pool_base = 0, pool_bytes = 0;    // the regions' pool after the lanes' caches
     std::mutex pool_mu;
     std::condition_variable pool_cv;
     std::map<uint64_t, uint64_t> free_regions;    // offset -> size, coalesced
@@ -1463,6 +1600,7 @@ struct ltl_batch {
     uint32_t jobs_left = 0;
     uint32_t in_flight = 0;
     uint32_t head_bypassed = 0;            // admissions that passed over the job at the queue's head
+    std::vector<Footprint> foot;           // per job of the run
     ltl_batch_stats stats{};
 };
 
@@ -1500,18 +1638,26 @@ static void pool_release(ltl_batch *b, uint64_t off, uint64_t size) {
     }
 }
 
-// Estimated workspace bytes of a job (its language-cache footprint): the fixed tables
-// of a region of that size plus the matrices of the stored levels up to cost 5 (or
-// the bound), with level sizes modelled as A * 5^(c-1) (about the growth of the
-// workloads' first levels), at least LTL_MIN_WORKSPACE.  Too small an estimate costs
-// a re-run in a larger region, never a different result.
-static uint64_t footprint_estimate(const ltl_batch_job &jb) {
+// Region bytes for `entries` stored matrices plus `cands` candidates of the level being
+// evaluated (the language cache's hash and entry tables are the lane's own).
+static uint64_t region_for(const Footprint &f, uint64_t entries, uint64_t cands) {
+    const uint64_t body = f.fixed + entries * f.cmb + cands * 40;
+    return std::max<uint64_t>(LTL_MIN_WORKSPACE, align_up(body + body / 8 + (8u << 20), 1u << 20));
+}
+
+// First estimate: the stored levels up to cost 5 (or the bound) with level sizes modelled
+// as A * 5^(c-1) (about the growth of the workloads' first levels).  Too small an estimate
+// costs a re-run in a larger region, never a different result.
+static Footprint footprint_estimate(const ltl_batch_job &jb) {
+    Footprint f;
     const ltl_spec &sp = jb.spec;
     const uint32_t T = sp.num_pos + sp.num_neg;
     std::vector<uint64_t> off((size_t)T + 1, 0);
     if (sp.flags & LTL_SPEC_DEVICE) {
-        if (hipMemcpy(off.data(), sp.offsets, off.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
-            return LTL_MIN_WORKSPACE;
+        if (hipMemcpy(off.data(), sp.offsets, off.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+            f.request = LTL_MIN_WORKSPACE;
+            return f;
+        }
     } else {
         memcpy(off.data(), sp.offsets, off.size() * 8);
     }
@@ -1525,13 +1671,26 @@ static uint64_t footprint_estimate(const ltl_batch_job &jb) {
         r += w;
     }
     const uint64_t R = align_up(std::max<uint64_t>(r, 1), 64);
-    const uint64_t cmb = R * (W / 8);
+    f.cmb = R * (W / 8);
+    f.fixed = R * 64 + (uint64_t)sp.num_props * f.cmb + off[T] * 4 + (uint64_t)T * 16 + (4u << 20);
     uint64_t entries = 0, e = sp.num_props;
     for (uint32_t c = 1; c < std::min<uint32_t>(jb.cost_bound, 6); ++c, e *= 5) entries += e;
-    const uint64_t tables = R * 64 + (uint64_t)sp.num_props * cmb + off[T] * 4 + (uint64_t)T * 16 + (4u << 20);
-    const uint64_t levels = entries * cmb + entries * 5 * 32;    // matrices + per-candidate scratch
-    // the hash table takes a quarter of the region
-    return std::max<uint64_t>(LTL_MIN_WORKSPACE, align_up((tables + levels) * 4 / 3 + (8u << 20), 1u << 20));
+    f.request = region_for(f, entries, e);
+    return f;
+}
+
+// Region for the next attempt of a job that ran out of memory: what its completed levels
+// hold, plus one more level grown by the last growth factor (2..10), and at least four
+// times the last region.
+static uint64_t regrow(const Footprint &f, const ltl_result &res, uint64_t last) {
+    const uint32_t d = std::min<uint32_t>(res.levels_done, LTL_MAX_LEVELS - 1);
+    uint64_t stored = 0;
+    for (uint32_t c = 1; c <= d; ++c) stored += res.level_new[c];
+    const uint64_t en = d ? res.level_new[d] : 1, ep = d > 1 ? res.level_new[d - 1] : 1;
+    const double g = std::min(10.0, std::max(2.0, (double)en / (double)std::max<uint64_t>(ep, 1)));
+    const uint64_t cn = d ? res.level_candidates[d] : 1;
+    const uint64_t need = region_for(f, stored + (uint64_t)(g * (double)en), (uint64_t)(g * (double)cn));
+    return std::max<uint64_t>(last * 4, need);
 }
 
 static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
@@ -1551,6 +1710,28 @@ static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
     }
 }
 
+// Slots of the hash table a context sizes for a workspace of `bytes` (as job_setup does
+// when hash_slots_log2 is 0).
+static uint32_t auto_slots_log2(uint64_t bytes) {
+    uint32_t sl = 26;
+    while (sl > 10 && (24ull << sl) > bytes / 4) --sl;
+    return sl;
+}
+
+// A job that ran out of memory would also run out, at the same level and with the same
+// counts, in the whole pool `total`: its stored entries exceeded the entry cap (the
+// lane's hash table does not depend on the region), or the new entries of its failing
+// level alone exceed the pool.  Then the result of this run is final.
+static bool oom_at_any_size(const Footprint &f, const ltl_result &res, int kind, uint64_t oom_new, uint64_t total) {
+    if (kind == 3) return true;
+    if (kind == 2 && f.cmb) {
+        uint64_t stored = 0;
+        for (uint32_t c = 1; c <= res.levels_done && c < LTL_MAX_LEVELS; ++c) stored += res.level_new[c];
+        return (stored + oom_new) * f.cmb > total;
+    }
+    return false;
+}
+
 // Shared-budget lanes: each lane takes the first arrived job (in arrival order) whose
 // requested region fits the free workspace, binds its context to that region and runs
 // it; a job that runs out of memory in a region smaller than the whole workspace goes
@@ -1558,7 +1739,7 @@ static void batch_lane_jobs(ltl_batch *b, uint32_t lane) {
 // at the head from waiting forever, at most 4 * lanes admissions may pass over it.
 static void batch_lane_shared(ltl_batch *b, uint32_t lane) {
     ltl_ctx *c = b->ctxs[lane];
-    const uint64_t total = b->o.workspace_bytes & ~255ull;
+    const uint64_t total = b->pool_bytes;
     for (;;) {
         uint32_t i = 0;
         uint64_t req = 0, off = 0;
@@ -1599,21 +1780,22 @@ static void batch_lane_shared(ltl_batch *b, uint32_t lane) {
             b->stats.max_in_flight = std::max(b->stats.max_in_flight, b->in_flight);
             ++b->stats.admissions;
         }
-        // the lane's context on the job's region: its hash table is sized from the region
-        // and initialised by the job (the region held other jobs' data before)
-        c->o.workspace = (char *)b->o.workspace + off;
+        // the lane's context on the job's region; its language cache (hash and entry tables)
+        // is the lane's own, emptied by each job, so no job initialises a table
+        c->o.workspace = (char *)b->o.workspace + b->pool_base + off;
         c->o.workspace_bytes = req;
-        c->table_clean_log2 = 0;
         const auto a = std::chrono::steady_clock::now();
         ltl_result &res = b->results[i];
-        const int st = ltl_learn(c, &b->jobs[i].spec, &b->jobs[i].ops, b->jobs[i].cost_bound, &res);
+        int kind = 0;
+        uint64_t oom_new = 0;
+        const int st = learn_job(c, &b->jobs[i].spec, &b->jobs[i].ops, b->jobs[i].cost_bound, &res, &kind, &oom_new);
         const auto e = std::chrono::steady_clock::now();
         std::lock_guard<std::mutex> lk(b->pool_mu);
         pool_release(b, off, req);
         --b->in_flight;
         if (b->job_ms) b->job_ms[2 * (size_t)i] += std::chrono::duration<double, std::milli>(e - a).count();
-        if (st == LTL_E_OOM && req < total) {
-            b->queue.emplace_front(i, std::min<uint64_t>(total, req * 4));
+        if (st == LTL_E_OOM && req < total && !oom_at_any_size(b->foot[i], res, kind, oom_new, total)) {
+            b->queue.emplace_front(i, std::min<uint64_t>(total, regrow(b->foot[i], res, req)));
             ++b->stats.reruns;
         } else {
             if (b->job_ms) b->job_ms[2 * (size_t)i + 1] = std::chrono::duration<double, std::milli>(e - b->t0).count();
@@ -1690,6 +1872,20 @@ extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
     if (!b) return LTL_E_INVAL;
     b->o = *o;
     b->shared = shared;
+    // shared budget: each lane's language cache (hash and entry tables, 24 bytes a slot) at
+    // the start of the workspace, as large as the hash table a context of the whole
+    // workspace would have, or smaller until the lanes' caches take at most half of it;
+    // the rest is the pool of job regions
+    uint32_t cache_sl = auto_slots_log2(o->workspace_bytes);
+    while (cache_sl > 10 && (uint64_t)o->lanes * (24ull << cache_sl) > o->workspace_bytes / 2) --cache_sl;
+    const uint64_t cache_one = align_up(24ull << cache_sl, 256);
+    const uint64_t cache_all = shared ? cache_one * o->lanes : 0;
+    b->pool_base = cache_all;
+    b->pool_bytes = shared ? ((o->workspace_bytes - cache_all) & ~255ull) : 0;
+    if (shared && b->pool_bytes < LTL_MIN_WORKSPACE) {
+        delete b;
+        return LTL_E_INVAL;
+    }
     const uint32_t lanes = o->lanes;
     b->streams.assign(lanes, nullptr);
     b->ctxs.assign(lanes, nullptr);
@@ -1704,15 +1900,20 @@ extern "C" int ltl_batch_create(const ltl_batch_opts *o, ltl_batch **out) {
         co.flags = o->flags & ~(LTL_BATCH_BIG_ALONE | LTL_BATCH_SHARED_BUDGET);
         // shared budget: a lane's context is bound to a region per job (set when the job
         // is admitted); until then it names the start of the workspace
-        co.workspace = (char *)o->workspace + (shared ? 0 : (uint64_t)l * slice);
+        co.workspace = (char *)o->workspace + (shared ? cache_all : (uint64_t)l * slice);
         co.workspace_bytes = shared ? LTL_MIN_WORKSPACE : slice;
         co.stream = b->streams[l];
         co.hash_slots_log2 = o->hash_slots_log2;
         co.word_bits = o->word_bits;
         co.fp_bits = o->fp_bits;
         co.max_entries = o->max_entries;
+        co.split_tiles = o->split_tiles;
         st = ltl_ctx_create(&co, &b->ctxs[l]);
         if (st == LTL_OK && (o->flags & LTL_BATCH_BIG_ALONE)) b->ctxs[l]->big_mu = &b->big_mu;
+        if (st == LTL_OK && shared) {
+            b->ctxs[l]->cache = (char *)o->workspace + (uint64_t)l * cache_one;
+            b->ctxs[l]->cache_slots_log2 = cache_sl;
+        }
     }
     if (st != LTL_OK) {
         ltl_batch_destroy(b);
@@ -1755,13 +1956,21 @@ static int batch_go(ltl_batch *b, const ltl_batch_job *jobs, uint32_t njobs, con
     b->next = 0;
     if (b->shared) {      // every job starts with its footprint estimate
         b->stats = ltl_batch_stats{};
-        b->stats.budget_bytes = b->o.workspace_bytes & ~255ull;
+        b->stats.budget_bytes = b->pool_bytes;
         b->free_regions.clear();
-        b->free_regions[0] = b->stats.budget_bytes;
+        b->free_regions[0] = b->pool_bytes;
         b->in_use = 0;
         b->queue.clear();
-        for (uint32_t i = 0; i < njobs; ++i)
-            b->queue.emplace_back(i, std::min<uint64_t>(b->stats.budget_bytes, footprint_estimate(jobs[i])));
+        b->foot.resize(njobs);
+        // a first region of at least a third of a lane's even share: the lanes' first
+        // regions take at most a third of the budget, and most jobs then fit at once
+        // (each re-run repeats the levels before its failure)
+        const uint64_t floor = align_up(b->stats.budget_bytes / (3ull * b->o.lanes), 1u << 20) & ~255ull;
+        for (uint32_t i = 0; i < njobs; ++i) {
+            b->foot[i] = footprint_estimate(jobs[i]);
+            b->queue.emplace_back(i, std::min<uint64_t>(b->stats.budget_bytes,
+                                                        std::max<uint64_t>(floor, b->foot[i].request)));
+        }
         b->jobs_left = njobs;
         b->in_flight = 0;
         b->head_bypassed = 0;

@@ -28,7 +28,8 @@ struct Block {
     uint32_t nti, ntj;    // tile grid (rows of a-tiles, columns of b-tiles)
     uint32_t a_gid, b_gid;   // global entry id of the first a / b entry (ATOM: prop 0)
     uint64_t a_ptr;       // ATOM: device address of the first atom matrix
-    uint64_t b_ptr;       // unused (0)
+    uint32_t st_base;     // LDS-staged binary blocks: first 8 x 8 group of tiles in the class list
+    uint32_t nst;         // ... and the block's groups
     uint32_t fcb[4];      // OP_FUSED4 blocks: canonical base of F, G, X, NOT over the same children
     uint32_t ind;         // bit 0 / bit 1: a / b children are stored entries, found through store[]
     uint32_t pad;
@@ -112,6 +113,10 @@ struct Launch {
     // cls: 0 unary, 1 and/or, 2 until (doubling), 3 until (carry adder)
     static hipError_t level(const LevelArgs<T> &A, bool mw, bool verify, int cls, const Block *blocks,
                             uint32_t nblocks, uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
+    // whole-row binary classes with child operands staged in LDS: one workgroup of 4 waves
+    // per 8 x 8 group of tiles (pass 0 evaluation, 1 verification, 2 write pass)
+    static hipError_t level_staged(const LevelArgs<T> &A, bool mw, int pass, int cls, const Block *blocks,
+                                   uint32_t nblocks, uint32_t ngroups, uint32_t chunk, uint32_t grid, hipStream_t s);
     // row-split levels, every connective class in one dispatch: evaluation with one
     // workgroup per tile (claims and claimers' matrices included) ...
     static hipError_t level_wg(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
@@ -121,7 +126,7 @@ struct Launch {
     // whole-row levels: groups joined by other candidates, then the write pass per class
     static hipError_t mark_members(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
     static hipError_t write_pass(const LevelArgs<T> &A, bool mw, int cls, const Block *blocks, uint32_t nblocks,
-                                 uint32_t ntiles, uint32_t grid, hipStream_t s);
+                                 uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s);
     static constexpr uint32_t waves_per_wg(bool mw) { return mw ? 4u : 8u; }
     // ... and verification with one wave per (tile, row chunk)
     static hipError_t verify_all(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,

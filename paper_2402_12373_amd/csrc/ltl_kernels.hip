@@ -39,9 +39,13 @@ namespace ltl {
 
 constexpr int OP_UC = 8;   // U computed by the carry-chain adder
 
-// Row blocks of operands in flight per evaluation wave (a tuning constant)
+// Row blocks of operands in flight per evaluation wave, for one-word rows and for
+// multi-word rows (tuning constants: multi-word tiles hold more registers per row block)
 #ifndef LTL_EVAL_PIPE
 #define LTL_EVAL_PIPE 2
+#endif
+#ifndef LTL_EVAL_PIPE_MW
+#define LTL_EVAL_PIPE_MW 1
 #endif
 // Waves per SIMD the 64-bit level kernels are register-allocated for (tuning constants)
 #ifndef LTL_WAVES_U64
@@ -568,7 +572,7 @@ __device__ __forceinline__ uint64_t child_addr(const LevelArgs<T> &A, const Bloc
         const uint32_t pos = uniform(A.store[(which ? b.b_gid : b.a_gid) + i]);
         return (uint64_t)(uintptr_t)A.arena + (uint64_t)pos * cmb;
     }
-    return (which ? b.b_ptr : b.a_ptr) + (uint64_t)i * cmb;
+    return b.a_ptr + (uint64_t)i * cmb;      // atoms (a side only: ATOM blocks are unary)
 }
 
 template <typename T>
@@ -666,7 +670,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
 
     // row blocks are streamed PIPE at a time, the next PIPE loaded while the current
     // ones are computed
-    constexpr int PIPE = (VERIFY || WG) ? 1 : LTL_EVAL_PIPE;
+    constexpr int PIPE = (VERIFY || WG) ? 1 : (MW ? LTL_EVAL_PIPE_MW : LTL_EVAL_PIPE);
     auto load_group = [&](uint32_t blk, Rowset (&L)[PIPE]) {
 #pragma unroll
         for (int u = 0; u < PIPE; ++u)
@@ -858,12 +862,261 @@ __device__ __forceinline__ Block uniform_block(const Block &in) {
     return b;
 }
 
+// ---------------------------------------------------------------------------
+// LDS staging of child operand tiles (binary connectives, whole-row levels).  A
+// workgroup of 4 waves takes an 8 x 8 group of pairs (2 x 2 tiles of 4 x 4): per row
+// block each wave loads 4 of the 16 child words (waves 0-1 the 8 a-children, waves
+// 2-3 the 8 b-children) into LDS, and every wave reads the 4 + 4 words of its own
+// tile from there, so each child row block is fetched once per 8 x 8 group instead of
+// once per 4 x 4 tile.  The LDS buffer is double-buffered: one barrier per row block.
+// ---------------------------------------------------------------------------
+enum { CLS_UNARY = 0, CLS_ANDOR = 1, CLS_U = 2, CLS_UC = 3 };
+constexpr int STG_SIDE = 2 * TILE;            // children per side of a group
+template <typename T>
+struct StageBuf {
+    T w[2][2 * STG_SIDE][64];
+};
+
+template <typename T, bool MW, int OP, bool VERIFY, bool WONLY>
+__device__ __forceinline__ void run_tile_staged(const LevelArgs<T> &A, const Block &b, uint32_t ia0, uint32_t jb0,
+                                                int lane, uint32_t wv, uint32_t rb0, uint32_t rb1, StageBuf<T> *sb) {
+    constexpr int TI = TILE, TJ = TILE, NP = TI * TJ;
+    constexpr bool EVAL = !VERIFY && !WONLY;
+    const uint32_t nbj = b.tri ? b.na : b.nb;
+    const uint32_t di = TI * (wv >> 1), dj = TJ * (wv & 1);
+    const uint32_t i0 = ia0 + di, j0 = jb0 + dj;
+    uint32_t idx[NP];
+#pragma unroll
+    for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < TJ; ++jj) {
+            const uint32_t i = i0 + ii, j = j0 + jj;
+            const bool v = i < b.na && (b.tri ? (j < b.na && j > i) : (j < b.nb));
+            idx[ii * TJ + jj] = uniform(v ? cand_index(b, i, j) : 0xFFFFFFFFu);
+        }
+    // the 4 children this wave stages
+    const uint32_t side = wv >> 1, part = wv & 1;
+    gptr<T> sp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t c = (side ? jb0 : ia0) + 4u * part + (uint32_t)k;
+        sp[k] = as_global<T>(child_addr<T>(A, b, (int)side, min(c, (side ? nbj : b.na) - 1)));
+    }
+    // what this wave does with its pairs
+    uint32_t need = 0;
+    gptr<T> tp[VERIFY ? NP : 1];      // VERIFY: stored matrix to compare with, or null
+    gptr<T> dp[WONLY ? NP : 1];       // WONLY: arena place of the claimer's matrix, or null
+    if constexpr (VERIFY) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            uint32_t g = 0xFFFFFFFFu;
+            if (idx[p] != 0xFFFFFFFFu) {
+                const uint32_t h = uniform(A.cand_slot[idx[p]]);
+                if (h != NO_SLOT) {
+                    const uint32_t v = uniform(A.tval[h]);
+                    if (v & VAL_SETTLED) {
+                        g = v & ~VAL_SETTLED;
+                        if (g >= A.level_base) {
+                            const uint32_t src = A.verify_rep
+                                ? uniform(A.recipe[g])
+                                : uniform(A.claimer[uniform(A.store[g]) - A.level_base]);
+                            if (src == idx[p]) g = 0xFFFFFFFFu;
+                        }
+                    } else if (v != idx[p]) {
+                        g = A.level_base + uniform(rank_of(A.bitmap, A.wordpre, v));
+                    }
+                }
+            }
+            tp[p] = (g != 0xFFFFFFFFu) ? as_global<T>(arena_addr<T>(A, uniform(A.store[g]))) : (gptr<T>)nullptr;
+            if (tp[p]) need |= 1u << p;
+        }
+    } else if constexpr (WONLY) {
+        const bool keep_all = !A.bound_level && uniform64(A.ctr->first_sol) == ~0ull;
+        uint32_t my_claim = 0xFFFFFFFFu;
+        if (lane < NP) {
+            uint32_t idx_l = 0xFFFFFFFFu;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                if (lane == p) idx_l = idx[p];
+            if (idx_l != 0xFFFFFFFFu) {
+                const uint32_t q = A.cand_claim[idx_l];
+                if (q < A.arena_cap && (keep_all || A.has_member[q])) my_claim = q;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const uint32_t cp = (uint32_t)__builtin_amdgcn_readlane((int)my_claim, p);
+            dp[p] = (cp < A.arena_cap) ? as_global<T>(arena_addr<T>(A, A.level_base + cp)) : (gptr<T>)nullptr;
+            if (dp[p]) need |= 1u << p;
+        }
+    } else {
+        need = ~0u;
+    }
+    need = uniform(need);
+    // the group is skipped only if none of its waves has work (every wave stages)
+    if (!__syncthreads_or(need != 0u)) return;
+
+    uint64_t acc[EVAL ? NP : 1];
+    uint32_t viol[EVAL ? NP : 1];
+    T diff[VERIFY ? NP : 1];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if constexpr (EVAL) { acc[p] = 0; viol[p] = 0; }
+        if constexpr (VERIFY) diff[p] = 0;
+    }
+    const uint32_t slot0 = side * STG_SIDE + 4u * part;
+    T nxt[4];
+    if (rb0 < rb1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nxt[k] = ldg(sp[k], rb0 * 64u + (uint32_t)lane);
+    }
+    uint32_t buf = 0;
+    for (uint32_t blk = rb0; blk < rb1; ++blk) {
+        const uint32_t r = blk * 64u + (uint32_t)lane;
+        T cur[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
+        if (blk + 1 < rb1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nxt[k] = ldg(sp[k], r + 64u);
+        }
+        RowMeta<T> m = load_meta<T, MW, EVAL>(A.rows, r, lane);
+        T tv[VERIFY ? NP : 1];
+        if constexpr (VERIFY) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) tv[p] = tp[p] ? ldg(tp[p], r) : (T)0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sb->w[buf][slot0 + k][lane] = cur[k];
+        __syncthreads();
+        if (need) {
+            T av[TI], bv[TJ];
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii) av[ii] = sb->w[buf][di + ii][lane];
+#pragma unroll
+            for (int jj = 0; jj < TJ; ++jj) bv[jj] = sb->w[buf][STG_SIDE + dj + jj][lane];
+            finish_meta<T, MW>(m, lane);
+            T w[NP];
+            tile_words<T, MW, OP, TI, TJ, !EVAL>(av, bv, m, A.rows, lane, w, need);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                if constexpr (EVAL) {
+                    if constexpr (!MW && sizeof(T) == 4) viol[p] |= (uint32_t)(w[p] ^ m.sw);
+                    else viol[p] |= (uint32_t)((w[p] ^ m.sw) >> (8 * sizeof(T) - 32)) &
+                                    (uint32_t)(m.sm >> (8 * sizeof(T) - 32));
+                    fp_add<T>(acc[p], w[p], m);
+                } else if constexpr (VERIFY) {
+                    diff[p] |= w[p] ^ tv[p];
+                } else {
+                    if (dp[p]) stg((T *)(uintptr_t)dp[p], r, w[p]);
+                }
+            }
+        }
+        buf ^= 1u;
+    }
+    if constexpr (EVAL) {
+        const uint64_t my_fp = wave_sums<NP>(acc, lane);   // valid in lanes < NP
+        uint32_t my_idx = 0xFFFFFFFFu;
+        bool my_bad = false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if constexpr (!MW && sizeof(T) == 4) viol[p] &= 0x80000000u;
+            const bool bad = __ballot(viol[p] != 0) != 0ull;
+            if (lane == p) { my_idx = idx[p]; my_bad = bad; }
+        }
+        if (my_idx != 0xFFFFFFFFu) {
+            uint32_t my_claim;
+            if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
+            A.cand_slot[my_idx] = probe_claim<T>(A, finish_fp(my_fp, A.fp_mask), my_idx, my_claim);
+            if (A.cand_claim) A.cand_claim[my_idx] = my_claim;
+        }
+    } else if constexpr (VERIFY) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (!tp[p]) continue;
+            const bool mism = __ballot(diff[p] != 0) != 0ull;
+            if (mism && lane == 0) {
+                const uint32_t bit = 1u << (idx[p] & 31u);
+                if (!(atomicOr(&A.coll_bits[idx[p] >> 5], bit) & bit)) atomicAdd(&A.ctr->n_coll, 1u);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int find_block_group(const Block *B, int nb, uint32_t s) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (B[mid].st_base <= s) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Local group index -> first a and b child of the 8 x 8 group (row-major over the
+// block's group grid; the upper triangle for AND/OR of one level with itself).
+__device__ __forceinline__ void decode_group(const Block &b, uint32_t ls, uint32_t &ia0, uint32_t &jb0) {
+    const uint32_t ngi = (b.nti + 1) / 2;
+    if (!b.tri) {
+        const uint32_t ngj = (b.ntj + 1) / 2;
+        ia0 = (ls / ngj) * STG_SIDE;
+        jb0 = (ls % ngj) * STG_SIDE;
+        return;
+    }
+    const uint64_t n = ngi;
+    double nn = 2.0 * (double)n + 1.0;
+    double disc = nn * nn - 8.0 * (double)ls;
+    uint64_t it = (uint64_t)((nn - sqrt(disc > 0 ? disc : 0.0)) * 0.5);
+    if (it >= n) it = n - 1;
+    auto start = [&](uint64_t i) -> uint64_t { return i * n - (i * (i ? i - 1 : 0)) / 2; };
+    while (it > 0 && start(it) > ls) --it;
+    while (it + 1 < n && start(it + 1) <= ls) ++it;
+    const uint64_t jt = it + (ls - start(it));
+    ia0 = (uint32_t)it * STG_SIDE;
+    jb0 = (uint32_t)jt * STG_SIDE;
+}
+
+// PASS 0 evaluation, 1 verification, 2 write pass; one workgroup of 4 waves per
+// (group, row chunk) work item.
+template <typename T, bool MW, int PASS, int CLS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : LTL_WAVES_U64)))
+void k_level_stg(LevelArgs<T> A, const Block *blocks, uint32_t nblocks, uint32_t ngroups, uint32_t chunk) {
+    __shared__ StageBuf<T> sb;
+    constexpr bool VERIFY = PASS == 1, WONLY = PASS == 2;
+    const int lane = (int)__lane_id();
+    const uint32_t wv = uniform(threadIdx.x >> 6);
+    if constexpr (VERIFY || WONLY) {
+        if (uniform(A.ctr->overflow) || uniform(A.ctr->n_new) > A.arena_cap) return;
+    }
+    const uint32_t NB = A.rows.NB;
+    const uint32_t nchunk = (NB + chunk - 1) / chunk;
+    const uint32_t nwork = ngroups * nchunk;
+    for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const uint32_t s = w / nchunk, q = w - s * nchunk;
+        const uint32_t rb0 = q * chunk, rb1 = min(NB, rb0 + chunk);
+        const int bi = (int)uniform((uint32_t)find_block_group(blocks, (int)nblocks, s));
+        const Block b = uniform_block(blocks[bi]);
+        uint32_t ia0, jb0;
+        decode_group(b, s - b.st_base, ia0, jb0);
+        ia0 = uniform(ia0);
+        jb0 = uniform(jb0);
+        if constexpr (CLS == CLS_ANDOR) {
+            if (b.op == LTL_AND) run_tile_staged<T, MW, LTL_AND, VERIFY, WONLY>(A, b, ia0, jb0, lane, wv, rb0, rb1, &sb);
+            else run_tile_staged<T, MW, LTL_OR, VERIFY, WONLY>(A, b, ia0, jb0, lane, wv, rb0, rb1, &sb);
+        } else if constexpr (CLS == CLS_U) {
+            run_tile_staged<T, MW, LTL_U, VERIFY, WONLY>(A, b, ia0, jb0, lane, wv, rb0, rb1, &sb);
+        } else {
+            run_tile_staged<T, MW, OP_UC, VERIFY, WONLY>(A, b, ia0, jb0, lane, wv, rb0, rb1, &sb);
+        }
+        __syncthreads();    // the LDS buffers are free for the next work item
+    }
+}
+
 // Connective classes get kernels of their own, so that each is register-
 // allocated for its own tile loop: CLS_UNARY (ATOM, NOT, X, F, G; 4 children
 // per tile), CLS_ANDOR (4 x 4 pairs), CLS_U (4 x 4 pairs, doubling) and
 // CLS_UC (4 x 4 pairs, carry adder).  Blocks of a class are listed in
 // A.cls_blocks with class-local tile numbering.
-enum { CLS_UNARY = 0, CLS_ANDOR = 1, CLS_U = 2, CLS_UC = 3 };
+
 
 template <typename T, bool MW, bool VERIFY, int CLS, bool WONLY = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : LTL_WAVES_U64))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
@@ -1022,6 +1275,7 @@ __global__ __launch_bounds__(256) void k_probe(LevelArgs<T> A, uint32_t ncand) {
         if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)x);
         uint32_t claim;
         A.cand_slot[x] = probe_claim<T>(A, finish_fp(A.cand_fp[x], A.fp_mask), x, claim);
+        if (A.cand_claim) A.cand_claim[x] = claim;
     }
 }
 
@@ -1610,6 +1864,37 @@ hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls
     return hipGetLastError();
 }
 
+template <typename T, bool MW, int PASS>
+static void launch_stg_cls(const LevelArgs<T> &A, int cls, const Block *blocks, uint32_t nb, uint32_t ng, uint32_t ch,
+                           uint32_t grid, hipStream_t s) {
+    switch (cls) {
+    case CLS_ANDOR: hipLaunchKernelGGL((k_level_stg<T, MW, PASS, CLS_ANDOR>), dim3(grid), dim3(256), 0, s, A, blocks, nb, ng, ch); break;
+    case CLS_U:     hipLaunchKernelGGL((k_level_stg<T, MW, PASS, CLS_U>), dim3(grid), dim3(256), 0, s, A, blocks, nb, ng, ch); break;
+    default:        hipLaunchKernelGGL((k_level_stg<T, MW, PASS, CLS_UC>), dim3(grid), dim3(256), 0, s, A, blocks, nb, ng, ch); break;
+    }
+}
+
+template <typename T, bool MW>
+static void launch_stg(const LevelArgs<T> &A, int pass, int cls, const Block *blocks, uint32_t nb, uint32_t ng,
+                       uint32_t ch, uint32_t grid, hipStream_t s) {
+    if (pass == 0) launch_stg_cls<T, MW, 0>(A, cls, blocks, nb, ng, ch, grid, s);
+    else if (pass == 1) launch_stg_cls<T, MW, 1>(A, cls, blocks, nb, ng, ch, grid, s);
+    else launch_stg_cls<T, MW, 2>(A, cls, blocks, nb, ng, ch, grid, s);
+}
+
+template <typename T>
+hipError_t Launch<T>::level_staged(const LevelArgs<T> &A, bool mw, int pass, int cls, const Block *blocks,
+                                   uint32_t nblocks, uint32_t ngroups, uint32_t chunk, uint32_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            launch_stg<T, true>(A, pass, cls, blocks, nblocks, ngroups, chunk, grid, s);
+            return hipGetLastError();
+        }
+    }
+    launch_stg<T, false>(A, pass, cls, blocks, nblocks, ngroups, chunk, grid, s);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t Launch<T>::mark_members(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((ncand + 255) / 256, 4096));
@@ -1619,8 +1904,7 @@ hipError_t Launch<T>::mark_members(const LevelArgs<T> &A, uint32_t ncand, hipStr
 
 template <typename T, bool MW>
 static void launch_write_cls(const LevelArgs<T> &A, int cls, const Block *blocks, uint32_t nb, uint32_t nt,
-                             uint32_t grid, hipStream_t s) {
-    const uint32_t ch = A.rows.NB;
+                             uint32_t ch, uint32_t grid, hipStream_t s) {
     switch (cls) {
     case CLS_UNARY: hipLaunchKernelGGL((k_level<T, MW, false, CLS_UNARY, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
     case CLS_ANDOR: hipLaunchKernelGGL((k_level<T, MW, false, CLS_ANDOR, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
@@ -1631,14 +1915,14 @@ static void launch_write_cls(const LevelArgs<T> &A, int cls, const Block *blocks
 
 template <typename T>
 hipError_t Launch<T>::write_pass(const LevelArgs<T> &A, bool mw, int cls, const Block *blocks, uint32_t nblocks,
-                                 uint32_t ntiles, uint32_t grid, hipStream_t s) {
+                                 uint32_t ntiles, uint32_t chunk, uint32_t grid, hipStream_t s) {
     if constexpr (sizeof(T) == 8) {
         if (mw) {
-            launch_write_cls<T, true>(A, cls, blocks, nblocks, ntiles, grid, s);
+            launch_write_cls<T, true>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
             return hipGetLastError();
         }
     }
-    launch_write_cls<T, false>(A, cls, blocks, nblocks, ntiles, grid, s);
+    launch_write_cls<T, false>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ LTL_E_INVAL, LTL_E_INCONSISTENT, LTL_E_TOO_LONG, LTL_E_OOM, LTL_E_DEVICE, LTL_E_
 LTL_E_BUFFER = -7
 ATOM, NOT, AND, OR, X, F, G, U = range(8)
 CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL, CTX_RUC, CTX_U_DOUBLING = 0x1, 0x2, 0x4, 0x8, 0x10
+CTX_LDS_TILES = 0x20   # binary tiles of whole-row levels stage 8 x 8 groups of child words in LDS
 BATCH_BIG_ALONE = 0x100    # batch flag: whole-row levels of different lanes take turns
 BATCH_SHARED_BUDGET = 0x200   # batch flag: one memory budget, regions sized per job
 SPEC_DEVICE = 0x1
@@ -35,7 +36,7 @@ EXPORTS = ("ltl_ctx_create", "ltl_ctx_destroy", "ltl_learn", "ltl_learn_batch", 
            "ltl_batch_destroy", "ltl_job_create", "ltl_eval_level",
            "ltl_job_result", "ltl_job_formula", "ltl_job_dump_cm", "ltl_job_get_info", "ltl_job_destroy",
            "ltl_status_str", "ltl_overfit", "ltl_batch_serve", "ltl_holds", "ltl_det_split", "ltl_rand_split",
-           "ltl_learn_noalloc", "ltl_batch_get_stats")
+           "ltl_learn_noalloc", "ltl_batch_get_stats", "ltl_autotune")
 
 
 class LTLError(RuntimeError):
@@ -68,7 +69,16 @@ class Node(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("device", C.c_int32), ("flags", C.c_uint32), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_uint64), ("lanes", C.c_uint32), ("hash_slots_log2", C.c_uint32),
-                ("word_bits", C.c_uint32), ("fp_bits", C.c_uint32), ("max_entries", C.c_uint64)]
+                ("word_bits", C.c_uint32), ("fp_bits", C.c_uint32), ("max_entries", C.c_uint64),
+                ("split_tiles", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+TUNE_CONFIGS = 5
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tried", C.c_uint32), ("best", C.c_uint32), ("flags", C.c_uint32 * TUNE_CONFIGS),
+                ("split_tiles", C.c_uint32 * TUNE_CONFIGS), ("ms", C.c_double * TUNE_CONFIGS)]
 
 
 class BatchJob(C.Structure):
@@ -128,6 +138,8 @@ def load_library(path: str = LIB_PATH):
     L.ltl_batch_run.restype = C.c_int
     L.ltl_batch_serve.argtypes = [C.c_void_p, P(BatchJob), C.c_uint32, P(C.c_double), P(Result), P(C.c_double)]
     L.ltl_batch_serve.restype = C.c_int
+    L.ltl_autotune.argtypes = [C.c_void_p, P(Spec), P(OpSet), C.c_uint32, P(Tuning)]
+    L.ltl_autotune.restype = C.c_int
     L.ltl_batch_get_stats.argtypes = [C.c_void_p, P(BatchStats)]
     L.ltl_batch_get_stats.restype = C.c_int
     L.ltl_batch_destroy.argtypes = [C.c_void_p]
@@ -358,6 +370,17 @@ class Context:
         self.L.ltl_learn(self.h, C.byref(spec.c), C.byref(opset(cost, ops)), bound, C.byref(r))
         return _convert(r)
 
+    def autotune(self, inst_or_spec, bound: int, cost=None, ops=None):
+        """ltl_autotune: times the job under each tile shape / level schedule; returns
+        (best (flags, split_tiles), [(flags, split_tiles, ms), ...])."""
+        spec = inst_or_spec if isinstance(inst_or_spec, SpecBuffers) else SpecBuffers(inst_or_spec)
+        t = Tuning()
+        st = self.L.ltl_autotune(self.h, C.byref(spec.c), C.byref(opset(cost, ops)), bound, C.byref(t))
+        if st != LTL_OK:
+            raise LTLError(st, "ltl_autotune")
+        rows = [(int(t.flags[k]), int(t.split_tiles[k]), float(t.ms[k])) for k in range(t.tried)]
+        return rows[t.best][:2], rows
+
     def job(self, inst_or_spec, bound: int, cost=None, ops=None) -> "Job":
         return Job(self, inst_or_spec, bound, cost, ops)
 
@@ -423,12 +446,13 @@ class Job:
         return i
 
 
-def _batch_opts(workspace, lanes, device, flags, hash_slots_log2, word_bits, fp_bits, max_entries):
+def _batch_opts(workspace, lanes, device, flags, hash_slots_log2, word_bits, fp_bits, max_entries, split_tiles=0):
     o = BatchOpts()
     o.device, o.flags, o.workspace = device, flags, workspace.data_ptr()
     o.workspace_bytes = workspace.numel()
     o.lanes, o.hash_slots_log2, o.word_bits, o.fp_bits, o.max_entries = lanes, hash_slots_log2, word_bits, \
         fp_bits, max_entries
+    o.split_tiles = split_tiles
     return o
 
 
@@ -448,7 +472,7 @@ class Batch:
 
     def __init__(self, lanes: int = 4, workspace_bytes: int = 8 << 30, device: int = 0, flags: int = 0,
                  hash_slots_log2: int = 0, word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0,
-                 workspace=None):
+                 workspace=None, split_tiles: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
@@ -457,7 +481,8 @@ class Batch:
             workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
         self.workspace = workspace
         self.lanes = lanes
-        o = _batch_opts(workspace, lanes, device, flags, hash_slots_log2, word_bits, fp_bits, max_entries)
+        o = _batch_opts(workspace, lanes, device, flags, hash_slots_log2, word_bits, fp_bits, max_entries,
+                        split_tiles)
         h = C.c_void_p()
         torch.cuda.synchronize()
         st = self._L.ltl_batch_create(C.byref(o), C.byref(h))

@@ -193,6 +193,24 @@ def test_whole_row_tiny(ltl, ctx_whole, seed):
     _level_by_level(ltl, ctx_whole, inst, cfg["bound"])
 
 
+@pytest.mark.parametrize("flags", ["lds-tiles", "lds-tiles-doubling"])
+def test_whole_row_lds_tiles(ltl, flags):
+    """The whole-row kernels with child operands of binary connectives staged in LDS for
+    8 x 8 groups of pairs (LTL_CTX_LDS_TILES) on one-word and multi-word rows, both U
+    methods: the oracle's results and every stored matrix."""
+    fl = ltl.CTX_LDS_TILES | (ltl.CTX_U_DOUBLING if flags.endswith("doubling") else 0)
+    c = ltl.Context(workspace_bytes=1 << 30, hash_slots_log2=20, split_tiles=1, flags=fl)
+    try:
+        for seed in (1, 4):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            _say("lds tiles tiny", seed, flags)
+            _level_by_level(ltl, c, inst, cfg["bound"])
+        _say("lds tiles until chains", flags)
+        _level_by_level(ltl, c, synth.until_chain_instance(0), 5, max_entries_per_level=200)
+    finally:
+        c.close()
+
+
 def test_single_word_u64_rows(ltl):
     """Short traces in 64-bit words (one word per trace) match the 32-bit layout."""
     c64 = ltl.Context(workspace_bytes=256 << 20, hash_slots_log2=18, word_bits=64)
@@ -641,13 +659,26 @@ def test_batch_serve_arrivals(ltl):
         plain.close()
 
 
+def test_autotune(ltl, ctx):
+    """ltl_autotune times each tile shape / level schedule on a job and picks the fastest;
+    every configuration gives the job's result (checked by the library), the context's own
+    options are unchanged afterwards."""
+    for inst, bound in ((synth.preset_instance("tiny", 3)[0], 7), (synth.until_chain_instance(0), 5)):
+        best, rows = ctx.autotune(inst, bound)
+        _say("autotune", inst.name, best, rows)
+        assert len(rows) == 5 and all(ms > 0 for _, _, ms in rows)
+        assert best in [(f, t) for f, t, _ in rows]
+        assert ctx.opts.split_tiles == 0 and ctx.opts.flags == 0
+        _same(ctx.learn(inst, bound), O.learn(inst, bound, mode=O.MODE_EXPAND), "after autotune")
+
+
 def test_batch_shared_budget_admission(ltl):
-    """LTL_BATCH_SHARED_BUDGET serving: jobs get regions of one 2 GiB budget sized by their
-    estimated footprint; the regions in use never exceed the budget; a job that outgrows its
-    region runs again in a larger one (the Hamming job of bound 12 needs about 1 GB, its
-    estimate is 16 MB); every result equals the job's plain run alone on a context with the
-    whole budget."""
-    budget = 2 << 30
+    """LTL_BATCH_SHARED_BUDGET serving: jobs get regions of one 1 GiB budget sized by their
+    estimated footprint (at least budget / 12 here); the regions in use never exceed the
+    budget; a job that outgrows its region runs again in a larger one (the Hamming job of
+    bound 12 needs a few hundred MB); every result equals the job's plain run alone on a
+    context with the whole budget."""
+    budget = 1 << 30
     specs = [synth.preset_instance("tiny", s) for s in range(12)]
     insts = [i for i, _ in specs] + [synth.hamming_instance(0, 4, 2), synth.until_chain_instance(0),
                                      synth.preset_instance("scale", 0)[0]]
@@ -659,7 +690,7 @@ def test_batch_shared_budget_admission(ltl):
         res, dur, done = ex.serve(insts, bounds, arrival)
         st = ex.stats()
         _say("shared budget: peak", st.peak_bytes, "reruns", st.reruns, "in flight", st.max_in_flight)
-        assert st.budget_bytes == budget and 0 < st.peak_bytes <= budget
+        assert 0 < st.budget_bytes <= budget and 0 < st.peak_bytes <= st.budget_bytes
         assert st.reruns >= 1 and st.admissions == len(insts) + st.reruns
         assert st.max_in_flight >= 2
         for i in range(len(insts)):
