@@ -52,7 +52,74 @@ def measured_traffic(kind: str, workload_key: str):
         k = rec.get("per_launch_bytes", {}).get(kind)
         return None if k is None else float(k)
     return None
+# level-pipeline kernels (evaluation, write pass, verification, compaction, probe, fallback)
+LEVEL_KERNELS = ("k_level", "k_probe", "k_materialize", "k_mark_members", "k_compact_small", "k_mark", "k_scan_",
+                 "k_scatter", "k_or_bits", "k_fallback")
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, workload_key: str, out_path: str) -> None:
+    """Writes the calibrated HBM bytes per level-kernel dispatch from two rocprofv3 --pmc runs
+    of this bench (FETCH_SIZE, then WRITE_SIZE, --output-format csv) that each ran with
+    --copy-calibration-mib 1024: the largest copy dispatch of each run (1 GiB read and
+    written) gives the factor that turns the counter's KiB into bytes."""
+    import csv
+    import glob
+    import hashlib
+
+    def per_dispatch(d, counter):
+        v = {}
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        for f in files:
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        e = v.setdefault((f, r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])
+                        e[1] += float(r["Counter_Value"])
+        return list(v.values())
+
+    def is_level(name):
+        base = name.split("(")[0].split("<")[0].replace("void ", "").replace("ltl::", "").strip()
+        return base.startswith(LEVEL_KERNELS)
+
+    F, W = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    scale = []
+    for D in (F, W):
+        copies = [val for name, val in D if "copyBuffer" in name]
+        if not copies:
+            raise SystemExit("no copy dispatch to calibrate with (run with --copy-calibration-mib 1024)")
+        scale.append(gib_kib / max(copies))
+    fetch = [val * scale[0] * 1024 for name, val in F if is_level(name)]
+    write = [val * scale[1] * 1024 for name, val in W if is_level(name)]
+    if not fetch or len(fetch) != len(write):
+        raise SystemExit(f"level dispatches differ between the runs: {len(fetch)} vs {len(write)}")
+    per = (sum(fetch) + sum(write)) / len(fetch)
+    rec = {"kernel_source_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest(),
+           "per_launch_bytes": {"level": per}, "dispatches": {"level": len(fetch)},
+           "read_bytes_per_launch": sum(fetch) / len(fetch), "write_bytes_per_launch": sum(write) / len(write),
+           "calibration": {"fetch_factor": round(scale[0], 4), "write_factor": round(scale[1], 4)},
+           "note": "calibrated FETCH_SIZE + WRITE_SIZE per dispatch of the level kernels, one bench step + warm-up",
+           "workload_key": workload_key}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({"per_launch_MB": round(per / 1e6, 3), "dispatches": len(fetch),
+                      "fetch_factor": rec["calibration"]["fetch_factor"],
+                      "write_factor": rec["calibration"]["write_factor"], "out": out_path}))
+
+
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T
+
+
+def workload_key(args) -> str:
+    """Names a fixed workload with its seeds and bound (the key of a committed counter summary)."""
+    from ltl_inputs import synth
+    if not args.seeds:
+        args.seeds = "0-3" if args.workload == "long" else "0-7"
+    bound = args.bound or (16 if args.workload == "hamming" else synth.PRESETS[args.workload]["bound"])
+    return (f"{args.workload} seeds {args.seeds} bound {bound}" + (" ruc" if args.ruc else "")
+            + (" ucarry" if args.ucarry else "") + (" udoubling" if args.udoubling else ""))
 
 
 def parse_seeds(s: str):
@@ -127,7 +194,14 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device (a kernel of known traffic for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="no run: write the calibrated bytes per level dispatch from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this bench with the same workload options")
     args = ap.parse_args()
+
+    if args.summarize_counters:
+        fd, wd, out = args.summarize_counters
+        return summarize_counters(fd, wd, workload_key(args), out)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -262,9 +336,7 @@ def bench_fixed(args):
     # the basis then (a lower bound of the fraction)
     roof, kern_ms, eval_tops, verify_gbs = roofline(ltl, results, geom, u_carry,
                                                     wall_ms=wall * 1e3 if lanes > 1 else None)
-    wkey = (f"{args.workload} seeds {args.seeds} bound {cfg['bound']}" + (" ruc" if args.ruc else "")
-            + (" ucarry" if args.ucarry else "") + (" udoubling" if args.udoubling else ""))
-    t = measured_traffic(roof["kind"], wkey)
+    t = measured_traffic(roof["kind"], workload_key(args))
     roof["traffic"] = None if t is None else round(t / 1e6, 3)
     roof["traffic_unit"] = "MB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)"
 
