@@ -16,7 +16,11 @@
  *     exact one: a candidate is cached iff its whole characteristic matrix is
  *     not yet in the language cache (the exhaustive case of Sec. 5);
  *   - the separation predicate (dagger) of Sec. 4: every positive trace
- *     satisfies phi at position 0 and no negative trace does.
+ *     satisfies phi at position 0 and no negative trace does;
+ *   - optionally the relaxed uniqueness check of Sec. 5 itself: a candidate is
+ *     cached iff its 126-bit key is new, the key being the matrix itself when it
+ *     has at most 126 bits, else a keyed hash of it (our stand-in for the hash the
+ *     paper names) or the first-k-percent map (FKP) of Sec. 7 (oracle_run_relaxed).
  *
  * Two evaluation modes for the temporal operators, cross-checked by tests:
  *   MODE_QUANT  : the clauses literally (O(n^2) per trace for F, G, U);
@@ -236,6 +240,7 @@ typedef struct {
     uint64_t *h;         /* stored hash per slot (0 = empty) */
     int32_t *lev;
     int64_t *idx;
+    uint64_t *key;       /* relaxed mode: the entry's 126-bit key (2 words per slot) */
     int64_t cap, n;
 } o_map;
 
@@ -252,6 +257,11 @@ struct o_run {
     double *secs;        /* per level wall time */
     int64_t first;       /* canonical index of first solution (-1 none) */
     o_recipe sol;        /* the solution candidate */
+    int ruc;             /* RUC_NONE (exact), RUC_HASH, RUC_FKP */
+    uint64_t ruc_seed;   /* RUC_HASH: SplitMix64 seed of the per-chunk keys */
+    int ruc_bits;        /* keep the first ruc_bits bits of each key (1..125); 0 = all 126 */
+    int64_t *ruc_m;      /* per trace: positions that enter the packed key (pack form) */
+    int ruc_pack;        /* key = packed prefix bits (FKP, or any matrix of <= 126 bits) */
 };
 typedef struct o_run o_run;
 
@@ -260,6 +270,130 @@ static uint64_t fnv1a(const uint8_t *p, int64_t n) {
     uint64_t h = 1469598103934665603ull;
     for (int64_t i = 0; i < n; ++i) { h ^= p[i]; h *= 1099511628211ull; }
     return h ? h : 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relaxed uniqueness check (Sec. 5): 126-bit keys.                          */
+/*                                                                           */
+/* The key is a string of 126 bits, held in two words (bit 0 of the string = */
+/* the top bit of the first word; the last two bits of the second word are   */
+/* zero).                                                                    */
+/*  - Pack form: the characteristic sequences' first m_t positions, trace by  */
+/*    trace in the order P then N, cut after 126 bits and padded with zeros.  */
+/*    A matrix of at most 126 bits is its own key (m_t = |tr_t|): the check   */
+/*    is then exact.  FKP (Sec. 7) keeps the first k percent of each sequence */
+/*    (m_t = |tr_t| k / 100 rounded half up), k in 1..100 the smallest whose  */
+/*    total is nearest to 126 bits.                                          */
+/*  - Hash form (RUC_HASH on a matrix of more than 126 bits): two keyed sums  */
+/*    over 32-position chunks, chunk j of trace t holding positions          */
+/*    32j .. 32j+31 (position 32j in the top bit, zeros past the end):        */
+/*        A = sum premix(v, a) * a,  B = sum premix(v, b) * b   (mod 2^64)    */
+/*    with premix(v, k) = y ^ (y >> 16), y = (v ^ (v >> 8)) + k (mod 2^32),   */
+/*    and the odd 32-bit keys a, b = top halves of draws 2i and 2i + 1 of the */
+/*    SplitMix64 sequence (Steele, Lea, Flood, OOPSLA 2014) of the seed, with */
+/*    i = t * 2^32 + j, low bit set.  The string is A's top 63 bits, then B's. */
+/* ------------------------------------------------------------------------ */
+enum { RUC_NONE = 0, RUC_HASH = 1, RUC_FKP = 2 };
+#define RUC_KEY_BITS 126
+
+static uint64_t splitmix64_draw(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static uint32_t ruc_premix(uint32_t v, uint32_t k) {
+    uint32_t y = (v ^ (v >> 8)) + k;
+    return y ^ (y >> 16);
+}
+
+/* FKP's k for the traces of s (0 if the whole matrix fits 126 bits); fills m[t]. */
+static int ruc_prefixes(const o_spec *s, int kind, int64_t *m) {
+    int T = s->num_pos + s->num_neg;
+    if (total_positions(s) <= RUC_KEY_BITS || kind != RUC_FKP) {
+        for (int t = 0; t < T; ++t) m[t] = trace_len(s, t);
+        return 0;
+    }
+    int best = 1;
+    int64_t best_d = -1;
+    for (int k = 1; k <= 100; ++k) {
+        int64_t tot = 0;
+        for (int t = 0; t < T; ++t) tot += (trace_len(s, t) * k + 50) / 100;
+        int64_t d = tot > RUC_KEY_BITS ? tot - RUC_KEY_BITS : RUC_KEY_BITS - tot;
+        if (best_d < 0 || d < best_d) { best_d = d; best = k; }
+    }
+    for (int t = 0; t < T; ++t) m[t] = (trace_len(s, t) * best + 50) / 100;
+    return best;
+}
+
+static void ruc_key_of(const o_spec *s, int pack, const int64_t *m, uint64_t seed, int bits, const uint8_t *cm,
+                       uint64_t key[2]) {
+    int T = s->num_pos + s->num_neg;
+    uint64_t k0 = 0, k1 = 0;
+    if (pack) {
+        int64_t q = 0;
+        for (int t = 0; t < T && q < RUC_KEY_BITS; ++t) {
+            const uint8_t *row = cm + s->offsets[t];
+            for (int64_t i = 0; i < m[t] && q < RUC_KEY_BITS; ++i, ++q) {
+                if (!row[i]) continue;
+                if (q < 64) k0 |= 1ull << (63 - q);
+                else k1 |= 1ull << (63 - (q - 64));
+            }
+        }
+    } else {
+        uint64_t A = 0, B = 0;
+        for (int t = 0; t < T; ++t) {
+            const uint8_t *row = cm + s->offsets[t];
+            int64_t n = trace_len(s, t);
+            for (int64_t j = 0; 32 * j < n; ++j) {
+                uint32_t v = 0;
+                for (int i = 0; i < 32 && 32 * j + i < n; ++i)
+                    if (row[32 * j + i]) v |= 1u << (31 - i);
+                uint64_t ci = ((uint64_t)t << 32) | (uint64_t)j;
+                uint32_t a = (uint32_t)(splitmix64_draw(seed, 2 * ci) >> 32) | 1u;
+                uint32_t b = (uint32_t)(splitmix64_draw(seed, 2 * ci + 1) >> 32) | 1u;
+                A += (uint64_t)ruc_premix(v, a) * a;
+                B += (uint64_t)ruc_premix(v, b) * b;
+            }
+        }
+        k0 = (A & ~1ull) | (B >> 63);
+        k1 = (B << 1) & ~3ull;
+    }
+    if (bits > 0 && bits < RUC_KEY_BITS) {
+        if (bits <= 64) { k0 &= bits == 64 ? ~0ull : ~(~0ull >> bits); k1 = 0; }
+        else k1 &= ~(~0ull >> (bits - 64));
+    }
+    key[0] = k0;
+    key[1] = k1;
+}
+
+/* Test hooks: the key of one matrix, and FKP's k. */
+int oracle_ruc_key(const o_spec *s, const uint8_t *cm, int kind, uint64_t seed, int bits, uint64_t *out) {
+    if (!s || !cm || !out || (kind != RUC_HASH && kind != RUC_FKP)) return -1;
+    int T = s->num_pos + s->num_neg;
+    int64_t *m = (int64_t *)malloc((size_t)(T > 0 ? T : 1) * sizeof(int64_t));
+    if (!m) return -1;
+    ruc_prefixes(s, kind, m);
+    int pack = kind == RUC_FKP || total_positions(s) <= RUC_KEY_BITS;
+    ruc_key_of(s, pack, m, seed, bits, cm, out);
+    free(m);
+    return 0;
+}
+
+int oracle_fkp_k(const o_spec *s, int64_t *m_out) {
+    if (!s) return -1;
+    int T = s->num_pos + s->num_neg;
+    int64_t *m = (int64_t *)malloc((size_t)(T > 0 ? T : 1) * sizeof(int64_t));
+    if (!m) return -1;
+    int k = ruc_prefixes(s, RUC_FKP, m);
+    if (m_out) memcpy(m_out, m, (size_t)T * sizeof(int64_t));
+    free(m);
+    return k;
+}
+
+static uint64_t key_hash(const uint64_t key[2]) {
+    return fnv1a((const uint8_t *)key, 16);
 }
 
 static void pack_bits(const uint8_t *cm, int64_t tb, uint8_t *dst, int64_t pbytes) {
@@ -281,37 +415,45 @@ static int map_grow(o_run *r) {
     uint64_t *h = (uint64_t *)calloc((size_t)ncap, sizeof(uint64_t));
     int32_t *lev = (int32_t *)malloc((size_t)ncap * sizeof(int32_t));
     int64_t *idx = (int64_t *)malloc((size_t)ncap * sizeof(int64_t));
-    if (!h || !lev || !idx) { free(h); free(lev); free(idx); return -1; }
+    uint64_t *key = (uint64_t *)malloc((size_t)ncap * 2 * sizeof(uint64_t));
+    if (!h || !lev || !idx || !key) { free(h); free(lev); free(idx); free(key); return -1; }
     for (int64_t k = 0; k < m->cap; ++k) {
         if (!m->h[k]) continue;
         int64_t pos = (int64_t)(m->h[k] & (uint64_t)(ncap - 1));
         while (h[pos]) pos = (pos + 1) & (ncap - 1);
         h[pos] = m->h[k]; lev[pos] = m->lev[k]; idx[pos] = m->idx[k];
+        key[2 * pos] = m->key[2 * k]; key[2 * pos + 1] = m->key[2 * k + 1];
     }
-    free(m->h); free(m->lev); free(m->idx);
-    m->h = h; m->lev = lev; m->idx = idx; m->cap = ncap;
+    free(m->h); free(m->lev); free(m->idx); free(m->key);
+    m->h = h; m->lev = lev; m->idx = idx; m->key = key; m->cap = ncap;
     return 0;
 }
 
-/* Returns 1 if `bits` (hash hv) is already cached, else 0. */
-static int map_contains(o_run *r, const uint8_t *bits, uint64_t hv) {
+/* Returns 1 if the language is already cached, else 0: exact mode compares the
+ * matrices `bits`, relaxed mode the 126-bit keys `key` (hash hv of either). */
+static int map_contains(o_run *r, const uint8_t *bits, const uint64_t *key, uint64_t hv) {
     o_map *m = &r->map;
     if (!m->cap) return 0;
     int64_t pos = (int64_t)(hv & (uint64_t)(m->cap - 1));
     while (m->h[pos]) {
-        if (m->h[pos] == hv && memcmp(entry_bits(r, m->lev[pos], m->idx[pos]), bits, (size_t)r->pbytes) == 0)
-            return 1;
+        if (m->h[pos] == hv) {
+            if (r->ruc ? (m->key[2 * pos] == key[0] && m->key[2 * pos + 1] == key[1])
+                       : memcmp(entry_bits(r, m->lev[pos], m->idx[pos]), bits, (size_t)r->pbytes) == 0)
+                return 1;
+        }
         pos = (pos + 1) & (m->cap - 1);
     }
     return 0;
 }
 
-static int map_insert(o_run *r, uint64_t hv, int lev, int64_t idx) {
+static int map_insert(o_run *r, uint64_t hv, const uint64_t *key, int lev, int64_t idx) {
     o_map *m = &r->map;
     if ((m->n + 1) * 2 > m->cap && map_grow(r)) return -1;
     int64_t pos = (int64_t)(hv & (uint64_t)(m->cap - 1));
     while (m->h[pos]) pos = (pos + 1) & (m->cap - 1);
-    m->h[pos] = hv; m->lev[pos] = lev; m->idx[pos] = idx; m->n++;
+    m->h[pos] = hv; m->lev[pos] = lev; m->idx[pos] = idx;
+    m->key[2 * pos] = key ? key[0] : 0; m->key[2 * pos + 1] = key ? key[1] : 0;
+    m->n++;
     return 0;
 }
 
@@ -347,6 +489,7 @@ typedef struct {
     uint8_t *ca, *cb;   /* per-thread child scratch: threads * tb */
     uint8_t *pk;        /* n * pbytes */
     uint64_t *hv;
+    uint64_t *key;      /* relaxed mode: n * 2 words */
     uint8_t *sep;
     int64_t next_index; /* canonical index of rc[0] */
     int64_t first;      /* -1 none */
@@ -375,15 +518,22 @@ static void batch_flush(o_batch *B) {
         cm_apply(&r->spec, rc.op, ca, rc.lb >= 0 ? cb : NULL, r->mode, out);
         B->sep[k] = (uint8_t)separates(&r->spec, out);
         pack_bits(out, tb, B->pk + (size_t)k * r->pbytes, r->pbytes);
-        B->hv[k] = fnv1a(B->pk + (size_t)k * r->pbytes, r->pbytes);
+        if (r->ruc) {
+            ruc_key_of(&r->spec, r->ruc_pack, r->ruc_m, r->ruc_seed, r->ruc_bits, out, B->key + 2 * k);
+            B->hv[k] = key_hash(B->key + 2 * k);
+        } else {
+            B->hv[k] = fnv1a(B->pk + (size_t)k * r->pbytes, r->pbytes);
+        }
     }
     /* sequential merge in canonical order */
     for (int64_t k = 0; k < n && !B->err; ++k) {
         int64_t ci = B->next_index + k;
         if (B->sep[k] && B->first < 0) { B->first = ci; r->sol = B->rc[k]; }
         const uint8_t *pk = B->pk + (size_t)k * r->pbytes;
-        if (!map_contains(r, pk, B->hv[k])) {
-            if (level_push(r, B->level, pk, B->rc[k]) || map_insert(r, B->hv[k], B->level, r->L[B->level].n - 1))
+        const uint64_t *key = B->key + 2 * k;
+        if (!map_contains(r, pk, key, B->hv[k])) {
+            if (level_push(r, B->level, pk, B->rc[k]) ||
+                map_insert(r, B->hv[k], key, B->level, r->L[B->level].n - 1))
                 B->err = 1;
         }
     }
@@ -454,12 +604,17 @@ static double now_s(void) {
  * stored entries (0 = none); a level must be stored iff it has no solution and
  * it is below the bound; if storing it would exceed the cap, the run stops with
  * ST_EOOM at that level (its counts are still reported).
+ * ruc: RUC_NONE for the exact check, else the relaxed check of Sec. 5 with the
+ * key form RUC_HASH (seed ruc_seed) or RUC_FKP; ruc_bits > 0 keeps only the
+ * first ruc_bits bits of every key.  The entry kept for a key is the
+ * canonical-first candidate that has it; new-language counts count new keys.
  */
-o_run *oracle_run(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bound, int mode,
-                  int threads, int64_t max_entries) {
+o_run *oracle_run_relaxed(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bound, int mode,
+                          int threads, int64_t max_entries, int ruc, uint64_t ruc_seed, int ruc_bits) {
     o_run *r = (o_run *)calloc(1, sizeof(o_run));
     if (!r) return NULL;
     r->spec = *s;
+    r->ruc = ruc; r->ruc_seed = ruc_seed; r->ruc_bits = ruc_bits;
     memcpy(r->cost, cost, sizeof(r->cost));
     r->op_mask = op_mask; r->bound = bound; r->mode = mode;
     r->threads = threads > 0 ? threads : 1;
@@ -479,8 +634,15 @@ o_run *oracle_run(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bo
             if (!memcmp(s->letters + s->offsets[i], s->letters + s->offsets[j],
                         (size_t)trace_len(s, i) * sizeof(uint32_t))) { r->status = ST_EINCONS; return r; }
         }
+    if (ruc < RUC_NONE || ruc > RUC_FKP || ruc_bits < 0) return r;
     r->tb = total_positions(s);
     r->pbytes = (r->tb + 7) / 8;
+    if (ruc) {
+        r->ruc_m = (int64_t *)malloc((size_t)T * sizeof(int64_t));
+        if (!r->ruc_m) return r;
+        ruc_prefixes(s, ruc, r->ruc_m);
+        r->ruc_pack = ruc == RUC_FKP || r->tb <= RUC_KEY_BITS;
+    }
     r->L = (o_level *)calloc((size_t)bound + 1, sizeof(o_level));
     r->E = (int64_t *)calloc((size_t)bound + 1, sizeof(int64_t));
     r->C = (int64_t *)calloc((size_t)bound + 1, sizeof(int64_t));
@@ -500,11 +662,13 @@ o_run *oracle_run(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bo
     B.cb = (uint8_t *)malloc((size_t)r->threads * (size_t)r->tb);
     B.pk = (uint8_t *)malloc((size_t)cap * (size_t)r->pbytes);
     B.hv = (uint64_t *)malloc((size_t)cap * sizeof(uint64_t));
+    B.key = (uint64_t *)calloc((size_t)cap * 2, sizeof(uint64_t));
     B.sep = (uint8_t *)malloc((size_t)cap);
     uint8_t *tmp = (uint8_t *)malloc((size_t)r->tb);
     uint8_t *pk = (uint8_t *)malloc((size_t)r->pbytes);
     int64_t stored = 0;
-    if (!B.rc || !B.cm || !B.ca || !B.cb || !B.pk || !B.hv || !B.sep || !tmp || !pk) goto fail;
+    uint64_t akey[2] = {0, 0};
+    if (!B.rc || !B.cm || !B.ca || !B.cb || !B.pk || !B.hv || !B.key || !B.sep || !tmp || !pk) goto fail;
 
     /* Atom level (Sec. 3 listing: atom check, then the cache starts with the atoms). */
     {
@@ -518,10 +682,16 @@ o_run *oracle_run(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bo
                 r->sol.op = O_ATOM; r->sol.la = -1; r->sol.lb = -1; r->sol.ia = p; r->sol.ib = 0;
             }
             pack_bits(tmp, r->tb, pk, r->pbytes);
-            uint64_t hv = fnv1a(pk, r->pbytes);
-            if (!map_contains(r, pk, hv)) {
+            uint64_t hv;
+            if (r->ruc) {
+                ruc_key_of(s, r->ruc_pack, r->ruc_m, r->ruc_seed, r->ruc_bits, tmp, akey);
+                hv = key_hash(akey);
+            } else {
+                hv = fnv1a(pk, r->pbytes);
+            }
+            if (!map_contains(r, pk, akey, hv)) {
                 o_recipe rc = { O_ATOM, -1, -1, p, 0 };
-                if (level_push(r, c0, pk, rc) || map_insert(r, hv, c0, r->L[c0].n - 1)) goto fail;
+                if (level_push(r, c0, pk, rc) || map_insert(r, hv, akey, c0, r->L[c0].n - 1)) goto fail;
             }
         }
         r->C[c0] = s->num_props;
@@ -547,16 +717,21 @@ o_run *oracle_run(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bo
 fail:
     r->status = ST_EOOM;
 done:
-    free(B.rc); free(B.cm); free(B.ca); free(B.cb); free(B.pk); free(B.hv); free(B.sep);
+    free(B.rc); free(B.cm); free(B.ca); free(B.cb); free(B.pk); free(B.hv); free(B.key); free(B.sep);
     free(tmp); free(pk);
     return r;
+}
+
+o_run *oracle_run(const o_spec *s, const int32_t *cost, uint32_t op_mask, int bound, int mode,
+                  int threads, int64_t max_entries) {
+    return oracle_run_relaxed(s, cost, op_mask, bound, mode, threads, max_entries, RUC_NONE, 0, 0);
 }
 
 void oracle_free(o_run *r) {
     if (!r) return;
     if (r->L) for (int c = 0; c <= r->bound; ++c) { free(r->L[c].bits); free(r->L[c].rec); }
     free(r->L); free(r->E); free(r->C); free(r->secs);
-    free(r->map.h); free(r->map.lev); free(r->map.idx);
+    free(r->map.h); free(r->map.lev); free(r->map.idx); free(r->map.key); free(r->ruc_m);
     free(r);
 }
 

@@ -20,6 +20,7 @@ LIB = os.environ.get("LTL_ORACLE_LIB") or os.path.join(HERE, "libltl_oracle.so")
 
 ATOM, NOT, AND, OR, X, F, G, U = range(8)
 MODE_QUANT, MODE_EXPAND = 0, 1
+RUC_NONE, RUC_HASH, RUC_FKP = 0, 1, 2          # exact check; relaxed check of Sec. 5 (hash / FKP keys)
 ST_OK, ST_NOT_FOUND, ST_EINVAL, ST_EINCONS, ST_EOOM = 0, 1, -1, -2, -4
 
 
@@ -61,6 +62,13 @@ def lib():
         L.oracle_run.argtypes = [C.POINTER(_Spec), C.POINTER(C.c_int32), C.c_uint32, C.c_int, C.c_int,
                                  C.c_int, C.c_int64]
         L.oracle_run.restype = C.c_void_p
+        L.oracle_run_relaxed.argtypes = [C.POINTER(_Spec), C.POINTER(C.c_int32), C.c_uint32, C.c_int, C.c_int,
+                                         C.c_int, C.c_int64, C.c_int, C.c_uint64, C.c_int]
+        L.oracle_run_relaxed.restype = C.c_void_p
+        L.oracle_ruc_key.argtypes = [C.POINTER(_Spec), C.c_void_p, C.c_int, C.c_uint64, C.c_int, C.c_void_p]
+        L.oracle_ruc_key.restype = C.c_int
+        L.oracle_fkp_k.argtypes = [C.POINTER(_Spec), C.c_void_p]
+        L.oracle_fkp_k.restype = C.c_int
         L.oracle_free.argtypes = [C.c_void_p]
         for name, rt in [("oracle_status", C.c_int), ("oracle_found_cost", C.c_int),
                          ("oracle_levels_done", C.c_int), ("oracle_first_index", C.c_int64)]:
@@ -147,11 +155,12 @@ class Result:
 
 class Run:
     def __init__(self, spec: Spec, bound: int, cost=UNIT_COST, op_mask: int = ALL_OPS, mode: int = MODE_QUANT,
-                 threads: int = 1, max_entries: int = 0):
+                 threads: int = 1, max_entries: int = 0, ruc: int = RUC_NONE, ruc_seed: int = 0, ruc_bits: int = 0):
         self.spec = spec
         self.bound = bound
         c = (C.c_int32 * 8)(*cost)
-        self.h = lib().oracle_run(C.byref(spec.c), c, op_mask, bound, mode, threads, max_entries)
+        self.h = lib().oracle_run_relaxed(C.byref(spec.c), c, op_mask, bound, mode, threads, max_entries,
+                                          ruc, ruc_seed, ruc_bits)
         assert self.h
 
     def __del__(self):
@@ -423,10 +432,27 @@ def rand_split(pos, neg, num_props: int, win: int, seed: int = 0, cost=UNIT_COST
 
 
 def learn(inst, bound: int, cost=UNIT_COST, op_mask: int = ALL_OPS, mode: int = MODE_QUANT, threads: int = 1,
-          max_entries: int = 0) -> Result:
+          max_entries: int = 0, ruc: int = RUC_NONE, ruc_seed: int = 0, ruc_bits: int = 0) -> Result:
     spec = Spec.of(inst)
-    run = Run(spec, bound, cost, op_mask, mode, threads, max_entries)
+    run = Run(spec, bound, cost, op_mask, mode, threads, max_entries, ruc, ruc_seed, ruc_bits)
     return run.result()
+
+
+def ruc_key(spec: Spec, cm: np.ndarray, kind: int, seed: int = 0, bits: int = 0) -> int:
+    """The 126-bit key of the relaxed check (Sec. 5) of one matrix (one byte per
+    position, trace-major), as an integer whose bit 125 is the key's first bit."""
+    cm = np.ascontiguousarray(cm, dtype=np.uint8)
+    out = (C.c_uint64 * 2)()
+    assert lib().oracle_ruc_key(C.byref(spec.c), cm.ctypes.data, kind, seed, bits, out) == 0
+    return (out[0] << 62) | (out[1] >> 2)
+
+
+def fkp_prefixes(spec: Spec):
+    """FKP (Sec. 7): (k, positions kept per trace); k = 0 when the whole matrix fits 126 bits."""
+    m = np.zeros(spec.num_pos + spec.num_neg, dtype=np.int64)
+    k = lib().oracle_fkp_k(C.byref(spec.c), m.ctypes.data)
+    assert k >= 0
+    return k, [int(x) for x in m]
 
 
 if __name__ == "__main__":
