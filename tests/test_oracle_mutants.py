@@ -25,7 +25,7 @@ MUTANTS = {
                  "for (int64_t j = i + 1; j < len; ++j) if (A[j]) { v = 1; break; }"),
     "U_inclusive": ("for (int64_t m = i; m < j; ++m) if (!A[m]) { ok = 0; break; }",
                     "for (int64_t m = i; m <= j; ++m) if (!A[m]) { ok = 0; break; }"),
-    "no_dedup": ("if (!map_contains(r, pk, B->hv[k])) {", "if (1) {"),
+    "no_dedup": ("if (!map_contains(r, pk, key, B->hv[k])) {", "if (1) {"),
     "swapped_classes": ("if (t < s->num_pos ? !v : v) return 0;", "if (t < s->num_pos ? v : !v) return 0;"),
     "U_expand_no_phi": ("nxt = B[i] || (A[i] && nxt);", "nxt = B[i] || nxt;"),
     "nnf_ignored": ("if (op == O_NOT && (r->op_mask & O_NNF) && x != r->cost[O_ATOM]) continue;", ";"),
