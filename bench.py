@@ -119,6 +119,7 @@ def workload_key(args) -> str:
         args.seeds = "0-3" if args.workload == "long" else "0-7"
     bound = args.bound or (16 if args.workload == "hamming" else synth.PRESETS[args.workload]["bound"])
     return (f"{args.workload} seeds {args.seeds} bound {bound}" + (" ruc" if args.ruc else "")
+            + (" fkp" if args.ruc and args.fkp else "")
             + (" ucarry" if args.ucarry else "") + (" udoubling" if args.udoubling else ""))
 
 
@@ -176,7 +177,9 @@ def main():
                     help="levels of fewer tiles run the row-split kernels (ltl_ctx_opts.split_tiles; "
                          "0 = the library default, 1 = whole-row kernels at every level)")
     ap.add_argument("--ruc", action="store_true",
-                    help="relaxed uniqueness check (LTL_CTX_RUC): fingerprint match taken as equality, no compare")
+                    help="relaxed uniqueness check (LTL_CTX_RUC, Sec. 5): a candidate is cached iff its 126-bit key "
+                         "is new, no matrix compare")
+    ap.add_argument("--fkp", action="store_true", help="with --ruc: first-k-percent keys (LTL_CTX_RUC_FKP, Sec. 7)")
     ap.add_argument("--big-alone", action="store_true",
                     help="batch lanes take turns for whole-row levels (LTL_BATCH_BIG_ALONE)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -269,7 +272,8 @@ def bench_fixed(args):
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     slots = 26 if args.workload != "tiny" else 20
     ucarry = (ltl.CTX_U_CARRY if args.ucarry else 0) | (ltl.CTX_U_DOUBLING if args.udoubling else 0) | \
-        (ltl.CTX_RUC if args.ruc else 0) | (ltl.CTX_LDS_TILES if args.lds_tiles else 0)
+        (ltl.CTX_RUC if args.ruc else 0) | (ltl.CTX_RUC_FKP if args.ruc and args.fkp else 0) | \
+        (ltl.CTX_LDS_TILES if args.lds_tiles else 0)
     # timed steps: one event pair per level (level GPU time, for the roofline); the one-stream
     # pass: events around every kernel group (time per kernel kind)
     timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
@@ -404,7 +408,8 @@ def bench_fixed(args):
                    "jobs_per_step": len(dev), "lanes": lanes, "hash_slots_log2": slots,
                    "u_operator": ("carry adder" if u_carry else "doubling (App. B)")
                    + ("" if args.ucarry or args.udoubling else " (chosen by row layout)"),
-                   "dedup": "relaxed (fingerprint only)" if args.ruc else "exact (fingerprint + full compare)",
+                   "dedup": ("relaxed (126-bit FKP keys, Sec. 7)" if args.fkp else "relaxed (126-bit keyed sums)")
+                   if args.ruc else "exact (fingerprint + full compare)",
                    "binary_tiles": "LDS-staged 8 x 8 groups" if args.lds_tiles else "register 4 x 4"},
         "trace_bits_per_s": round(value * tb_mean, 1),
         "jobs_per_s": round(len(results) / wall, 3),

@@ -86,13 +86,28 @@ typedef struct ltl_job ltl_job;
                                     around each kernel group)                                  */
 #define LTL_CTX_TIMING_LEVEL 0x4u /* record only the GPU time of each level: one event pair from
                                     its first to its last kernel (level_ms; kernel_ms stays 0) */
-#define LTL_CTX_RUC       0x8u   /* relaxed uniqueness check (Sec. 5): a candidate whose 64-bit
-                                    fingerprint is already cached is taken as that language
-                                    without the full compare (no verification pass, no exact
-                                    re-check).  Results equal the default exact mode unless two
-                                    distinct matrices share a fingerprint; then a language can
-                                    be dropped (the formula may not be minimal) and level counts
-                                    are counts of distinct fingerprints                         */
+#define LTL_CTX_RUC       0x8u   /* relaxed uniqueness check (Sec. 5): a candidate is cached iff
+                                    its 126-bit key is new; matrices are never compared (no
+                                    verification pass).  The key of a matrix of at most 126 bits
+                                    is the matrix itself (trace by trace, P then N), so the check
+                                    is exact there.  A larger matrix is hashed: two keyed sums
+                                    over its 32-position chunks (chunk j of trace t: positions
+                                    32j..32j+31, first position in the top bit),
+                                        A = sum premix(v, a) * a,  B = sum premix(v, b) * b
+                                    (mod 2^64), premix(v, k) = y ^ (y >> 16) with
+                                    y = (v ^ (v >> 8)) + k (mod 2^32); a and b are the top halves,
+                                    low bit set, of draws 2i and 2i + 1 of the SplitMix64
+                                    sequence of ltl_ctx_opts.ruc_seed, i = t * 2^32 + j; the key
+                                    is the top 63 bits of A, then of B.  False positives drop
+                                    languages (the formula found separates but may cost more
+                                    than the minimum); level counts count new keys.  The entry
+                                    kept for a key is its canonical-first candidate.  Levels run
+                                    the whole-row kernels                                        */
+#define LTL_CTX_RUC_FKP   0x40u  /* with LTL_CTX_RUC: keys by first-k-percent (Sec. 7) instead
+                                    of hashing: the first m_t = round(k |tr_t| / 100) positions
+                                    (halves rounded up) of each trace, concatenated in trace
+                                    order and cut after 126 bits, k in 1..100 the smallest whose
+                                    total is nearest to 126 bits                                 */
 
 typedef struct {
     int32_t  device;            /* HIP device ordinal used by every call of this context        */
@@ -114,6 +129,10 @@ typedef struct {
                                    every level; results do not depend on it                     */
     uint64_t max_entries;       /* cap on stored language-cache entries; 0 = derived from the
                                    hash table (half its slots)                                  */
+    uint64_t ruc_seed;          /* LTL_CTX_RUC: seed of the keyed sums' keys                    */
+    uint32_t ruc_key_bits;      /* LTL_CTX_RUC, debug: keep only the first ruc_key_bits bits
+                                   (1..125) of every key, forcing false positives; 0 = 126      */
+    uint32_t reserved;          /* 0                                                            */
 } ltl_ctx_opts;
 
 /* Create a context on opts->device.  Returns LTL_E_INVAL for a null/unaligned

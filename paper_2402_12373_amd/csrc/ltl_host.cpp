@@ -134,6 +134,9 @@ struct ltl_job {
     void *valid = nullptr, *sepm = nullptr, *sepw = nullptr, *atoms = nullptr;
     uint64_t *nxt = nullptr, *tfp = nullptr, *offsets_d = nullptr;
     uint32_t *key = nullptr;
+    uint32_t *ruc_meta = nullptr;            // relaxed check: key metadata per row half
+    unsigned long long *entry_key = nullptr; // relaxed check: key per global entry
+    bool ruc_pack = false;                   // keys in pack form (FKP, or matrices of <= 126 bits)
     uint32_t *row_trace = nullptr, *row_word = nullptr, *letters_d = nullptr;
     Block *blocks_d = nullptr;       // canonical order (candidate decode)
     Block *blocks_cls_d = nullptr;   // grouped by connective class, class-local tiles
@@ -308,7 +311,7 @@ static Rows<T> make_rows(const ltl_job *j) {
 extern "C" int ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out) {
     if (!opts || !out || !opts->workspace || opts->workspace_bytes < LTL_MIN_WORKSPACE) return LTL_E_INVAL;
     if (((uintptr_t)opts->workspace) & 255u) return LTL_E_INVAL;
-    if (opts->fp_bits > 64) return LTL_E_INVAL;
+    if (opts->fp_bits > 64 || opts->ruc_key_bits > 125) return LTL_E_INVAL;
     if (opts->word_bits != 0 && opts->word_bits != 32 && opts->word_bits != 64) return LTL_E_INVAL;
     if (opts->hash_slots_log2 != 0 && (opts->hash_slots_log2 < 8 || opts->hash_slots_log2 > 31)) return LTL_E_INVAL;
     if (hipSetDevice(opts->device) != hipSuccess) return LTL_E_DEVICE;
@@ -427,7 +430,11 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     const uint32_t nkeys = (wb == 64) ? 2u : 1u;
     const uint64_t o_valid = 0, o_sepm = R * j->wbytes, o_sepw = 2 * R * j->wbytes, o_nxt = 3 * R * j->wbytes;
     const uint64_t o_key = o_nxt + R * 8, o_rtr = o_key + R * 4 * nkeys, o_rwd = o_rtr + R * 4;
-    const uint64_t tables_bytes = o_rwd + R * 4;
+    // relaxed check: two words per 32-bit half of a row (the key metadata)
+    const bool ruc = (c->o.flags & LTL_CTX_RUC) != 0;
+    const uint64_t o_ruc = o_rwd + R * 4;
+    const uint64_t tables_bytes = o_ruc + (ruc ? R * 8 * nkeys : 0);
+    if (ruc && R * 8 * nkeys >= (1ull << 31)) return LTL_E_TOO_LONG;
     const uint64_t o_tfp = align_up(tables_bytes, 256);
     const uint64_t jpin_need = o_tfp + (uint64_t)T * 8;
     if (c->noalloc) {
@@ -473,6 +480,59 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
         uint64_t seed = 0x5eed1e55c0ffee11ull;
         for (uint64_t q = 0; q < R * nkeys; ++q) keys[q] = (uint32_t)(splitmix64(seed) >> 32) | 1u;
     }
+    if (ruc) {
+        // Key metadata of the relaxed check (Sec. 5; FKP, Sec. 7), per 32-bit half of a row
+        // (chunk j of trace t: positions 32j..32j+31), top half first:
+        //   pack form (FKP, or every matrix of at most 126 bits): the first m_t positions of
+        //   each trace, in trace order, fill the key from bit 0 and stop at 126 bits; a half
+        //   gets (mask of its kept positions, key bit of its first position);
+        //   keyed sums: the odd keys (a, b), top halves of SplitMix64 draws 2i and 2i + 1
+        //   of the seed's sequence, i = t * 2^32 + j.
+        // Halves past the end of their trace get (0, 0) and add nothing.
+        const uint32_t kb = 126;
+        std::vector<uint64_t> m(T);
+        for (uint32_t t = 0; t < T; ++t) m[t] = j->off[t + 1] - j->off[t];
+        j->ruc_pack = (c->o.flags & LTL_CTX_RUC_FKP) || j->TB <= kb;
+        if ((c->o.flags & LTL_CTX_RUC_FKP) && j->TB > kb) {
+            uint32_t best = 1;
+            uint64_t best_d = ~0ull;
+            for (uint32_t k = 1; k <= 100; ++k) {
+                uint64_t tot = 0;
+                for (uint32_t t = 0; t < T; ++t) tot += (m[t] * k + 50) / 100;
+                const uint64_t d = tot > kb ? tot - kb : kb - tot;
+                if (d < best_d) { best_d = d; best = k; }
+            }
+            for (uint32_t t = 0; t < T; ++t) m[t] = (m[t] * best + 50) / 100;
+        }
+        uint32_t *meta = (uint32_t *)(img + o_ruc);     // zeroed with the image
+        const uint32_t halves = nkeys;
+        uint64_t keyoff = 0;                            // key bit of the current trace's first position
+        for (uint32_t t = 0; t < T; ++t) {
+            const uint64_t len = j->off[t + 1] - j->off[t];
+            for (uint32_t w = 0; w < j->nwords[t]; ++w) {
+                const uint64_t row = j->row0[t] + w;
+                for (uint32_t hh = 0; hh < halves; ++hh) {
+                    const uint64_t jc = (uint64_t)w * halves + hh;      // chunk of the trace
+                    if (32 * jc >= len) continue;
+                    uint32_t *e = meta + (row * halves + hh) * 2;
+                    if (j->ruc_pack) {
+                        const uint64_t start = keyoff + 32 * jc;
+                        if (32 * jc >= m[t] || start >= kb) continue;
+                        const uint64_t kept = std::min<uint64_t>({32, m[t] - 32 * jc, kb - start});
+                        e[0] = (uint32_t)(0xFFFFFFFFull << (32 - kept));
+                        e[1] = (uint32_t)start;
+                    } else {
+                        const uint64_t ci = ((uint64_t)t << 32) | jc;
+                        // draw i is the mix of seed + (i + 1) gamma; splitmix64 adds gamma first
+                        uint64_t st = c->o.ruc_seed + (2 * ci) * 0x9e3779b97f4a7c15ull;
+                        e[0] = (uint32_t)(splitmix64(st) >> 32) | 1u;
+                        e[1] = (uint32_t)(splitmix64(st) >> 32) | 1u;
+                    }
+                }
+            }
+            keyoff += m[t];
+        }
+    }
 
     // workspace carve: the language-cache hash table first (12 bytes per slot), at
     // a fixed place so that a context can hand an emptied table to its next job
@@ -511,6 +571,11 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
         j->key = (uint32_t *)(tables + o_key);
         j->row_trace = (uint32_t *)(tables + o_rtr);
         j->row_word = (uint32_t *)(tables + o_rwd);
+        j->ruc_meta = ruc ? (uint32_t *)(tables + o_ruc) : nullptr;
+    }
+    if (ruc) {
+        j->entry_key = (unsigned long long *)ws_take(j, nslots * 16);
+        if (!j->entry_key) return LTL_E_OOM;
     }
     j->atoms = ws_take(j, (uint64_t)j->A * R * j->wbytes);
     j->tfp = (uint64_t *)ws_take(j, (uint64_t)T * 8);
@@ -769,7 +834,9 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         return j->ws + top;
     };
     const uint64_t nwa = align_up(nw, 64);                 // words, so the bitmaps stay aligned
-    const bool split = ntiles < (j->ctx->o.split_tiles ? (uint64_t)j->ctx->o.split_tiles : SPLIT_TILES);
+    // the relaxed check runs the whole-row kernels at every level (its key pass is theirs)
+    const bool ruc = (j->ctx->o.flags & LTL_CTX_RUC) != 0;
+    const bool split = !ruc && ntiles < (j->ctx->o.split_tiles ? (uint64_t)j->ctx->o.split_tiles : SPLIT_TILES);
     // batch lanes that take turns for whole-row levels: held until the level's work is done
     std::unique_lock<std::mutex> big_turn;
     if (!split && j->ctx->big_mu) big_turn = std::unique_lock<std::mutex>(*j->ctx->big_mu);
@@ -789,10 +856,11 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     uint32_t *cand_claim = split ? nullptr : (uint32_t *)take_top((uint64_t)nc * 4);
     uint32_t *has_member = split ? nullptr : (uint32_t *)take_top(align_up((uint64_t)new_cap * 4, 256));
     T *stage = (T *)take_top((uint64_t)j->R * sizeof(T));
+    unsigned long long *cand_key = ruc ? (unsigned long long *)take_top((uint64_t)nc * 16) : nullptr;
     const uint64_t arena_off = (uint64_t)(j->arena - j->ws);
     const uint64_t arena_used = j->total_entries * j->cm_bytes;
     if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !claimer || !new_owner || !stage ||
-        (!split && (!cand_claim || !has_member)) ||
+        (!split && (!cand_claim || !has_member)) || (ruc && !cand_key) ||
         arena_off + arena_used > top)
         return LTL_E_OOM;
     uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
@@ -855,7 +923,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     cls_first[4] = (uint32_t)grouped.size();
     // whole-row binary classes with LTL_CTX_LDS_TILES stage their child operands in LDS:
     // groups of 2 x 2 tiles (8 x 8 pairs), numbered per class like the tiles
-    const bool staged = !split && (j->ctx->o.flags & LTL_CTX_LDS_TILES);
+    const bool staged = !split && !ruc && (j->ctx->o.flags & LTL_CTX_LDS_TILES);
     uint32_t cls_groups[4] = {0, 0, 0, 0};
     if (staged) {
         for (int k = 1; k < 4; ++k) {
@@ -955,6 +1023,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.wg_split = wg_split;
     A.cand_fp = cand_fp;
     A.cand_viol = cand_viol;
+    A.ruc_meta = j->ruc_meta;
+    A.cand_key = cand_key;
+    A.entry_key = j->entry_key;
+    A.ruc_pack = j->ruc_pack ? 1u : 0u;
+    A.ruc_bits = j->ctx->o.ruc_key_bits;
+    A.mat_if_stored = 0;
     {   // materialize work items: entries x row chunks (sized on the candidate count, an upper bound)
         const uint64_t per = std::max<uint64_t>(
             1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max<uint64_t>(1, new_cap)));
@@ -1008,7 +1082,9 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             const Block *cb = grouped_d + cls_first[k];
             const uint32_t nb = cls_first[k + 1] - cls_first[k];
             hipError_t e;
-            if (stg)
+            if (ruc && !verify && !write)
+                e = Launch<T>::level_ruc(A, j->mw, k, cb, nb, cls_tiles[k], grid, st);
+            else if (stg)
                 e = Launch<T>::level_staged(A, j->mw, write ? 2 : (verify ? 1 : 0), k, cb, nb, cls_groups[k], chunk,
                                             grid, st);
             else if (write)
@@ -1035,6 +1111,10 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         Timer tm(j, LTL_K_EVAL, merged_eval ? (wg_split > 1 ? 2u : 1u) : ncls);
         HIP_TRY(launch_level(false));
     }
+    if (ruc) {              // relaxed check: the claims of new keys
+        Timer tm(j, LTL_K_COMPACT);
+        HIP_TRY(Launch<T>::ruc_claim(A, nc, j->s));
+    }
     if (wg_split > 1) {     // claimers' matrices (their rows were spread over workgroups)
         Timer tm(j, LTL_K_MATERIALIZE);
         HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
@@ -1052,12 +1132,16 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
                                    j->entry_slot, new_owner, j->store, false, grid_new, j->s));
         }
     }
-    // relaxed uniqueness check: nothing is compared, so no claim needs writing for the
-    // verification (has_member stays clear) and there is no verification pass
-    const bool ruc = (j->ctx->o.flags & LTL_CTX_RUC) != 0;
-    if (write_pass) {
-        Timer tm(j, LTL_K_MATERIALIZE, ruc ? ncls : ncls + 1);
-        if (!ruc) HIP_TRY(Launch<T>::mark_members(A, nc, j->s));
+    if (ruc) {
+        // relaxed check: nothing is compared.  If the level will be stored (decided on the
+        // device), each entry gets its representative's matrix and key
+        A.mat_if_stored = 1;
+        Timer tm(j, LTL_K_MATERIALIZE, 2);
+        HIP_TRY(Launch<T>::materialize(A, j->mw, 1u, grid_mat, j->s));
+        HIP_TRY(Launch<T>::ruc_entry_keys(A, j->s));
+    } else if (write_pass) {
+        Timer tm(j, LTL_K_MATERIALIZE, ncls + 1);
+        HIP_TRY(Launch<T>::mark_members(A, nc, j->s));
         HIP_TRY(launch_level(false, true));
     }
     if (!ruc) {
@@ -1428,7 +1512,7 @@ extern "C" int ltl_autotune(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset 
     static const uint32_t kFlags[LTL_TUNE_CONFIGS] = {0, LTL_CTX_LDS_TILES, 0, 0, LTL_CTX_LDS_TILES};
     static const uint32_t kSplit[LTL_TUNE_CONFIGS] = {8192, 8192, 2048, 32768, 32768};
     const ltl_ctx_opts saved = ctx->o;
-    const uint32_t keep = LTL_CTX_U_CARRY | LTL_CTX_U_DOUBLING | LTL_CTX_RUC;
+    const uint32_t keep = LTL_CTX_U_CARRY | LTL_CTX_U_DOUBLING | LTL_CTX_RUC | LTL_CTX_RUC_FKP;
     ltl_result ref{}, r{};
     int status = LTL_OK;
     double best = 1e300;

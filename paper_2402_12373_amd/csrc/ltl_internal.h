@@ -105,6 +105,16 @@ struct LevelArgs {
     uint32_t wg_split;
     unsigned long long *cand_fp;   // per candidate: sum of partial fingerprints
     uint32_t *cand_viol;           // per candidate: separation violated (bit)
+    // Relaxed uniqueness check: the evaluation writes each candidate's 126-bit key, a
+    // claim pass caches the new keys, and the level's entries get their representative's
+    // matrix (materialize, representative mode) and key.
+    const uint32_t *ruc_meta;      // per row: per 32-bit half (top half first), the keyed sums'
+                                   // odd keys (a, b), or in pack form (kept-position mask, key offset)
+    unsigned long long *cand_key;  // per candidate: its key (2 words)
+    unsigned long long *entry_key; // per global entry: its key
+    uint32_t ruc_pack;             // keys in pack form (prefix bits) instead of keyed sums
+    uint32_t ruc_bits;             // keep the first ruc_bits bits of each key (0: all 126)
+    uint32_t mat_if_stored;        // materialize only if the level will be stored (checked on the device)
 };
 
 
@@ -121,6 +131,12 @@ struct Launch {
     // workgroup per tile (claims and claimers' matrices included) ...
     static hipError_t level_wg(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
                                uint32_t ntiles, uint32_t grid, hipStream_t s);
+    // relaxed check: evaluation writing each candidate's key (whole-row tiles, one class) ...
+    static hipError_t level_ruc(const LevelArgs<T> &A, bool mw, int cls, const Block *blocks, uint32_t nblocks,
+                                uint32_t ntiles, uint32_t grid, hipStream_t s);
+    // ... the claims of new keys, and the keys of the level's entries after the compaction
+    static hipError_t ruc_claim(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
+    static hipError_t ruc_entry_keys(const LevelArgs<T> &A, hipStream_t s);
     // claims for tiles spread over several workgroups (A.wg_split > 1)
     static hipError_t probe(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
     // whole-row levels: groups joined by other candidates, then the write pass per class

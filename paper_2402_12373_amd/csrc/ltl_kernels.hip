@@ -302,6 +302,69 @@ __device__ __forceinline__ void fp_add(uint64_t &acc, T w, const RowMeta<T> &m) 
     }
 }
 
+// Relaxed uniqueness check (Sec. 5), one 32-bit half h of a row (positions 32j..32j+31 of
+// a trace, first position in the top bit) with its metadata (a, b):
+//   keyed sums: A += premix(h, a) * a, B += premix(h, b) * b (odd keys a, b; dead halves 0);
+//   pack form : the kept positions h & a, top-aligned, land at bit b of the 128-bit key
+//               (bit 0 = the top bit of A); the host keeps every key bit below 126, so the
+//               halves' contributions never overlap and their sum is their union.
+__device__ __forceinline__ void ruc_half(uint64_t &ka, uint64_t &kb, uint32_t h, uint32_t a, uint32_t b, bool pack) {
+    if (pack) {
+        const uint64_t x = (uint64_t)(h & a) << 32;
+        if (b < 64) {
+            ka += x >> b;
+            kb += b ? (x << (64 - b)) : 0ull;
+        } else {
+            kb += x >> (b - 64);
+        }
+    } else {
+        ka += (uint64_t)premix(h, a) * (uint64_t)a;
+        kb += (uint64_t)premix(h, b) * (uint64_t)b;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ruc_add(uint64_t &ka, uint64_t &kb, T w, const uint4 &mk, bool pack) {
+    if constexpr (sizeof(T) == 8) {
+        ruc_half(ka, kb, (uint32_t)(w >> 32), mk.x, mk.y, pack);
+        ruc_half(ka, kb, (uint32_t)w, mk.z, mk.w, pack);
+    } else {
+        ruc_half(ka, kb, (uint32_t)w, mk.x, mk.y, pack);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ uint4 load_ruc_meta(const uint32_t *meta, uint32_t r) {
+    const gptr<uint64_t> m = as_global((const uint64_t *)meta);
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t top = ldg(m, 2 * r), low = ldg(m, 2 * r + 1);
+        return make_uint4((uint32_t)top, (uint32_t)(top >> 32), (uint32_t)low, (uint32_t)(low >> 32));
+    }
+    const uint64_t v = ldg(m, r);
+    return make_uint4((uint32_t)v, (uint32_t)(v >> 32), 0u, 0u);
+}
+
+// The 126-bit key from the two sums: pack form as summed; keyed sums: A's top 63 bits,
+// then B's.  Then only the first `bits` bits are kept (debug truncation).
+__device__ __forceinline__ void ruc_key(uint64_t sa, uint64_t sb, bool pack, uint32_t bits, uint64_t &k0,
+                                        uint64_t &k1) {
+    if (pack) {
+        k0 = sa;
+        k1 = sb;
+    } else {
+        k0 = (sa & ~1ull) | (sb >> 63);
+        k1 = (sb << 1) & ~3ull;
+    }
+    if (bits > 0 && bits < 126) {
+        if (bits <= 64) {
+            k0 &= (bits == 64) ? ~0ull : ~(~0ull >> bits);
+            k1 = 0;
+        } else {
+            k1 &= ~(~0ull >> (bits - 64));
+        }
+    }
+}
+
 __device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor((unsigned long long)x, o);
@@ -594,7 +657,7 @@ struct WgShare {
 // WONLY: the write pass of a whole-row level (no evaluation): the claimers of the
 // tile, known from cand_claim, get their matrices written.
 template <typename T, bool MW, int OP, int TI, int TJ, bool VERIFY, bool CW = true, bool WG = false,
-          bool WONLY = false>
+          bool WONLY = false, bool RK = false>
 __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, uint32_t i0, uint32_t j0, int lane,
                                          uint32_t rb0, uint32_t rb1, WgShare *sh = nullptr, uint32_t wv = 0,
                                          uint32_t nwv = 1) {
@@ -628,6 +691,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
         RowMeta<T> m;
         T av[TI], bv[TJ];
         T tv[VERIFY ? NP : 1];
+        uint4 rk[RK ? 1 : 0];       // relaxed check: key metadata of the row
     };
     gptr<T> tp[VERIFY ? NP : 1];      // VERIFY: stored matrix to compare with, or null
     if constexpr (VERIFY) {
@@ -658,6 +722,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
     auto load = [&](uint32_t blk, Rowset &L) {
         const uint32_t r = blk * 64u + (uint32_t)lane;
         L.m = load_meta<T, MW, !VERIFY>(A.rows, r, lane);
+        if constexpr (RK) L.rk[0] = load_ruc_meta<T>(A.ruc_meta, r);
 #pragma unroll
         for (int ii = 0; ii < TI; ++ii) L.av[ii] = ldg(ap[ii], r);
 #pragma unroll
@@ -694,11 +759,15 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
         }
       } else {
         uint64_t acc[NP];
+        uint64_t acc_b[RK ? NP : 1];      // relaxed check: the second keyed sum
+        const bool rpack = RK && A.ruc_pack;
         // separation violations: only the position-0 bit (the top bit of a trace's first
         // word) counts, so 64-bit rows keep the top halves alone
         uint32_t viol[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) { acc[p] = 0; viol[p] = 0; }
+#pragma unroll
+        for (int p = 0; p < (RK ? NP : 1); ++p) acc_b[p] = 0;
         Rowset cur[PIPE], nxt[PIPE];
         load_group(rb0, cur);
         for (uint32_t blk = rb0; blk < rb1; blk += PIPE) {
@@ -716,7 +785,8 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                         if constexpr (!MW && sizeof(T) == 4) viol[p] |= (uint32_t)(w[p] ^ cur[u].m.sw);
                         else viol[p] |= (uint32_t)((w[p] ^ cur[u].m.sw) >> (8 * sizeof(T) - 32)) &
                                         (uint32_t)(cur[u].m.sm >> (8 * sizeof(T) - 32));
-                        fp_add<T>(acc[p], w[p], cur[u].m);
+                        if constexpr (RK) ruc_add<T>(acc[p], acc_b[RK ? p : 0], w[p], cur[u].rk[0], rpack);
+                        else fp_add<T>(acc[p], w[p], cur[u].m);
                     }
                 }
             }
@@ -724,6 +794,8 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
             for (int u = 0; u < PIPE; ++u) cur[u] = nxt[u];
         }
         const uint64_t my_fp = wave_sums<NP>(acc, lane);   // valid in lanes < NP
+        uint64_t my_fp_b = 0;
+        if constexpr (RK) my_fp_b = wave_sums<NP>(acc_b, lane);
         uint32_t my_idx = 0xFFFFFFFFu;
         bool my_bad = false;
 #pragma unroll
@@ -732,7 +804,17 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
             const bool bad = __ballot(viol[p] != 0) != 0ull;
             if (lane == p) { my_idx = idx[p]; my_bad = bad; }
         }
-        if constexpr (WG) {
+        if constexpr (RK) {
+            // relaxed check: the key is written; the claims are a pass of their own
+            if (my_idx != 0xFFFFFFFFu) {
+                if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
+                uint64_t k0, k1;
+                ruc_key(my_fp, my_fp_b, rpack, A.ruc_bits, k0, k1);
+                A.cand_key[2 * (uint64_t)my_idx] = k0;
+                A.cand_key[2 * (uint64_t)my_idx + 1] = k1;
+            }
+            return;
+        } else if constexpr (WG) {
             // partial results of this wave's row chunk -> wave 0 claims for the tile
             if (lane < NP) {
                 sh->fp[wv][lane] = my_fp;
@@ -1118,7 +1200,7 @@ void k_level_stg(LevelArgs<T> A, const Block *blocks, uint32_t nblocks, uint32_t
 // A.cls_blocks with class-local tile numbering.
 
 
-template <typename T, bool MW, bool VERIFY, int CLS, bool WONLY = false>
+template <typename T, bool MW, bool VERIFY, int CLS, bool WONLY = false, bool RK = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : LTL_WAVES_U64))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
                                                uint32_t ntiles, uint32_t chunk) {
     const int lane = (int)__lane_id();
@@ -1141,20 +1223,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         j0 = uniform(j0);
         if constexpr (CLS == CLS_UNARY) {
             switch (b.op) {
-            case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
-            case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
-            default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1); break;
+            case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1); break;
+            default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1); break;
             }
         } else if constexpr (CLS == CLS_ANDOR) {
-            if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
-            else run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
+            if (b.op == LTL_AND) run_tile<T, MW, LTL_AND, TILE, TILE, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1);
+            else run_tile<T, MW, LTL_OR, TILE, TILE, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1);
         } else if constexpr (CLS == CLS_U) {
-            run_tile<T, MW, LTL_U, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
+            run_tile<T, MW, LTL_U, TILE, TILE, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1);
         } else {
-            run_tile<T, MW, OP_UC, TILE, TILE, VERIFY, true, false, WONLY>(A, b, i0, j0, lane, rb0, rb1);
+            run_tile<T, MW, OP_UC, TILE, TILE, VERIFY, true, false, WONLY, RK>(A, b, i0, j0, lane, rb0, rb1);
         }
     }
 }
@@ -1366,9 +1448,74 @@ __device__ void write_matrix(const LevelArgs<T> &A, const T *pa, const T *pb, T 
 // re-check after a failed compare): entry e stores the matrix of its
 // representative recipe[base + e] at store[base + e].  A work item is one chunk
 // of A.mat_chunk row blocks of one entry.
+// ---------------------------------------------------------------------------
+// Relaxed check: claims of new keys (one thread per candidate).  A slot word holds
+// a tag of the key's slot hash and the claiming candidate; a candidate whose tag
+// matches compares its whole key with the claimer's (a slot of this level) or with
+// the entry's (a settled slot), so equal keys always meet and different keys never
+// merge, whatever the slot hash (fp_mask truncates it in tests).  The smallest
+// canonical index of a key's candidates wins (atomicMin), as in the exact check.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ruc_claim(LevelArgs<T> A, uint32_t ncand) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncand) return;
+    const uint64_t k0 = A.cand_key[2 * (uint64_t)c], k1 = A.cand_key[2 * (uint64_t)c + 1];
+    const uint64_t th = mix64(k0 ^ mix64(k1 ^ 0x9E3779B97F4A7C15ull)) & A.fp_mask;
+    const uint32_t tag = (uint32_t)th | 0x80000000u;
+    const unsigned long long word = ((unsigned long long)tag << 32) | c;
+    uint32_t h = (uint32_t)(mix64(th) >> 32) & A.slot_mask;
+    for (uint32_t n = 0; n < MAX_PROBES; ++n) {
+        unsigned long long w = __hip_atomic_load(&A.tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w == 0ull) {
+            const unsigned long long prev = atomicCAS(&A.tkey[h], 0ull, word);
+            if (prev == 0ull) {
+                atomicMin(&A.tval[h], c);
+                const uint32_t pos = atomicAdd(&A.ctr->n_new, 1u);
+                if (pos < A.new_cap) {
+                    A.new_slots[pos] = h;
+                    A.claimer[pos] = c;
+                } else {
+                    atomicOr(&A.ctr->overflow, 1u);
+                }
+                A.cand_slot[c] = h;
+                return;
+            }
+            w = prev;
+        }
+        if ((uint32_t)(w >> 32) == tag) {
+            const uint32_t v = __hip_atomic_load(&A.tval[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long *o = (v & VAL_SETTLED) ? A.entry_key + 2 * (uint64_t)(v & ~VAL_SETTLED)
+                                                             : A.cand_key + 2 * (uint64_t)(uint32_t)w;
+            if (o[0] == k0 && o[1] == k1) {
+                if (!(v & VAL_SETTLED)) atomicMin(&A.tval[h], c);
+                A.cand_slot[c] = h;
+                return;
+            }
+        }
+        h = (h + 1) & A.slot_mask;
+    }
+    atomicOr(&A.ctr->overflow, 1u);
+    A.cand_slot[c] = NO_SLOT;
+}
+
+// Relaxed check: each new entry keeps its representative's key (for later levels).
+template <typename T>
+__global__ __launch_bounds__(256) void k_ruc_entry_keys(LevelArgs<T> A) {
+    if (A.bound_level || uniform64(A.ctr->first_sol) != ~0ull) return;
+    const uint32_t n = level_new_count(A.ctr, A.arena_cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t g = A.level_base + i;
+        const uint32_t x = A.recipe[g];
+        A.entry_key[2 * (uint64_t)g] = A.cand_key[2 * (uint64_t)x];
+        A.entry_key[2 * (uint64_t)g + 1] = A.cand_key[2 * (uint64_t)x + 1];
+    }
+}
+
 template <typename T, bool MW>
 __global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t rep_mode) {
     const int lane = (int)__lane_id();
+    if (A.mat_if_stored && (A.bound_level || uniform64(A.ctr->first_sol) != ~0ull)) return;
     const uint32_t n_entries = uniform(level_new_count(A.ctr, A.arena_cap));
     const uint32_t NB = A.rows.NB;
     const uint32_t chunk = A.mat_chunk;
@@ -1861,6 +2008,45 @@ hipError_t Launch<T>::level(const LevelArgs<T> &A, bool mw, bool verify, int cls
     }
     if (verify) launch_cls<T, false, true>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
     else launch_cls<T, false, false>(A, cls, blocks, nblocks, ntiles, chunk, grid, s);
+    return hipGetLastError();
+}
+
+template <typename T, bool MW>
+static void launch_ruc_cls(const LevelArgs<T> &A, int cls, const Block *blocks, uint32_t nb, uint32_t nt,
+                           uint32_t grid, hipStream_t s) {
+    const uint32_t ch = A.rows.NB;
+    switch (cls) {
+    case CLS_UNARY: hipLaunchKernelGGL((k_level<T, MW, false, CLS_UNARY, false, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    case CLS_ANDOR: hipLaunchKernelGGL((k_level<T, MW, false, CLS_ANDOR, false, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    case CLS_U:     hipLaunchKernelGGL((k_level<T, MW, false, CLS_U, false, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    default:        hipLaunchKernelGGL((k_level<T, MW, false, CLS_UC, false, true>), dim3(grid), dim3(256), 0, s, A, blocks, nb, nt, ch); break;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::level_ruc(const LevelArgs<T> &A, bool mw, int cls, const Block *blocks, uint32_t nblocks,
+                                uint32_t ntiles, uint32_t grid, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {
+        if (mw) {
+            launch_ruc_cls<T, true>(A, cls, blocks, nblocks, ntiles, grid, s);
+            return hipGetLastError();
+        }
+    }
+    launch_ruc_cls<T, false>(A, cls, blocks, nblocks, ntiles, grid, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::ruc_claim(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, (ncand + 255) / 256);
+    hipLaunchKernelGGL((k_ruc_claim<T>), dim3(grid), dim3(256), 0, s, A, ncand);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::ruc_entry_keys(const LevelArgs<T> &A, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((A.new_cap + 255) / 256, 2048));
+    hipLaunchKernelGGL((k_ruc_entry_keys<T>), dim3(grid), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ LTL_E_BUFFER = -7
 ATOM, NOT, AND, OR, X, F, G, U = range(8)
 CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL, CTX_RUC, CTX_U_DOUBLING = 0x1, 0x2, 0x4, 0x8, 0x10
 CTX_LDS_TILES = 0x20   # binary tiles of whole-row levels stage 8 x 8 groups of child words in LDS
+CTX_RUC_FKP = 0x40     # with CTX_RUC: first-k-percent keys (Sec. 7) instead of the keyed sums
 BATCH_BIG_ALONE = 0x100    # batch flag: whole-row levels of different lanes take turns
 BATCH_SHARED_BUDGET = 0x200   # batch flag: one memory budget, regions sized per job
 SPEC_DEVICE = 0x1
@@ -50,7 +51,8 @@ class CtxOpts(C.Structure):
     _fields_ = [("device", C.c_int32), ("flags", C.c_uint32), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_uint64), ("stream", C.c_void_p), ("hash_slots_log2", C.c_uint32),
                 ("word_bits", C.c_uint32), ("fp_bits", C.c_uint32), ("split_tiles", C.c_uint32),
-                ("max_entries", C.c_uint64)]
+                ("max_entries", C.c_uint64), ("ruc_seed", C.c_uint64), ("ruc_key_bits", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class Spec(C.Structure):
@@ -322,7 +324,7 @@ class Context:
 
     def __init__(self, workspace_bytes: int = 1 << 30, device: int = 0, flags: int = 0, hash_slots_log2: int = 0,
                  word_bits: int = 0, fp_bits: int = 0, max_entries: int = 0, stream=None, workspace=None,
-                 split_tiles: int = 0):
+                 split_tiles: int = 0, ruc_seed: int = 0, ruc_key_bits: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the LTL learner has no CPU path")
@@ -346,6 +348,8 @@ class Context:
         o.fp_bits = fp_bits
         o.split_tiles = split_tiles
         o.max_entries = max_entries
+        o.ruc_seed = ruc_seed
+        o.ruc_key_bits = ruc_key_bits
         self.opts = o
         h = C.c_void_p()
         st = L.ltl_ctx_create(C.byref(o), C.byref(h))

@@ -70,9 +70,9 @@ def test_canonical_order_cases(ctx, case):
     assert g.solution == case["expect_formula"], (case["name"], g.solution)
 
 
-def _level_by_level(ltl, ctx, inst, bound, check_entries=True, max_entries_per_level=None):
+def _level_by_level(ltl, ctx, inst, bound, check_entries=True, max_entries_per_level=None, **oracle_kw):
     """Evaluates levels one at a time and compares every stored matrix and formula."""
-    run = O.Run(O.Spec.of(inst), bound, mode=O.MODE_EXPAND, threads=8)
+    run = O.Run(O.Spec.of(inst), bound, mode=O.MODE_EXPAND, threads=8, **oracle_kw)
     ora = run.result()
     job = ctx.job(inst, bound)
     try:
@@ -508,39 +508,55 @@ def test_batch_big_levels_take_turns(ltl):
         plain.close()
 
 
-def test_relaxed_uniqueness_check(ltl):
-    """LTL_CTX_RUC (the paper's relaxed check, Sec. 5): with full fingerprints the results
-    equal the exact mode's; with fingerprints cut to 4 bits the exact mode still matches the
-    oracle while the relaxed one drops languages."""
-    key = lambda r: (r.status, r.cost, r.level_new, r.level_candidates, r.solution_index, r.solution)
-    exact = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22)
-    ruc = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, flags=ltl.CTX_RUC)
+RUC_CASES = [("hash", 0), ("hash", 9), ("hash", 14), ("fkp", 0), ("fkp", 10)]
+
+
+@pytest.mark.parametrize("kind,bits", RUC_CASES, ids=[f"{k}-{b or 126}bit" for k, b in RUC_CASES])
+def test_relaxed_check_matches_oracle(ltl, kind, bits):
+    """LTL_CTX_RUC (Sec. 5; FKP keys, Sec. 7) against the oracle's relaxed mode with the same
+    126-bit keys: the same languages are cached (canonical-first candidate of each new key),
+    so level counts, the first solution and its formula agree, on one-word and multi-word
+    rows.  Keys cut to a few bits make false positives frequent, so the results depend on
+    every key bit; slot hashes cut to 4 bits (fp_bits) make different keys share slots."""
+    flags = ltl.CTX_RUC | (ltl.CTX_RUC_FKP if kind == "fkp" else 0)
+    okind = O.RUC_FKP if kind == "fkp" else O.RUC_HASH
+    rng = np.random.default_rng(5)
+    cases = [(synth.preset_instance("tiny", s)[0], 7, None, f"tiny/{s}") for s in range(6)]
+    cases.append((random_instance(rng, 2, 6, 6, 40, 150), 5, None, "u64 multi-word"))
+    cases.append((random_instance(rng, 3, 5, 5, 60, 70), 5, None, "u64 one-word"))
+    cases.append((random_instance(rng, 2, 4, 4, 3, 9), 7, None, "at most 126 bits"))
+    cases.append((synth.hamming_instance(0, 4, 2), 12, O.U_FREE_NNF, "hamming U-free NNF"))
+    for fp_bits in (0, 4):
+        c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=20, flags=flags, ruc_seed=17,
+                        ruc_key_bits=bits, fp_bits=fp_bits)
+        try:
+            for inst, bound, ops, name in cases:
+                _say("ruc", kind, bits, fp_bits, name)
+                o = O.learn(inst, bound, op_mask=ops if ops is not None else O.ALL_OPS, ruc=okind, ruc_seed=17,
+                            ruc_bits=bits)
+                g = c.learn(inst, bound, ops=ops)
+                _same(g, o, f"{kind}/{bits}/{fp_bits}/{name}")
+                if bits == 0 and int(inst.offsets[-1]) <= 126:    # Sec. 5: exact up to 126 bits
+                    _same(g, O.learn(inst, bound, op_mask=ops if ops is not None else O.ALL_OPS), name)
+        finally:
+            c.close()
+
+
+@pytest.mark.parametrize("kind", ["hash", "fkp"])
+def test_relaxed_check_stored_matrices(ltl, kind):
+    """With truncated keys several languages share a key and the entry kept is the
+    canonical-first one: every stored matrix and entry formula equals the oracle's."""
+    flags = ltl.CTX_RUC | (ltl.CTX_RUC_FKP if kind == "fkp" else 0)
+    okind = O.RUC_FKP if kind == "fkp" else O.RUC_HASH
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=20, flags=flags, ruc_seed=3, ruc_key_bits=11)
     try:
-        for seed in range(16):
-            inst, cfg = synth.preset_instance("tiny", seed)
-            _say("ruc tiny seed", seed)
-            assert key(ruc.learn(inst, cfg["bound"])) == key(exact.learn(inst, cfg["bound"])), seed
-        inst = synth.hamming_instance(0, 3, 2)
-        assert key(ruc.learn(inst, 16, ops=O.U_FREE_NNF)) == key(exact.learn(inst, 16, ops=O.U_FREE_NNF))
+        rng = np.random.default_rng(9)
+        for inst, bound, name in [(synth.preset_instance("tiny", 2)[0], 7, "tiny/2"),
+                                  (random_instance(rng, 2, 6, 6, 40, 150), 5, "u64 multi-word")]:
+            _say("ruc stored matrices", kind, name)
+            _level_by_level(ltl, c, inst, bound, ruc=okind, ruc_seed=3, ruc_bits=11)
     finally:
-        exact.close()
-        ruc.close()
-    exact4 = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, fp_bits=4)
-    ruc4 = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=22, fp_bits=4, flags=ltl.CTX_RUC)
-    try:
-        differs = 0
-        for seed in range(8):
-            inst, cfg = synth.preset_instance("tiny", seed)
-            o = O.learn(inst, cfg["bound"])
-            _same(exact4.learn(inst, cfg["bound"]), o, f"exact fp4 tiny/{seed}")
-            r = ruc4.learn(inst, cfg["bound"])
-            differs += int(key(r)[:4] != (o.status, o.cost, o.level_new, o.level_candidates))
-            # a relaxed level never holds more languages than the exact one
-            assert r.level_new[1] <= o.level_new[1]
-        assert differs > 0
-    finally:
-        exact4.close()
-        ruc4.close()
+        c.close()
 
 
 def test_learn_complete(ltl, ctx, monkeypatch):
