@@ -37,6 +37,12 @@
 
 namespace ltl {
 
+#ifndef LTL_UC_PAIR_BARRIER
+#define LTL_UC_PAIR_BARRIER 0
+#endif
+#ifndef LTL_UC_ADD_PREFIX
+#define LTL_UC_ADD_PREFIX 1      // carries between the words of a trace by one add (else Kogge-Stone)
+#endif
 constexpr int OP_UC = 8;   // U computed by the carry-chain adder
 
 // Row blocks of operands in flight per evaluation wave, for one-word rows and for
@@ -66,6 +72,7 @@ template <typename T>
 struct RowMeta {
     T v, sm, sw;
     uint64_t nx, hn;
+    uint64_t hnr;      // multi-word rows: hn bit-reversed, shifted down by one (carry prefix)
     uint32_t k0, k1;
     uint32_t cont;     // multi-word rows: all ones if the next lane holds the next word of this
                        // lane's trace, else 0
@@ -131,6 +138,7 @@ __device__ __forceinline__ RowMeta<T> load_meta(const Rows<T> &rw, uint32_t r, i
         m.nx = 0;
     }
     m.hn = 0;
+    m.hnr = 0;
     m.cont = 0;
     return m;
 }
@@ -141,6 +149,7 @@ __device__ __forceinline__ void finish_meta(RowMeta<T> &m, int lane) {
     if constexpr (MW) {
         const bool c = (m.nx & (2ull << lane)) != 0ull;
         m.hn = __ballot(c);
+        m.hnr = __builtin_bitreverse64(m.hn) >> 1;
         m.cont = c ? ~0u : 0u;
     }
 }
@@ -223,35 +232,48 @@ __device__ __forceinline__ T op_U(T phi, T psi, const RowMeta<T> &m, uint32_t k,
     return c2;
 }
 
+// U as a carry chain.  Read a word MSB-first (bit 63 = its first position) as an
+// unsigned integer: with A = phi | psi and B = psi, the carry out of each bit of A + B is
+// psi | (phi & carry in), which is the recurrence of phi U psi toward earlier positions.
+// Per bit that is psi where psi holds, else phi & carry in; since S ^ psi = A ^ carry in
+// for the sum S, the result is bit-select(S ^ psi, psi, A) (a v_bfi per 32-bit half).
+template <typename T>
+__device__ __forceinline__ T uc_select(T S, T psi, T A) {
+    const T t = S ^ psi;
+    return (t & psi) | (~t & A);
+}
+
 template <typename T, bool MW>
 __device__ __forceinline__ T op_UC(T phi, T psi, const RowMeta<T> &m, uint32_t maxw, int lane) {
-    if constexpr (!MW && sizeof(T) == 4) {
-        uint64_t A = (uint64_t)(phi | psi), B = (uint64_t)psi;
-        uint64_t C = (A + B) ^ A ^ B;   // carry into each bit; bit 32 = carry out
-        return (T)(C >> 1);
-    } else if constexpr (!MW) {
-        uint64_t A = phi | psi, B = psi;
-        uint64_t S = A + B;
-        uint64_t cout = S < A ? 1ull : 0ull;
-        return ((S ^ A ^ B) >> 1) | (cout << 63);
+    const T A = phi | psi;
+    if constexpr (!MW) {
+        return uc_select<T>((T)(A + psi), psi, A);
     } else {
-        uint64_t A = phi | psi, B = psi;
-        uint64_t S = A + B;
-        bool g = S < A;                    // carry out without carry in
-        bool p = (S == ~0ull);             // carry out iff carry in
-        // carry out of each lane with the carries of the later words of its trace: a
-        // prefix over the lanes (Kogge-Stone doubling on the wave masks), from the last
-        // word of a trace toward its first; Pm is cut where a trace ends (m.hn clear)
-        uint64_t Gm = __ballot(g), Pm = __ballot(p) & m.hn;
+        const uint64_t S = A + psi;
+        // lanes whose word carries out without a carry in (G), and iff one comes in (P);
+        // the carry into each lane from the later words of its trace is a prefix over the
+        // lanes, from the last word of a trace toward its first; Pm is cut where a trace ends
+        uint64_t Gm = __builtin_amdgcn_ballot_w64(S < A);
+        uint64_t Pm = __builtin_amdgcn_ballot_w64(S == ~0ull) & m.hn;
+#if LTL_UC_ADD_PREFIX
+        // the prefix as one 64-bit add: in reversed lane order a later word is a lower
+        // bit, and with generate G and propagate P (disjoint) the carry into each bit of
+        // (G | P) + G is g | (p & carry) of the bit below; the bits below a lane whose next
+        // lane starts another trace are cleared first (m.hnr), so no carry crosses traces
+        (void)maxw;
+        const uint64_t Gr = __builtin_bitreverse64(Gm) & m.hnr, Pr = __builtin_bitreverse64(Pm) & m.hnr;
+        const uint64_t X = Gr | Pr;
+        const uint64_t Cm = __builtin_bitreverse64((X + Gr) ^ X ^ Gr);
+#else
         for (uint32_t d = 1; d < maxw; d <<= 1) {
             Gm |= Pm & (Gm >> d);
             Pm &= Pm >> d;
         }
-        const uint64_t Cm = (Gm >> 1) & m.hn;   // carry into each lane from the next word of its trace
-        uint64_t cin = (Cm >> lane) & 1ull;
-        uint64_t S2 = S + cin;
-        uint64_t cout = (uint64_t)g | ((uint64_t)p & cin);
-        return ((S2 ^ A ^ B) >> 1) | (cout << 63);
+        const uint64_t Cm = (Gm >> 1) & m.hn;
+#endif
+        (void)lane;
+        const uint64_t cin = __builtin_amdgcn_inverse_ballot_w64(Cm) ? 1ull : 0ull;
+        return uc_select<uint64_t>(S + cin, psi, A);
     }
 }
 
@@ -575,7 +597,7 @@ __device__ __forceinline__ T apply_fused(int k, T a, const RowMeta<T> &m, const 
 // With GUARD and several words per trace (where one step of one pair costs
 // lane moves and 64-bit shifts), the U chains of the other pairs, and of
 // a-children none of whose pairs is needed, are skipped and their words left
-// unspecified.  With one word per trace a step is two instructions, less than
+// unspecified; the carry adder skips the other pairs too.  With one word per trace a step is two instructions, less than
 // the branches that would skip it, so every pair is computed.
 template <typename T, bool MW, int OP, int TI, int TJ, bool GUARD = false>
 __device__ __forceinline__ void tile_words(const T (&av)[TI], const T (&bv)[TJ], const RowMeta<T> &m,
@@ -618,10 +640,23 @@ __device__ __forceinline__ void tile_words(const T (&av)[TI], const T (&bv)[TJ],
 #pragma unroll
             for (int jj = 0; jj < TJ; ++jj) w[ii * TJ + jj] = apply_fused<T, MW>(jj, av[ii], m, rw, lane);
     } else {
+        // the carry adder on several words per trace costs two ballots and a prefix over
+        // the wave's masks per pair: with GUARD, pairs outside `need` are skipped (left 0)
+        constexpr bool G = GUARD && MW && OP == OP_UC;
 #pragma unroll
         for (int ii = 0; ii < TI; ++ii)
 #pragma unroll
-            for (int jj = 0; jj < TJ; ++jj) w[ii * TJ + jj] = apply<T, MW, OP>(av[ii], bv[jj], m, rw, lane);
+            for (int jj = 0; jj < TJ; ++jj) {
+                if (G && !((need >> (ii * TJ + jj)) & 1u)) {
+                    w[ii * TJ + jj] = 0;
+                    continue;
+                }
+                w[ii * TJ + jj] = apply<T, MW, OP>(av[ii], bv[jj], m, rw, lane);
+#if LTL_UC_PAIR_BARRIER
+                // one pair's masks at a time in scalar registers
+                if constexpr (MW && OP == OP_UC) __builtin_amdgcn_sched_barrier(0);
+#endif
+            }
     }
 }
 
@@ -1200,8 +1235,10 @@ void k_level_stg(LevelArgs<T> A, const Block *blocks, uint32_t nblocks, uint32_t
 // A.cls_blocks with class-local tile numbering.
 
 
+// (the relaxed check's key pass holds two sums per pair: register-allocated for two waves
+// per SIMD, as the 64-bit kernels)
 template <typename T, bool MW, bool VERIFY, int CLS, bool WONLY = false, bool RK = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : LTL_WAVES_U64))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !RK ? 4 : LTL_WAVES_U64))) void k_level(LevelArgs<T> A, const Block *blocks, uint32_t nblocks,
                                                uint32_t ntiles, uint32_t chunk) {
     const int lane = (int)__lane_id();
     if constexpr (VERIFY || WONLY) {
