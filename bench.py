@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0,
                     help="jobs in flight (lanes of a batch executor: own stream, workspace slice, hash table); "
                          "default 4 for the fixed workloads, 1 for long (each long job needs the whole "
-                         "workspace), 8 for batched; 1 = one job after another")
+                         "workspace), 4 for batched; 1 = one job after another")
     ap.add_argument("--seeds", default="", help="job seeds, e.g. 0-7 (default: 0-3 for long, else 0-7)")
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: skip the autotuner (ltl_autotune on the largest of the first 16 jobs chooses "
                          "the binary tile shape and the whole-row level size for the plain and batched runs)")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="batched/served: lanes run the U class on their own stream (LTL_CTX_ONE_STREAM)")
     ap.add_argument("--slices", action="store_true",
                     help="batched/served: equal workspace slices per lane instead of one shared budget "
                          "with regions sized per job (LTL_BATCH_SHARED_BUDGET)")
@@ -455,17 +457,27 @@ def bench_batched(args):
     free, _ = torch.cuda.mem_get_info()
     ws_bytes = int(args.workspace_gb * 2 ** 30) if args.workspace_gb else int(min(free * 0.85, 200 * 2 ** 30))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    lanes = args.lanes or 8
+    lanes = args.lanes or 4
     slice_bytes = (ws_bytes // lanes) & ~255
     slots = 22
-    # autotuner: tile shape and level schedule from the largest of the first 16 jobs
+    # autotuner: tile shape and level schedule, tuned on the slowest of the first 32 jobs
+    # (an untimed pass with the defaults picks it: the configurations differ only on the
+    # large levels of the large jobs)
     tune_flags, tune_split, tuning = 0, 0, None
     if not args.no_autotune:
-        probe = max(range(min(16, len(insts))), key=lambda i: int(insts[i].total_positions))
         tctx = ltl.Context(workspace=ws)
+        tctx.learn(dev[0], bounds[0])          # the first call of a process runs slow
+        took = []
+        for i in range(min(32, len(insts))):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            tctx.learn(dev[i], bounds[i])
+            took.append(time.perf_counter() - a)
+        probe = max(range(len(took)), key=lambda i: took[i])
         (tune_flags, tune_split), rows = tctx.autotune(dev[probe], bounds[probe])
         tctx.close()
-        tuning = {"job": probe, "chosen": {"flags": tune_flags, "split_tiles": tune_split},
+        tuning = {"job": probe, "job_ms_default": round(took[probe] * 1e3, 3),
+                  "chosen": {"flags": tune_flags, "split_tiles": tune_split},
                   "tried_ms": [{"flags": f, "split_tiles": t, "ms": round(ms, 3)} for f, t, ms in rows]}
     # plain path: one job per call, one at a time, in a workspace of one lane's size (slices)
     # or the whole workspace (shared budget: a job's region grows up to it)
@@ -486,7 +498,7 @@ def bench_batched(args):
     ctx.close()
     print(f"plain path: {len(plain)} jobs in {t_plain:.2f} s", file=sys.stderr, flush=True)
     # batched: a batch executor (lanes created once, outside the timed region)
-    big = ltl.BATCH_BIG_ALONE if args.big_alone else 0
+    big = (ltl.BATCH_BIG_ALONE if args.big_alone else 0) | (ltl.CTX_ONE_STREAM if args.one_stream else 0)
     if args.slices:
         ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=slots,
                        flags=big | tune_flags, split_tiles=tune_split)
@@ -561,7 +573,7 @@ def bench_served(args):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     lanes = args.lanes or 4
     slice_bytes = (ws_bytes // lanes) & ~255
-    big = ltl.BATCH_BIG_ALONE if args.big_alone else 0
+    big = (ltl.BATCH_BIG_ALONE if args.big_alone else 0) | (ltl.CTX_ONE_STREAM if args.one_stream else 0)
     if args.slices:
         ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=22, flags=big)
     else:      # one budget: regions sized by each job's estimated footprint

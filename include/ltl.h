@@ -82,6 +82,9 @@ typedef struct ltl_job ltl_job;
 #define LTL_CTX_U_DOUBLING 0x10u /* compute U by the shift-doubling of App. B at every level
                                     (overrides the choice by row layout; LTL_CTX_U_CARRY wins
                                     if both are set)                                           */
+#define LTL_CTX_ONE_STREAM 0x80u /* run every kernel on the context's stream: the U class of a
+                                    whole-row level is not forked onto a second stream beside
+                                    the other classes (batch lanes, whose jobs already overlap) */
 #define LTL_CTX_TIMING    0x2u   /* record GPU time per kernel kind and per level (HIP events
                                     around each kernel group)                                  */
 #define LTL_CTX_TIMING_LEVEL 0x4u /* record only the GPU time of each level: one event pair from
@@ -238,7 +241,8 @@ typedef struct {
     uint32_t best;                           /* index of the fastest                      */
     uint32_t flags[LTL_TUNE_CONFIGS];        /* LTL_CTX_LDS_TILES or 0                    */
     uint32_t split_tiles[LTL_TUNE_CONFIGS];  /* ltl_ctx_opts.split_tiles                  */
-    double   ms[LTL_TUNE_CONFIGS];           /* wall time of the job (milliseconds)       */
+    double   ms[LTL_TUNE_CONFIGS];           /* wall time of the job, the fastest of three
+                                                runs (milliseconds)                       */
 } ltl_tuning;
 int ltl_autotune(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint32_t cost_bound, ltl_tuning *out);
 

@@ -320,7 +320,8 @@ extern "C" int ltl_ctx_create(const ltl_ctx_opts *opts, ltl_ctx **out) {
     c->o = *opts;
     c->s = (hipStream_t)opts->stream;
     if (hipHostMalloc((void **)&c->pinned, PINNED_BYTES, hipHostMallocDefault) != hipSuccess ||
-        (LTL_FORK_U && (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        (LTL_FORK_U && !(opts->flags & LTL_CTX_ONE_STREAM) &&
+         (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
                         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
                         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess))) {
         ltl_ctx_destroy(c);
@@ -1028,7 +1029,6 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.entry_key = j->entry_key;
     A.ruc_pack = j->ruc_pack ? 1u : 0u;
     A.ruc_bits = j->ctx->o.ruc_key_bits;
-    A.mat_if_stored = 0;
     {   // materialize work items: entries x row chunks (sized on the candidate count, an upper bound)
         const uint64_t per = std::max<uint64_t>(
             1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max<uint64_t>(1, new_cap)));
@@ -1134,11 +1134,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     if (ruc) {
         // relaxed check: nothing is compared.  If the level will be stored (decided on the
-        // device), each entry gets its representative's matrix and key
-        A.mat_if_stored = 1;
-        Timer tm(j, LTL_K_MATERIALIZE, 2);
-        HIP_TRY(Launch<T>::materialize(A, j->mw, 1u, grid_mat, j->s));
+        // device), each entry gets its representative's key and, in the write pass, its
+        // representative's matrix (a level that is not stored writes nothing: no member
+        // flags are set)
+        Timer tm(j, LTL_K_MATERIALIZE, ncls + 1);
         HIP_TRY(Launch<T>::ruc_entry_keys(A, j->s));
+        HIP_TRY(launch_level(false, true));
     } else if (write_pass) {
         Timer tm(j, LTL_K_MATERIALIZE, ncls + 1);
         HIP_TRY(Launch<T>::mark_members(A, nc, j->s));
@@ -1515,9 +1516,11 @@ extern "C" int ltl_autotune(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset 
     const uint32_t keep = LTL_CTX_U_CARRY | LTL_CTX_U_DOUBLING | LTL_CTX_RUC | LTL_CTX_RUC_FKP;
     ltl_result ref{}, r{};
     int status = LTL_OK;
-    double best = 1e300;
-    for (int k = -1; k < LTL_TUNE_CONFIGS; ++k) {
-        const int q = k < 0 ? 0 : k;          // k = -1: an untimed warm-up run
+    // an untimed warm-up run, then TUNE_ROUNDS rounds over the configurations (the
+    // fastest run of each counts: short jobs vary by more than the configurations do)
+    constexpr int TUNE_ROUNDS = 3;
+    for (int k = -1; k < TUNE_ROUNDS * LTL_TUNE_CONFIGS && status == LTL_OK; ++k) {
+        const int q = k < 0 ? 0 : k % LTL_TUNE_CONFIGS;
         ctx->o.flags = (saved.flags & keep) | kFlags[q];
         ctx->o.split_tiles = kSplit[q];
         const auto t0 = std::chrono::steady_clock::now();
@@ -1531,15 +1534,17 @@ extern "C" int ltl_autotune(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset 
         for (uint32_t c = 0; same && c <= r.levels_done && c < LTL_MAX_LEVELS; ++c)
             same = r.level_new[c] == ref.level_new[c] && r.level_candidates[c] == ref.level_candidates[c];
         if (!same) { status = LTL_E_STATE; break; }
-        out->ms[k] = ms;
-        out->flags[k] = kFlags[k];
-        out->split_tiles[k] = kSplit[k];
-        ++out->tried;
-        if (ms < best) {
-            best = ms;
-            out->best = (uint32_t)k;
+        if (k < LTL_TUNE_CONFIGS) {
+            out->ms[q] = ms;
+            out->flags[q] = kFlags[q];
+            out->split_tiles[q] = kSplit[q];
+            ++out->tried;
+        } else {
+            out->ms[q] = std::min(out->ms[q], ms);
         }
     }
+    for (uint32_t q = 0; q < out->tried; ++q)
+        if (out->ms[q] < out->ms[out->best]) out->best = q;
     ctx->o = saved;
     return status;
 }

@@ -107,14 +107,13 @@ struct LevelArgs {
     uint32_t *cand_viol;           // per candidate: separation violated (bit)
     // Relaxed uniqueness check: the evaluation writes each candidate's 126-bit key, a
     // claim pass caches the new keys, and the level's entries get their representative's
-    // matrix (materialize, representative mode) and key.
+    // key and, in the write pass, its matrix.
     const uint32_t *ruc_meta;      // per row: per 32-bit half (top half first), the keyed sums'
                                    // odd keys (a, b), or in pack form (kept-position mask, key offset)
     unsigned long long *cand_key;  // per candidate: its key (2 words)
     unsigned long long *entry_key; // per global entry: its key
     uint32_t ruc_pack;             // keys in pack form (prefix bits) instead of keyed sums
     uint32_t ruc_bits;             // keep the first ruc_bits bits of each key (0: all 126)
-    uint32_t mat_if_stored;        // materialize only if the level will be stored (checked on the device)
 };
 
 

@@ -847,6 +847,7 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
                 ruc_key(my_fp, my_fp_b, rpack, A.ruc_bits, k0, k1);
                 A.cand_key[2 * (uint64_t)my_idx] = k0;
                 A.cand_key[2 * (uint64_t)my_idx + 1] = k1;
+                A.cand_claim[my_idx] = 0xFFFFFFFFu;     // representatives are marked after the compaction
             }
             return;
         } else if constexpr (WG) {
@@ -1536,7 +1537,10 @@ __global__ __launch_bounds__(256) void k_ruc_claim(LevelArgs<T> A, uint32_t ncan
     A.cand_slot[c] = NO_SLOT;
 }
 
-// Relaxed check: each new entry keeps its representative's key (for later levels).
+// Relaxed check, after the compaction of a level that will be stored: each new entry
+// keeps its representative's key (for later levels), and the representative is marked
+// with the entry's arena slot (claim order) for the write pass, which then writes the
+// representative's matrix (a claimer's may differ from it under the same key).
 template <typename T>
 __global__ __launch_bounds__(256) void k_ruc_entry_keys(LevelArgs<T> A) {
     if (A.bound_level || uniform64(A.ctr->first_sol) != ~0ull) return;
@@ -1546,13 +1550,13 @@ __global__ __launch_bounds__(256) void k_ruc_entry_keys(LevelArgs<T> A) {
         const uint32_t x = A.recipe[g];
         A.entry_key[2 * (uint64_t)g] = A.cand_key[2 * (uint64_t)x];
         A.entry_key[2 * (uint64_t)g + 1] = A.cand_key[2 * (uint64_t)x + 1];
+        A.cand_claim[x] = A.store[g] - A.level_base;
     }
 }
 
 template <typename T, bool MW>
 __global__ __launch_bounds__(256) void k_materialize(LevelArgs<T> A, uint32_t rep_mode) {
     const int lane = (int)__lane_id();
-    if (A.mat_if_stored && (A.bound_level || uniform64(A.ctr->first_sol) != ~0ull)) return;
     const uint32_t n_entries = uniform(level_new_count(A.ctr, A.arena_cap));
     const uint32_t NB = A.rows.NB;
     const uint32_t chunk = A.mat_chunk;

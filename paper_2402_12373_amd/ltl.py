@@ -25,6 +25,7 @@ ATOM, NOT, AND, OR, X, F, G, U = range(8)
 CTX_U_CARRY, CTX_TIMING, CTX_TIMING_LEVEL, CTX_RUC, CTX_U_DOUBLING = 0x1, 0x2, 0x4, 0x8, 0x10
 CTX_LDS_TILES = 0x20   # binary tiles of whole-row levels stage 8 x 8 groups of child words in LDS
 CTX_RUC_FKP = 0x40     # with CTX_RUC: first-k-percent keys (Sec. 7) instead of the keyed sums
+CTX_ONE_STREAM = 0x80  # no second stream for the U class of whole-row levels
 BATCH_BIG_ALONE = 0x100    # batch flag: whole-row levels of different lanes take turns
 BATCH_SHARED_BUDGET = 0x200   # batch flag: one memory budget, regions sized per job
 SPEC_DEVICE = 0x1
