@@ -44,7 +44,7 @@ struct Counters {
     uint32_t n_new;                 // new fingerprint groups claimed this level
     uint32_t overflow;              // hash table or list capacity exceeded
     uint32_t n_coll;                // candidates whose full compare failed
-    uint32_t letter_or;             // OR of all letters (validation)
+    uint32_t letter_or;             // OR of the letters that name a missing proposition (validation)
     uint32_t n_fallback_new;        // representatives added by the exact fallback
     uint32_t pad[9];
 };

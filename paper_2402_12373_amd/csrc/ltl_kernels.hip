@@ -1959,20 +1959,26 @@ __global__ __launch_bounds__(256) void k_pack(const uint32_t *letters, const uin
             atoms[(size_t)p * R + r] = w;
         }
     }
-    uint32_t lor = lt;
+    // letters naming a missing proposition (validation): one atomic per wave that holds one
+    uint32_t lor = nprops < 32 ? (lt >> nprops) : 0u;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) lor |= (uint32_t)__shfl_xor((int)lor, o);
-    if (lane == 0 && lor) atomicOr(&ctr->letter_or, lor);
+    if (lane == 0 && lor) atomicOr(&ctr->letter_or, lor << nprops);
 }
 
-// Per-trace fingerprint (length and letters), for the P/N disjointness check.
-__global__ void k_trace_fp(const uint32_t *letters, const uint64_t *offsets, uint32_t ntr, uint64_t *out) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+// Per-trace fingerprint (length and letters), for the P/N disjointness check (equal
+// fingerprints are compared exactly on the host): one wave per trace, the sum of a mix of
+// each (position, letter) pair plus a mix of the length.
+__global__ __launch_bounds__(256) void k_trace_fp(const uint32_t *letters, const uint64_t *offsets, uint32_t ntr,
+                                                  uint64_t *out) {
+    const uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;     // wave-uniform
+    const uint32_t lane = (uint32_t)__lane_id();
     if (t >= ntr) return;
     const uint64_t off = offsets[t], len = offsets[t + 1] - off;
-    uint64_t h = mix64(len + 0x9e3779b97f4a7c15ull);
-    for (uint64_t i = 0; i < len; ++i) h = mix64(h ^ (uint64_t)letters[off + i]);
-    out[t] = h;
+    uint64_t h = 0;
+    for (uint64_t i = lane; i < len; i += 64) h += mix64((i << 32) ^ (uint64_t)letters[off + i] ^ 0x2545f4914f6cdd1dull);
+    h = wave_sum(h);
+    if (lane == 0) out[t] = h + mix64(len + 0x9e3779b97f4a7c15ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -2313,7 +2319,7 @@ hipError_t launch_table_init(unsigned long long *tkey, uint32_t *tval, uint64_t 
 
 hipError_t launch_trace_fp(const uint32_t *letters, const uint64_t *offsets, uint32_t ntr, uint64_t *out,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_trace_fp, dim3((ntr + 255) / 256), dim3(256), 0, s, letters, offsets, ntr, out);
+    hipLaunchKernelGGL(k_trace_fp, dim3((ntr + 3) / 4), dim3(256), 0, s, letters, offsets, ntr, out);
     return hipGetLastError();
 }
 
