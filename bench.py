@@ -459,7 +459,7 @@ def bench_batched(args):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     lanes = args.lanes or 4
     slice_bytes = (ws_bytes // lanes) & ~255
-    slots = 22
+    slots = 0          # hash table sized by the library from each slice (2^26 slots from 1.6 GB)
     # autotuner: tile shape and level schedule, tuned on the slowest of the first 32 jobs
     # (an untimed pass with the defaults picks it: the configurations differ only on the
     # large levels of the large jobs)
@@ -575,7 +575,7 @@ def bench_served(args):
     slice_bytes = (ws_bytes // lanes) & ~255
     big = (ltl.BATCH_BIG_ALONE if args.big_alone else 0) | (ltl.CTX_ONE_STREAM if args.one_stream else 0)
     if args.slices:
-        ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], hash_slots_log2=22, flags=big)
+        ex = ltl.Batch(lanes=lanes, workspace=ws[:slice_bytes * lanes], flags=big)
     else:      # one budget: regions sized by each job's estimated footprint
         ex = ltl.Batch(lanes=lanes, workspace=ws, flags=big | ltl.BATCH_SHARED_BUDGET)
     ex.run(dev[:lanes], bounds[:lanes])                     # warm-up: one job per lane
