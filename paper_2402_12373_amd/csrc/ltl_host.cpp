@@ -72,6 +72,9 @@ bool is_unary(int op) { return op == LTL_NOT || op == LTL_X || op == LTL_F || op
 #ifndef LTL_FORK_U
 #define LTL_FORK_U 1
 #endif
+#ifndef LTL_ANDOR_EVAL_AUX
+#define LTL_ANDOR_EVAL_AUX 1
+#endif
 
 struct ltl_ctx {
     ltl_ctx_opts o;
@@ -1078,7 +1081,10 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             }
             const uint64_t items = units * ((j->NB + chunk - 1) / chunk);
             const uint32_t grid = (uint32_t)std::min<uint64_t>(stg ? items : (items + 3) / 4, MAX_GRID);
-            hipStream_t st = (fork && k == ucls) ? j->ctx->aux : j->s;
+            // the evaluation's and/or class follows U on the second stream (the unary class,
+            // the longest, keeps the first to itself); verification and write pass keep U alone
+            const bool on_aux = fork && (k == ucls || (LTL_ANDOR_EVAL_AUX && k == 1 && !verify && !write));
+            hipStream_t st = on_aux ? j->ctx->aux : j->s;
             const Block *cb = grouped_d + cls_first[k];
             const uint32_t nb = cls_first[k + 1] - cls_first[k];
             hipError_t e;
