@@ -51,6 +51,9 @@ constexpr uint64_t PASS_MIN_CHUNK = 16;  // row blocks per chunk at least (per-i
 // per-level upload, one copy: [counters init (256 B) | canonical blocks | blocks by
 // class | all blocks, one tile numbering]
 constexpr uint64_t UPLOAD_BYTES = 256 + 3 * sizeof(Block) * MAX_BLOCKS;
+// the level's "cannot be kept" flag, a cache line away from the counters in the upload area
+constexpr uint64_t FULL_FLAG_OFF = 128;
+static_assert(sizeof(Counters) <= FULL_FLAG_OFF, "the counters precede the flag");
 // pinned staging: the upload image, then 256 B for the counters read back
 constexpr uint64_t PINNED_BYTES = UPLOAD_BYTES + 256;
 
@@ -983,6 +986,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     }
     *pin_ctr = Counters{};
     pin_ctr->first_sol = ~0ull;
+    *(uint32_t *)(j->ctx->pinned + FULL_FLAG_OFF) = 0;     // uploaded with the counters
     Block *grouped_d = j->blocks_d + lv.blocks.size();
     Block *all_d = grouped_d + grouped.size();
     HIP_TRY(hipMemcpyAsync(j->ctr, j->ctx->pinned,
@@ -1000,6 +1004,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     const uint32_t fb = j->ctx->o.fp_bits;
     A.fp_mask = (fb == 0 || fb >= 64) ? ~0ull : ((1ull << fb) - 1ull);
     A.ctr = j->ctr;
+    A.full = (uint32_t *)((char *)j->ctr + FULL_FLAG_OFF);
     A.cand_slot = cand_slot;
     A.new_slots = new_slots;
     A.claimer = claimer;

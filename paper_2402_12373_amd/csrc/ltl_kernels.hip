@@ -37,9 +37,6 @@
 
 namespace ltl {
 
-#ifndef LTL_UC_PAIR_BARRIER
-#define LTL_UC_PAIR_BARRIER 0
-#endif
 #ifndef LTL_UC_ADD_PREFIX
 #define LTL_UC_ADD_PREFIX 1      // carries between the words of a trace by one add (else Kogge-Stone)
 #endif
@@ -541,6 +538,19 @@ __device__ __forceinline__ uint32_t rank_of(const uint32_t *bitmap, const uint32
 // presumed duplicate of it, confirmed by the verify pass) or the group of this
 // level (the smallest canonical index wins by atomicMin).
 // ---------------------------------------------------------------------------
+// The next claim numbers of a level, one atomic per group of lanes that claim together
+// (the active lanes of the caller): the level's claim counter is one address that every
+// new language of the level increments.
+__device__ __forceinline__ uint32_t claim_number(Counters *ctr) {
+    const uint64_t m = __ballot(1);
+    const uint32_t lane = (uint32_t)__lane_id();
+    const uint32_t lead = (uint32_t)__builtin_ctzll(m);
+    uint32_t base = 0;
+    if (lane == lead) base = atomicAdd(&ctr->n_new, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, (int)lead);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
 template <typename T>
 __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx, uint32_t &claim) {
     claim = 0xFFFFFFFFu;
@@ -551,7 +561,8 @@ __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx
             unsigned long long prev = atomicCAS(&A.tkey[h], 0ull, (unsigned long long)fp);
             if (prev == 0ull) {
                 atomicMin(&A.tval[h], idx);
-                uint32_t pos = atomicAdd(&A.ctr->n_new, 1u);
+                const uint32_t pos = claim_number(A.ctr);
+                if (pos == A.arena_cap || pos == A.new_cap) atomicOr(A.full, 1u);   // the level cannot be kept
                 if (pos < A.new_cap) {
                     A.new_slots[pos] = h;
                     A.claimer[pos] = idx;
@@ -652,10 +663,6 @@ __device__ __forceinline__ void tile_words(const T (&av)[TI], const T (&bv)[TJ],
                     continue;
                 }
                 w[ii * TJ + jj] = apply<T, MW, OP>(av[ii], bv[jj], m, rw, lane);
-#if LTL_UC_PAIR_BARRIER
-                // one pair's masks at a time in scalar registers
-                if constexpr (MW && OP == OP_UC) __builtin_amdgcn_sched_barrier(0);
-#endif
             }
     }
 }
@@ -1251,6 +1258,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     for (uint32_t w = wave; w < nwork; w += nwaves) {
+        if constexpr (!VERIFY && !WONLY) {
+            // once the level's new groups outgrow the arena (or the slot list) the level ends
+            // in LTL_E_OOM whatever else it finds: the remaining tiles are not evaluated.  The
+            // flag has a cache line of its own (the claim counter's line is busy with atomics)
+            if (uniform(__hip_atomic_load(A.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) break;
+        }
         const uint32_t t = w / nchunk, q = w - t * nchunk;
         const uint32_t rb0 = q * chunk, rb1 = min(NB, rb0 + chunk);
         const int bi = (int)uniform((uint32_t)find_block_tile(blocks, (int)nblocks, t));
@@ -1509,7 +1522,8 @@ __global__ __launch_bounds__(256) void k_ruc_claim(LevelArgs<T> A, uint32_t ncan
             const unsigned long long prev = atomicCAS(&A.tkey[h], 0ull, word);
             if (prev == 0ull) {
                 atomicMin(&A.tval[h], c);
-                const uint32_t pos = atomicAdd(&A.ctr->n_new, 1u);
+                const uint32_t pos = claim_number(A.ctr);
+                if (pos == A.arena_cap || pos == A.new_cap) atomicOr(A.full, 1u);   // the level cannot be kept
                 if (pos < A.new_cap) {
                     A.new_slots[pos] = h;
                     A.claimer[pos] = c;
