@@ -95,6 +95,7 @@ struct ltl_ctx {
     // bytes a slot), kept clean across jobs, outside the job regions
     char *cache = nullptr;
     uint32_t cache_slots_log2 = 0;
+    uint64_t pool_total = 0;         // ... and the pool their regions come from
     // allocation-free contexts (ltl_learn_noalloc): host staging in ordinary memory instead
     // of page-locked buffers
     bool noalloc = false;
@@ -1005,6 +1006,17 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.fp_mask = (fb == 0 || fb >= 64) ? ~0ull : ((1ull << fb) - 1ull);
     A.ctr = j->ctr;
     A.full = (uint32_t *)((char *)j->ctr + FULL_FLAG_OFF);
+    {   // the evaluation stops once the claims pass abort_cap: the arena's capacity, or for a
+        // batch lane of a shared budget what would not fit the whole pool either (so that a
+        // level that fits the pool but not the region is counted in full, and its re-run
+        // sized from the count)
+        uint64_t cap = arena_cap;
+        if (j->ctx->pool_total) {
+            const uint64_t fit = j->ctx->pool_total / j->cm_bytes;
+            cap = std::max<uint64_t>(cap, fit > j->total_entries ? fit - j->total_entries : 0);
+        }
+        A.abort_cap = (uint32_t)std::min<uint64_t>(cap, new_cap);
+    }
     A.cand_slot = cand_slot;
     A.new_slots = new_slots;
     A.claimer = claimer;
@@ -1884,6 +1896,7 @@ static void batch_lane_shared(ltl_batch *b, uint32_t lane) {
         // is the lane's own, emptied by each job, so no job initialises a table
         c->o.workspace = (char *)b->o.workspace + b->pool_base + off;
         c->o.workspace_bytes = req;
+        c->pool_total = total;
         const auto a = std::chrono::steady_clock::now();
         ltl_result &res = b->results[i];
         int kind = 0;

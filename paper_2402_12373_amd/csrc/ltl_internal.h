@@ -105,7 +105,8 @@ struct LevelArgs {
     uint32_t wg_split;
     unsigned long long *cand_fp;   // per candidate: sum of partial fingerprints
     uint32_t *cand_viol;           // per candidate: separation violated (bit)
-    uint32_t *full;                // set once the level's claims pass arena_cap (own cache line)
+    uint32_t *full;                // set once the level's claims pass abort_cap (own cache line)
+    uint32_t abort_cap;            // claims after which the level is known to end out of memory
     // Relaxed uniqueness check: the evaluation writes each candidate's 126-bit key, a
     // claim pass caches the new keys, and the level's entries get their representative's
     // key and, in the write pass, its matrix.

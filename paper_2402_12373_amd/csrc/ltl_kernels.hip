@@ -562,7 +562,7 @@ __device__ uint32_t probe_claim(const LevelArgs<T> &A, uint64_t fp, uint32_t idx
             if (prev == 0ull) {
                 atomicMin(&A.tval[h], idx);
                 const uint32_t pos = claim_number(A.ctr);
-                if (pos == A.arena_cap || pos == A.new_cap) atomicOr(A.full, 1u);   // the level cannot be kept
+                if (pos == A.abort_cap || pos == A.new_cap) atomicOr(A.full, 1u);   // the level cannot be kept
                 if (pos < A.new_cap) {
                     A.new_slots[pos] = h;
                     A.claimer[pos] = idx;
@@ -1260,8 +1260,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     for (uint32_t w = wave; w < nwork; w += nwaves) {
         if constexpr (!VERIFY && !WONLY) {
             // once the level's new groups outgrow the arena (or the slot list) the level ends
-            // in LTL_E_OOM whatever else it finds: the remaining tiles are not evaluated.  The
-            // flag has a cache line of its own (the claim counter's line is busy with atomics)
+            // in LTL_E_OOM whatever else it finds: the remaining tiles are not evaluated (a batch
+            // lane of a shared budget goes on up to what the whole pool could hold).  The flag
+            // has a cache line of its own (the claim counter's line is busy with atomics)
             if (uniform(__hip_atomic_load(A.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) break;
         }
         const uint32_t t = w / nchunk, q = w - t * nchunk;
@@ -1523,7 +1524,7 @@ __global__ __launch_bounds__(256) void k_ruc_claim(LevelArgs<T> A, uint32_t ncan
             if (prev == 0ull) {
                 atomicMin(&A.tval[h], c);
                 const uint32_t pos = claim_number(A.ctr);
-                if (pos == A.arena_cap || pos == A.new_cap) atomicOr(A.full, 1u);   // the level cannot be kept
+                if (pos == A.abort_cap || pos == A.new_cap) atomicOr(A.full, 1u);   // the level cannot be kept
                 if (pos < A.new_cap) {
                     A.new_slots[pos] = h;
                     A.claimer[pos] = c;
