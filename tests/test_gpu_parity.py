@@ -6,6 +6,7 @@ formula of the first solution, and every stored characteristic matrix.
 """
 from __future__ import annotations
 
+import functools
 import os
 import sys
 
@@ -336,6 +337,33 @@ def test_table_reuse_across_jobs_after_oom(ltl):
         for seed in (1, 2, 3, 4):
             inst, cfg = synth.preset_instance("tiny", seed)
             _same(c.learn(inst, 7), O.learn(inst, 7, max_entries=30), f"reuse/{seed}")
+    finally:
+        c.close()
+
+
+@functools.lru_cache(maxsize=1)
+def _scale3_oracle():
+    inst, cfg = synth.preset_instance("scale", 3)
+    return O.learn(inst, cfg["bound"], mode=O.MODE_EXPAND, threads=8)
+
+
+@pytest.mark.parametrize("split_tiles", [0, 1], ids=PATHS)
+def test_arena_overflow_stops_and_context_recovers(ltl, split_tiles):
+    """A level whose new languages do not fit the arena ends the job with LTL_E_OOM (the
+    whole-row evaluation stops once the claims pass the arena): the completed levels equal
+    the oracle's, and the same context then learns other jobs exactly."""
+    inst, cfg = synth.preset_instance("scale", 3)       # level 8: 97 865 new languages of 8 KiB
+    o = _scale3_oracle()
+    c = ltl.Context(workspace_bytes=1 << 30, hash_slots_log2=22, split_tiles=split_tiles)
+    try:
+        g = c.learn(inst, cfg["bound"])
+        _say("arena overflow", split_tiles, g.status, g.levels_done)
+        assert g.status == ltl.LTL_E_OOM and 1 <= g.levels_done < o.levels_done
+        assert g.level_new[1:] == o.level_new[1:g.levels_done + 1]
+        assert g.level_candidates[1:] == o.level_candidates[1:g.levels_done + 1]
+        for seed in (0, 5):
+            inst2, cfg2 = synth.preset_instance("tiny", seed)
+            _same(c.learn(inst2, cfg2["bound"]), O.learn(inst2, cfg2["bound"]), f"after overflow/{seed}")
     finally:
         c.close()
 
