@@ -168,8 +168,8 @@ def main():
     ap.add_argument("--workspace-gb", type=float, default=0.0)
     ap.add_argument("--ucarry", action="store_true", help="U by the carry adder at every level (LTL_CTX_U_CARRY)")
     ap.add_argument("--udoubling", action="store_true",
-                    help="U by the doubling of App. B at every level (LTL_CTX_U_DOUBLING); default: doubling on "
-                         "one-word rows, the carry adder on multi-word rows")
+                    help="U by the doubling of App. B at every level (LTL_CTX_U_DOUBLING); default: the carry "
+                         "adder")
     ap.add_argument("--lds-tiles", action="store_true",
                     help="binary tiles of whole-row levels stage 8 x 8 groups of child words in LDS instead of "
                          "reading 4 x 4 tiles into registers (LTL_CTX_LDS_TILES)")
@@ -334,9 +334,8 @@ def bench_fixed(args):
     job.close()
     geom = dict(R=int(info.rows), halves=int(info.rows) * (int(info.word_bits) // 32), k=int(info.doubling_steps),
                 cm_bytes=int(info.cm_bytes))
-    # the U method the library used: forced by a flag, else by row layout (multi-word rows: carry)
-    multiword = int(info.word_bits) == 64 and max(i.max_len for i in insts) > 64
-    u_carry = args.ucarry or (not args.udoubling and multiword)
+    # the U method the library used: the carry adder unless the doubling is forced
+    u_carry = args.ucarry or not args.udoubling
     # lanes > 1: the levels of different jobs overlap on the device, so their summed event
     # time counts overlapping intervals more than once; the wall time of the timed steps is
     # the basis then (a lower bound of the fraction)
@@ -409,7 +408,7 @@ def bench_fixed(args):
         "config": {"workload": f"{workload_desc}, cost bound {cfg['bound']}, seeds {args.seeds}",
                    "jobs_per_step": len(dev), "lanes": lanes, "hash_slots_log2": slots,
                    "u_operator": ("carry adder" if u_carry else "doubling (App. B)")
-                   + ("" if args.ucarry or args.udoubling else " (chosen by row layout)"),
+                   + ("" if args.ucarry or args.udoubling else " (the library default)"),
                    "dedup": ("relaxed (126-bit FKP keys, Sec. 7)" if args.fkp else "relaxed (126-bit keyed sums)")
                    if args.ruc else "exact (fingerprint + full compare)",
                    "binary_tiles": "LDS-staged 8 x 8 groups" if args.lds_tiles else "register 4 x 4"},

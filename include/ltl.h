@@ -68,11 +68,9 @@ typedef struct ltl_job ltl_job;
 
 #define LTL_CTX_U_CARRY   0x1u   /* compute U by a carry-propagating add (one add per word and
                                     a prefix over the words of a trace) instead of the log2(n)
-                                    shift-doubling of App. B, at every level; both give
-                                    identical matrices.  Without this flag or LTL_CTX_U_DOUBLING
-                                    the library picks by row layout: doubling when every trace
-                                    fits one machine word (the paper's regime), the carry adder
-                                    when traces span several words                             */
+                                    shift-doubling of App. B; both give identical matrices.
+                                    This is the default (it was faster on every row layout
+                                    measured); LTL_CTX_U_DOUBLING selects the doubling         */
 #define LTL_CTX_LDS_TILES 0x20u  /* binary connectives of whole-row levels stage their child
                                     operands in LDS: a workgroup of 4 waves loads the words of
                                     8 + 8 children once per row block for an 8 x 8 group of
@@ -80,8 +78,8 @@ typedef struct ltl_job ltl_job;
                                     into registers for a 4 x 4 tile (the default); a tile
                                     shape for ltl_autotune, results are identical               */
 #define LTL_CTX_U_DOUBLING 0x10u /* compute U by the shift-doubling of App. B at every level
-                                    (overrides the choice by row layout; LTL_CTX_U_CARRY wins
-                                    if both are set)                                           */
+                                    instead of the carry adder (LTL_CTX_U_CARRY wins if both
+                                    are set)                                                   */
 #define LTL_CTX_ONE_STREAM 0x80u /* run every kernel on the context's stream: the U class of a
                                     whole-row level is not forked onto a second stream beside
                                     the other classes (batch lanes, whose jobs already overlap) */
@@ -256,7 +254,7 @@ int ltl_autotune(ltl_ctx *ctx, const ltl_spec *spec, const ltl_opset *ops, uint3
  * of a caller workspace.  No hipMalloc, hipHostMalloc, hipFree, stream or event
  * is created; the caller passes the device, a stream (NULL = the null stream),
  * the inputs and *out.  The hash table is 2^LTL_NOALLOC_SLOTS_LOG2 slots; U by
- * doubling; no timing.  A specification or a level that does not fit the array
+ * the carry adder; no timing.  A specification or a level that does not fit the array
  * returns LTL_E_OOM (nothing is allocated instead).  Calls on one GPU share its
  * array, which keeps the last call's contents (the call clears what must start at
  * zero); overlapping calls on one GPU would race, so the library runs them one at

@@ -882,11 +882,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     Block *pin_grouped = pin_blocks + lv.blocks.size();
     memcpy(pin_blocks, lv.blocks.data(), sizeof(Block) * lv.blocks.size());
     // the same blocks grouped by connective class, each class with its own tile numbering
-    // U by doubling (App. B) on one-word rows, where its log2(n) steps are few shifts of
-    // one register; by the carry adder on multi-word rows, where each doubling step moves
-    // words across lanes (measured 2x on the long workload); either can be forced
+    // U by the carry adder (one add, one xor and one bit-select per half-word, a scalar
+    // prefix across the words of a trace): faster than the App. B doubling on every row
+    // layout measured (2x on multi-word rows, where each doubling step moves words across
+    // lanes; 5% on one-word rows); the doubling can be forced
     const uint32_t fl = j->ctx->o.flags;
-    const bool ucarry = (fl & LTL_CTX_U_CARRY) != 0 || (!(fl & LTL_CTX_U_DOUBLING) && j->mw);
+    const bool ucarry = (fl & LTL_CTX_U_CARRY) != 0 || !(fl & LTL_CTX_U_DOUBLING);
     auto cls_of = [&](uint32_t op) {
         if (op == LTL_AND || op == LTL_OR) return 1;
         if (op == LTL_U) return ucarry ? 3 : 2;
