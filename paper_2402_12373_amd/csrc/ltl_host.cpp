@@ -47,6 +47,8 @@ constexpr uint64_t MIN_CHUNK = 4;        // row blocks per work item at least (p
 #define LTL_PASS_WAVES 65536
 #endif
 constexpr uint64_t PASS_WAVES = LTL_PASS_WAVES;
+constexpr uint32_t RUC_SPLIT_MIN_BLOCKS = 64;   // scale (32 row blocks): whole-row 2.47e8 vs row-split 2.02e8
+                                                // candidates/s; long (650): row-split 1.09e7 vs whole-row 0.62e7
 constexpr uint64_t PASS_MIN_CHUNK = 16;  // row blocks per chunk at least (per-item owner and claim lookups)
 // per-level upload, one copy: [counters init (256 B) | canonical blocks | blocks by
 // class | all blocks, one tile numbering]
@@ -842,9 +844,12 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         return j->ws + top;
     };
     const uint64_t nwa = align_up(nw, 64);                 // words, so the bitmaps stay aligned
-    // the relaxed check runs the whole-row kernels at every level (its key pass is theirs)
     const bool ruc = (j->ctx->o.flags & LTL_CTX_RUC) != 0;
-    const bool split = !ruc && ntiles < (j->ctx->o.split_tiles ? (uint64_t)j->ctx->o.split_tiles : SPLIT_TILES);
+    // the relaxed check writes its entries in a pass of its own, so the row-split kernels pay
+    // only where a tile's rows are long (one wave per tile would walk many row blocks):
+    // by default it keeps the whole-row kernels below RUC_SPLIT_MIN_BLOCKS row blocks
+    const bool split = ntiles < (j->ctx->o.split_tiles ? (uint64_t)j->ctx->o.split_tiles : SPLIT_TILES) &&
+                       (!ruc || j->ctx->o.split_tiles || j->NB >= RUC_SPLIT_MIN_BLOCKS);
     // batch lanes that take turns for whole-row levels: held until the level's work is done
     std::unique_lock<std::mutex> big_turn;
     if (!split && j->ctx->big_mu) big_turn = std::unique_lock<std::mutex>(*j->ctx->big_mu);
@@ -852,23 +857,26 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     // bitmap | coll_bits | fb_bits | cand_viol | cand_fp (row-split levels whose tiles
     // span several workgroups); cleared at once
     uint64_t clear_bytes = nwa * 4 * 3;
-    uint32_t *bits3 = (uint32_t *)take_top(
-        align_up(nwa * 4 * 4 + (split ? (uint64_t)nc * 8 : 0), 256));
+    // (the relaxed check's second sums follow cand_fp)
+    const uint64_t fp_words = split ? (uint64_t)nc * (ruc ? 2 : 1) : 0;
+    uint32_t *bits3 = (uint32_t *)take_top(align_up(nwa * 4 * 4 + fp_words * 8, 256));
     uint32_t *cand_slot = (uint32_t *)take_top((uint64_t)nc * 4);
     uint32_t *wordpre = (uint32_t *)take_top((uint64_t)nw * 4);
     uint32_t *chunks = (uint32_t *)take_top((uint64_t)std::max<uint32_t>(nchunks, 1) * 4);
     uint32_t *new_slots = (uint32_t *)take_top((uint64_t)new_cap * 4);
     uint32_t *claimer = (uint32_t *)take_top((uint64_t)new_cap * 4);
     uint32_t *new_owner = (uint32_t *)take_top((uint64_t)new_cap * 4);
-    // whole-row levels: claim number per candidate, and the claims other candidates joined
-    uint32_t *cand_claim = split ? nullptr : (uint32_t *)take_top((uint64_t)nc * 4);
-    uint32_t *has_member = split ? nullptr : (uint32_t *)take_top(align_up((uint64_t)new_cap * 4, 256));
+    // whole-row levels (and relaxed-check levels, whose write pass is always a pass of its
+    // own): claim number per candidate, and the claims other candidates joined
+    const bool write_pass = !split || ruc;
+    uint32_t *cand_claim = write_pass ? (uint32_t *)take_top((uint64_t)nc * 4) : nullptr;
+    uint32_t *has_member = write_pass ? (uint32_t *)take_top(align_up((uint64_t)new_cap * 4, 256)) : nullptr;
     T *stage = (T *)take_top((uint64_t)j->R * sizeof(T));
     unsigned long long *cand_key = ruc ? (unsigned long long *)take_top((uint64_t)nc * 16) : nullptr;
     const uint64_t arena_off = (uint64_t)(j->arena - j->ws);
     const uint64_t arena_used = j->total_entries * j->cm_bytes;
     if (!bits3 || !cand_slot || !wordpre || !chunks || !new_slots || !claimer || !new_owner || !stage ||
-        (!split && (!cand_claim || !has_member)) || (ruc && !cand_key) ||
+        (write_pass && (!cand_claim || !has_member)) || (ruc && !cand_key) ||
         arena_off + arena_used > top)
         return LTL_E_OOM;
     uint32_t *bitmap = bits3, *coll_bits = bits3 + nwa, *fb_bits = bits3 + 2 * nwa, *cand_viol = bits3 + 3 * nwa;
@@ -984,7 +992,7 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
             1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max(1u, all_tiles)));
         const uint32_t wgw = Launch<T>::waves_per_wg(j->mw);
         wg_split = (uint32_t)((need + wgw - 1) / wgw);
-        if (wg_split > 1) clear_bytes = nwa * 4 * 4 + (uint64_t)nc * 8;
+        if (wg_split > 1) clear_bytes = nwa * 4 * 4 + fp_words * 8;
     }
     *pin_ctr = Counters{};
     pin_ctr->first_sol = ~0ull;
@@ -1050,18 +1058,19 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
     A.entry_key = j->entry_key;
     A.ruc_pack = j->ruc_pack ? 1u : 0u;
     A.ruc_bits = j->ctx->o.ruc_key_bits;
+    A.ruc_fpb_off = nc;
     {   // materialize work items: entries x row chunks (sized on the candidate count, an upper bound)
         const uint64_t per = std::max<uint64_t>(
             1, std::min<uint64_t>((j->NB + MIN_CHUNK - 1) / MIN_CHUNK, TARGET_WAVES / std::max<uint64_t>(1, new_cap)));
         A.mat_chunk = (uint32_t)((j->NB + per - 1) / per);
     }
     auto launch_level = [&](bool verify, bool write = false) -> hipError_t {
-        if (merged_eval) {
+        if (merged_eval && !write) {
             if (!verify) {
                 const uint64_t items = (uint64_t)all_tiles * wg_split;
                 HIP_TRY_E(Launch<T>::level_wg(A, j->mw, all_d, (uint32_t)grouped.size(), all_tiles,
-                                              (uint32_t)std::min<uint64_t>(items, MAX_GRID), j->s));
-                if (wg_split > 1) return Launch<T>::probe(A, nc, j->s);
+                                              (uint32_t)std::min<uint64_t>(items, MAX_GRID), j->s, ruc));
+                if (wg_split > 1) return ruc ? Launch<T>::ruc_finish(A, nc, j->s) : Launch<T>::probe(A, nc, j->s);
                 return hipSuccess;
             }
             const uint64_t per = std::max<uint64_t>(
@@ -1139,11 +1148,10 @@ static int eval_level_t(ltl_job *j, uint32_t c, LevelInfo &lv) {
         Timer tm(j, LTL_K_COMPACT);
         HIP_TRY(Launch<T>::ruc_claim(A, nc, j->s));
     }
-    if (wg_split > 1) {     // claimers' matrices (their rows were spread over workgroups)
+    if (wg_split > 1 && !ruc) {     // claimers' matrices (their rows were spread over workgroups)
         Timer tm(j, LTL_K_MATERIALIZE);
         HIP_TRY(Launch<T>::materialize(A, j->mw, 0u, grid_mat, j->s));
     }
-    const bool write_pass = !split;
     {
         Timer tm(j, LTL_K_COMPACT, nw <= SMALL_COMPACT_WORDS ? 1u : 5u);
         if (nw <= SMALL_COMPACT_WORDS) {

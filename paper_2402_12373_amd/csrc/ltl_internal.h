@@ -116,6 +116,7 @@ struct LevelArgs {
     unsigned long long *entry_key; // per global entry: its key
     uint32_t ruc_pack;             // keys in pack form (prefix bits) instead of keyed sums
     uint32_t ruc_bits;             // keep the first ruc_bits bits of each key (0: all 126)
+    uint32_t ruc_fpb_off;          // row-split tiles over workgroups: second sums at cand_fp + this
 };
 
 
@@ -131,7 +132,9 @@ struct Launch {
     // row-split levels, every connective class in one dispatch: evaluation with one
     // workgroup per tile (claims and claimers' matrices included) ...
     static hipError_t level_wg(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
-                               uint32_t ntiles, uint32_t grid, hipStream_t s);
+                               uint32_t ntiles, uint32_t grid, hipStream_t s, bool ruc = false);
+    // relaxed check, row-split tiles spread over workgroups: added partial sums -> keys
+    static hipError_t ruc_finish(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s);
     // relaxed check: evaluation writing each candidate's key (whole-row tiles, one class) ...
     static hipError_t level_ruc(const LevelArgs<T> &A, bool mw, int cls, const Block *blocks, uint32_t nblocks,
                                 uint32_t ntiles, uint32_t grid, hipStream_t s);

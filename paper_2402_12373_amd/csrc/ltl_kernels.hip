@@ -690,6 +690,7 @@ __device__ __forceinline__ uint64_t arena_addr(const LevelArgs<T> &A, uint32_t p
 constexpr int WG_WAVES = 8;
 struct WgShare {
     unsigned long long fp[WG_WAVES][16];
+    unsigned long long fpb[WG_WAVES][16];   // relaxed check: the second keyed sum
     uint32_t bad[WG_WAVES][16];
     uint32_t claim[16];
 };
@@ -846,7 +847,40 @@ __device__ __forceinline__ void run_tile(const LevelArgs<T> &A, const Block &b, 
             const bool bad = __ballot(viol[p] != 0) != 0ull;
             if (lane == p) { my_idx = idx[p]; my_bad = bad; }
         }
-        if constexpr (RK) {
+        if constexpr (RK && WG) {
+            // relaxed check, a tile's row chunks over the waves of a workgroup (and maybe over
+            // several workgroups): partial sums combined in LDS, then the key or, for a tile
+            // spread over workgroups, the partial sums added per candidate (k_ruc_finish)
+            if (lane < NP) {
+                sh->fp[wv][lane] = my_fp;
+                sh->fpb[wv][lane] = my_fp_b;
+                sh->bad[wv][lane] = my_bad ? 1u : 0u;
+            }
+            __syncthreads();
+            if (wv == 0 && lane < NP && my_idx != 0xFFFFFFFFu) {
+                uint64_t fa = 0, fb = 0;
+                uint32_t bad = 0;
+                for (uint32_t w = 0; w < nwv; ++w) {
+                    fa += sh->fp[w][lane];
+                    fb += sh->fpb[w][lane];
+                    bad |= sh->bad[w][lane];
+                }
+                if (A.wg_split > 1) {
+                    atomicAdd(&A.cand_fp[my_idx], (unsigned long long)fa);
+                    atomicAdd(&A.cand_fp[A.ruc_fpb_off + my_idx], (unsigned long long)fb);
+                    if (bad) atomicOr(&A.cand_viol[my_idx >> 5], 1u << (my_idx & 31u));
+                } else {
+                    if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
+                    uint64_t k0, k1;
+                    ruc_key(fa, fb, rpack, A.ruc_bits, k0, k1);
+                    A.cand_key[2 * (uint64_t)my_idx] = k0;
+                    A.cand_key[2 * (uint64_t)my_idx + 1] = k1;
+                    A.cand_claim[my_idx] = 0xFFFFFFFFu;
+                }
+            }
+            __syncthreads();   // the shared block is free for the next tile
+            return;
+        } else if constexpr (RK) {
             // relaxed check: the key is written; the claims are a pass of their own
             if (my_idx != 0xFFFFFFFFu) {
                 if (!my_bad) atomicMin(&A.ctr->first_sol, (unsigned long long)my_idx);
@@ -1342,10 +1376,10 @@ __global__ __launch_bounds__(256) void k_level_all(LevelArgs<T> A, const Block *
 // registers per wave: half as many waves per workgroup.
 template <bool MW> constexpr int wg_waves() { return MW ? WG_WAVES / 2 : WG_WAVES; }
 
-template <typename T, bool MW>
-__global__ __launch_bounds__(64 * wg_waves<MW>()) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : LTL_WAVES_U64_WG)))
-void k_level_wg(LevelArgs<T> A, const Block *blocks,
-                                                                  uint32_t nblocks, uint32_t ntiles) {
+template <typename T, bool MW, bool RK = false>
+__global__ __launch_bounds__(64 * wg_waves<MW>())
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !RK ? 4 : LTL_WAVES_U64_WG)))
+void k_level_wg(LevelArgs<T> A, const Block *blocks, uint32_t nblocks, uint32_t ntiles) {
     __shared__ WgShare sh;
     const int lane = (int)__lane_id();
     const uint32_t wv = uniform(threadIdx.x >> 6);
@@ -1366,18 +1400,18 @@ void k_level_wg(LevelArgs<T> A, const Block *blocks,
         i0 = uniform(i0);
         j0 = uniform(j0);
         switch (b.op) {
-        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
-        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
-        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
-        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
-        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
-        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
-        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_ATOM: run_tile<T, MW, LTL_ATOM, TILE, 1, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_NOT:  run_tile<T, MW, LTL_NOT, TILE, 1, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_X:    run_tile<T, MW, LTL_X, TILE, 1, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_F:    run_tile<T, MW, LTL_F, TILE, 1, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_G:    run_tile<T, MW, LTL_G, TILE, 1, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_AND:  run_tile<T, MW, LTL_AND, TILE, TILE, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        case LTL_OR:   run_tile<T, MW, LTL_OR, TILE, TILE, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
         case LTL_U:
-            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv);
-            else run_tile<T, MW, LTL_U, TILE, TILE, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv);
+            if (A.ucarry) run_tile<T, MW, OP_UC, TILE, TILE, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv);
+            else run_tile<T, MW, LTL_U, TILE, TILE, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv);
             break;
-        default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, false, true, true>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
+        default:       run_tile<T, MW, (int)OP_FUSED4, TILE, 4, false, true, true, false, RK>(A, b, i0, j0, lane, rb0, rb1, &sh, wv, nwv); break;
         }
     }
 }
@@ -1550,6 +1584,21 @@ __global__ __launch_bounds__(256) void k_ruc_claim(LevelArgs<T> A, uint32_t ncan
     }
     atomicOr(&A.ctr->overflow, 1u);
     A.cand_slot[c] = NO_SLOT;
+}
+
+// Relaxed check, tiles spread over several workgroups: the added partial sums -> keys.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ruc_finish(LevelArgs<T> A, uint32_t ncand) {
+    const bool pack = A.ruc_pack != 0;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ncand; x += gridDim.x * blockDim.x) {
+        const bool bad = (A.cand_viol[x >> 5] >> (x & 31u)) & 1u;
+        if (!bad) atomicMin(&A.ctr->first_sol, (unsigned long long)x);
+        uint64_t k0, k1;
+        ruc_key(A.cand_fp[x], A.cand_fp[A.ruc_fpb_off + x], pack, A.ruc_bits, k0, k1);
+        A.cand_key[2 * (uint64_t)x] = k0;
+        A.cand_key[2 * (uint64_t)x + 1] = k1;
+        A.cand_claim[x] = 0xFFFFFFFFu;
+    }
 }
 
 // Relaxed check, after the compaction of a level that will be stored: each new entry
@@ -2196,16 +2245,31 @@ hipError_t Launch<T>::verify_all(const LevelArgs<T> &A, bool mw, const Block *bl
 
 template <typename T>
 hipError_t Launch<T>::level_wg(const LevelArgs<T> &A, bool mw, const Block *blocks, uint32_t nblocks,
-                               uint32_t ntiles, uint32_t grid, hipStream_t s) {
+                               uint32_t ntiles, uint32_t grid, hipStream_t s, bool ruc) {
     if constexpr (sizeof(T) == 8) {
         if (mw) {
-            hipLaunchKernelGGL((k_level_wg<T, true>), dim3(grid), dim3(64 * wg_waves<true>()), 0, s, A, blocks,
-                               nblocks, ntiles);
+            if (ruc)
+                hipLaunchKernelGGL((k_level_wg<T, true, true>), dim3(grid), dim3(64 * wg_waves<true>()), 0, s, A,
+                                   blocks, nblocks, ntiles);
+            else
+                hipLaunchKernelGGL((k_level_wg<T, true>), dim3(grid), dim3(64 * wg_waves<true>()), 0, s, A, blocks,
+                                   nblocks, ntiles);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_level_wg<T, false>), dim3(grid), dim3(64 * wg_waves<false>()), 0, s, A, blocks, nblocks,
-                       ntiles);
+    if (ruc)
+        hipLaunchKernelGGL((k_level_wg<T, false, true>), dim3(grid), dim3(64 * wg_waves<false>()), 0, s, A, blocks,
+                           nblocks, ntiles);
+    else
+        hipLaunchKernelGGL((k_level_wg<T, false>), dim3(grid), dim3(64 * wg_waves<false>()), 0, s, A, blocks,
+                           nblocks, ntiles);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::ruc_finish(const LevelArgs<T> &A, uint32_t ncand, hipStream_t s) {
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((ncand + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_ruc_finish<T>), dim3(grid), dim3(256), 0, s, A, ncand);
     return hipGetLastError();
 }
 

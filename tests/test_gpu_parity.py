@@ -537,10 +537,12 @@ def test_batch_big_levels_take_turns(ltl):
 
 
 RUC_CASES = [("hash", 0), ("hash", 9), ("hash", 14), ("fkp", 0), ("fkp", 10)]
+_RUC_ORACLE = {}      # oracle results per (case, key form, key bits), shared by the kernel paths
 
 
+@pytest.mark.parametrize("split_tiles", [0, 1], ids=PATHS)
 @pytest.mark.parametrize("kind,bits", RUC_CASES, ids=[f"{k}-{b or 126}bit" for k, b in RUC_CASES])
-def test_relaxed_check_matches_oracle(ltl, kind, bits):
+def test_relaxed_check_matches_oracle(ltl, kind, bits, split_tiles):
     """LTL_CTX_RUC (Sec. 5; FKP keys, Sec. 7) against the oracle's relaxed mode with the same
     126-bit keys: the same languages are cached (canonical-first candidate of each new key),
     so level counts, the first solution and its formula agree, on one-word and multi-word
@@ -554,20 +556,40 @@ def test_relaxed_check_matches_oracle(ltl, kind, bits):
     cases.append((random_instance(rng, 3, 5, 5, 60, 70), 5, None, "u64 one-word"))
     cases.append((random_instance(rng, 2, 4, 4, 3, 9), 7, None, "at most 126 bits"))
     cases.append((synth.hamming_instance(0, 4, 2), 12, O.U_FREE_NNF, "hamming U-free NNF"))
+    # long rows, few tiles: row-split tiles spread over several workgroups (partial sums)
+    cases.append((synth.preset_instance("long", 0)[0], 3, None, "long rows"))
     for fp_bits in (0, 4):
         c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=20, flags=flags, ruc_seed=17,
-                        ruc_key_bits=bits, fp_bits=fp_bits)
+                        ruc_key_bits=bits, fp_bits=fp_bits, split_tiles=split_tiles)
         try:
             for inst, bound, ops, name in cases:
                 _say("ruc", kind, bits, fp_bits, name)
-                o = O.learn(inst, bound, op_mask=ops if ops is not None else O.ALL_OPS, ruc=okind, ruc_seed=17,
-                            ruc_bits=bits)
+                key = (name, kind, bits)
+                if key not in _RUC_ORACLE:
+                    _RUC_ORACLE[key] = O.learn(inst, bound, op_mask=ops if ops is not None else O.ALL_OPS, ruc=okind,
+                                               ruc_seed=17, ruc_bits=bits, mode=O.MODE_EXPAND, threads=8)
+                o = _RUC_ORACLE[key]
                 g = c.learn(inst, bound, ops=ops)
                 _same(g, o, f"{kind}/{bits}/{fp_bits}/{name}")
                 if bits == 0 and int(inst.offsets[-1]) <= 126:    # Sec. 5: exact up to 126 bits
                     _same(g, O.learn(inst, bound, op_mask=ops if ops is not None else O.ALL_OPS), name)
         finally:
             c.close()
+
+
+def test_relaxed_check_row_split_small_rows(ltl):
+    """The relaxed check on the row-split kernels forced at every level (the library keeps
+    the whole-row kernels for short rows by default): the oracle's relaxed results."""
+    c = ltl.Context(workspace_bytes=2 << 30, hash_slots_log2=20, flags=ltl.CTX_RUC, ruc_seed=5, ruc_key_bits=9,
+                    split_tiles=0xFFFFFFFF)
+    try:
+        for seed in range(6):
+            inst, cfg = synth.preset_instance("tiny", seed)
+            _say("ruc row-split tiny", seed)
+            _same(c.learn(inst, cfg["bound"]), O.learn(inst, cfg["bound"], ruc=O.RUC_HASH, ruc_seed=5, ruc_bits=9),
+                  f"ruc row-split/{seed}")
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("kind", ["hash", "fkp"])
