@@ -22,7 +22,6 @@
 #include <map>
 #include <mutex>
 #include <new>
-#include <unordered_map>
 #include <thread>
 #include <vector>
 
@@ -98,6 +97,7 @@ struct ltl_ctx {
     char *cache = nullptr;
     uint32_t cache_slots_log2 = 0;
     uint64_t pool_total = 0;         // ... and the pool their regions come from
+    std::vector<uint32_t> fp_keys;   // the fingerprint keys' sequence, as far as jobs have needed it
     // allocation-free contexts (ltl_learn_noalloc): host staging in ordinary memory instead
     // of page-locked buffers
     bool noalloc = false;
@@ -485,10 +485,13 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
             row_word[row] = w;
         }
     }
-    {
-        uint32_t *keys = (uint32_t *)(img + o_key);
-        uint64_t seed = 0x5eed1e55c0ffee11ull;
-        for (uint64_t q = 0; q < R * nkeys; ++q) keys[q] = (uint32_t)(splitmix64(seed) >> 32) | 1u;
+    {   // the fingerprint keys: one fixed sequence, generated once per context and copied
+        if (c->fp_keys.size() < R * nkeys) {
+            uint64_t seed = 0x5eed1e55c0ffee11ull;
+            c->fp_keys.resize(R * nkeys);
+            for (uint64_t q = 0; q < R * nkeys; ++q) c->fp_keys[q] = (uint32_t)(splitmix64(seed) >> 32) | 1u;
+        }
+        memcpy(img + o_key, c->fp_keys.data(), R * nkeys * 4);
     }
     if (ruc) {
         // Key metadata of the relaxed check (Sec. 5; FKP, Sec. 7), per 32-bit half of a row
@@ -632,13 +635,14 @@ static int job_setup(ltl_job *j, const ltl_spec *spec) {
     collect_times(j);
     if (j->A < 32 && (hc.letter_or >> j->A)) return LTL_E_INVAL;      // a letter names a missing proposition
 
-    // P and N must be disjoint (Sec. 2): equal fingerprints are compared exactly
-    std::unordered_multimap<uint64_t, uint32_t> pos;
-    pos.reserve(j->npos * 2 + 1);
-    for (uint32_t t = 0; t < j->npos; ++t) pos.emplace(tf[t], t);
+    // P and N must be disjoint (Sec. 2): equal fingerprints are compared exactly (the
+    // positives' fingerprints sorted, each negative's looked up by binary search)
+    std::vector<std::pair<uint64_t, uint32_t>> pos(j->npos);
+    for (uint32_t t = 0; t < j->npos; ++t) pos[t] = {tf[t], t};
+    std::sort(pos.begin(), pos.end());
     for (uint32_t t = j->npos; t < T; ++t) {
-        auto rg = pos.equal_range(tf[t]);
-        for (auto it = rg.first; it != rg.second; ++it) {
+        auto lo = std::lower_bound(pos.begin(), pos.end(), std::make_pair(tf[t], 0u));
+        for (auto it = lo; it != pos.end() && it->first == tf[t]; ++it) {
             const uint32_t p = it->second;
             const uint64_t lp = j->off[p + 1] - j->off[p], ln = j->off[t + 1] - j->off[t];
             if (lp != ln) continue;
