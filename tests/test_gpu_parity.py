@@ -555,6 +555,8 @@ def test_relaxed_check_matches_oracle(ltl, kind, bits, split_tiles):
     cases.append((random_instance(rng, 2, 6, 6, 40, 150), 5, None, "u64 multi-word"))
     cases.append((random_instance(rng, 3, 5, 5, 60, 70), 5, None, "u64 one-word"))
     cases.append((random_instance(rng, 2, 4, 4, 3, 9), 7, None, "at most 126 bits"))
+    # 3 traces of 33..40 positions, 115 bits: minimal cost 4
+    cases.append((random_instance(np.random.default_rng(0), 1, 2, 1, 33, 40), 6, None, "at most 126 bits, 64-bit rows"))
     cases.append((synth.hamming_instance(0, 4, 2), 12, O.U_FREE_NNF, "hamming U-free NNF"))
     # long rows, few tiles: row-split tiles spread over several workgroups (partial sums)
     cases.append((synth.preset_instance("long", 0)[0], 3, None, "long rows"))
