@@ -8,7 +8,8 @@
   slots), the eight benchmark seeds: status, minimal cost, every level's counts
   and the first solution equal the oracle's (the oracle runs every level);
 * long workload (5 props, 4096+4096 traces, len 64..512, multi-word 64-bit rows):
-  levels 1..4 complete (counts, every entry's formula, sampled matrices).
+  levels 1..4 complete (counts, every entry's formula, sampled matrices), in the exact
+  mode and with the relaxed check of Sec. 5 (full and 12-bit keys).
 """
 from __future__ import annotations
 
@@ -72,6 +73,37 @@ def test_long_workload_levels(ltl, big_ctx, seed):
                 np.testing.assert_array_equal(job.dump_cm(c, e), run.entry_cm(c, e), err_msg=f"{c}/{e}")
     finally:
         job.close()
+
+
+@pytest.mark.parametrize("bits", [0, 12])
+def test_long_workload_relaxed_levels(ltl, bits):
+    """The relaxed check (Sec. 5, keyed sums) at the long workload's full size in the bench's
+    relaxed configuration (2^26 slots, key seed 0; the row-split kernels with tiles spread
+    over several workgroups), levels 1..4: the counts, every entry's formula and sampled
+    stored matrices equal the oracle's relaxed run with the same keys.  With keys cut to 12
+    bits, false positives decide which languages are kept."""
+    inst, cfg = synth.preset_instance("long", 0)
+    print("long relaxed, key bits", bits, flush=True)
+    run = O.Run(O.Spec.of(inst), 4, mode=O.MODE_EXPAND, threads=THREADS, ruc=O.RUC_HASH, ruc_seed=0, ruc_bits=bits)
+    ora = run.result()
+    c = ltl.Context(workspace_bytes=16 << 30, hash_slots_log2=26, flags=ltl.CTX_RUC, ruc_seed=0, ruc_key_bits=bits)
+    try:
+        job = c.job(ltl.spec_to_device(inst), cfg["bound"])
+        try:
+            for lv in range(1, 5):
+                st = job.eval_level(lv)
+                assert st.candidates == ora.level_candidates[lv] and st.new_entries == ora.level_new[lv], lv
+                n = ora.level_new[lv]
+                for e in range(n):
+                    assert job.formula(lv, e) == run.entry_formula(lv, e), (lv, e)
+                for e in sorted(set([0, n - 1] + list(range(0, n, max(1, n // 8))))):
+                    np.testing.assert_array_equal(job.dump_cm(lv, e), run.entry_cm(lv, e), err_msg=f"{lv}/{e}")
+        finally:
+            job.close()
+    finally:
+        c.close()
+    if bits:
+        assert sum(ora.level_new[1:5]) < sum(LONG_GOLDEN[0]["E"][:4])   # the exact counts
 
 
 def _long_golden():
