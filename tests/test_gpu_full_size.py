@@ -9,7 +9,8 @@
   and the first solution equal the oracle's (the oracle runs every level);
 * long workload (5 props, 4096+4096 traces, len 64..512, multi-word 64-bit rows):
   levels 1..4 complete (counts, every entry's formula, sampled matrices), in the exact
-  mode and with the relaxed check of Sec. 5 (full and 12-bit keys).
+  mode and with the relaxed check of Sec. 5 (full and 12-bit keyed sums, FKP keys);
+* long workload, whole jobs with the relaxed check and full keys: the stored exact results.
 """
 from __future__ import annotations
 
@@ -75,18 +76,21 @@ def test_long_workload_levels(ltl, big_ctx, seed):
         job.close()
 
 
-@pytest.mark.parametrize("bits", [0, 12])
-def test_long_workload_relaxed_levels(ltl, bits):
-    """The relaxed check (Sec. 5, keyed sums) at the long workload's full size in the bench's
-    relaxed configuration (2^26 slots, key seed 0; the row-split kernels with tiles spread
-    over several workgroups), levels 1..4: the counts, every entry's formula and sampled
-    stored matrices equal the oracle's relaxed run with the same keys.  With keys cut to 12
-    bits, false positives decide which languages are kept."""
+@pytest.mark.parametrize("kind,bits", [("hash", 0), ("hash", 12), ("fkp", 0)])
+def test_long_workload_relaxed_levels(ltl, kind, bits):
+    """The relaxed check (Sec. 5, keyed sums; FKP keys, Sec. 7) at the long workload's full
+    size in the bench's relaxed configuration (2^26 slots, key seed 0; the row-split kernels
+    with tiles spread over several workgroups), levels 1..4: the counts, every entry's
+    formula and sampled stored matrices equal the oracle's relaxed run with the same keys.
+    With keys cut to 12 bits, or FKP's first position of the first traces, false positives
+    decide which languages are kept."""
     inst, cfg = synth.preset_instance("long", 0)
-    print("long relaxed, key bits", bits, flush=True)
-    run = O.Run(O.Spec.of(inst), 4, mode=O.MODE_EXPAND, threads=THREADS, ruc=O.RUC_HASH, ruc_seed=0, ruc_bits=bits)
+    print("long relaxed", kind, "key bits", bits, flush=True)
+    okind = O.RUC_FKP if kind == "fkp" else O.RUC_HASH
+    flags = ltl.CTX_RUC | (ltl.CTX_RUC_FKP if kind == "fkp" else 0)
+    run = O.Run(O.Spec.of(inst), 4, mode=O.MODE_EXPAND, threads=THREADS, ruc=okind, ruc_seed=0, ruc_bits=bits)
     ora = run.result()
-    c = ltl.Context(workspace_bytes=16 << 30, hash_slots_log2=26, flags=ltl.CTX_RUC, ruc_seed=0, ruc_key_bits=bits)
+    c = ltl.Context(workspace_bytes=16 << 30, hash_slots_log2=26, flags=flags, ruc_seed=0, ruc_key_bits=bits)
     try:
         job = c.job(ltl.spec_to_device(inst), cfg["bound"])
         try:
@@ -102,7 +106,7 @@ def test_long_workload_relaxed_levels(ltl, bits):
             job.close()
     finally:
         c.close()
-    if bits:
+    if bits or kind == "fkp":
         assert sum(ora.level_new[1:5]) < sum(LONG_GOLDEN[0]["E"][:4])   # the exact counts
 
 
@@ -123,6 +127,25 @@ def _long_golden():
 
 
 LONG_GOLDEN = _long_golden()
+
+
+@pytest.mark.parametrize("seed", sorted(LONG_GOLDEN))
+def test_long_workload_relaxed_whole_jobs(ltl, seed):
+    """Whole long jobs with the relaxed check and full 126-bit keyed sums (levels 5..7 on the
+    whole-row kernels): no two of these languages share a key, so the relaxed run keeps
+    exactly the exact mode's languages and equals the oracle's stored exact results."""
+    want = LONG_GOLDEN[seed]
+    inst, cfg = synth.preset_instance("long", seed)
+    print("long relaxed whole job, seed", seed, flush=True)
+    c = ltl.Context(workspace_bytes=64 << 30, hash_slots_log2=26, flags=ltl.CTX_RUC, ruc_seed=0)
+    try:
+        g = c.learn(ltl.spec_to_device(inst), cfg["bound"])
+    finally:
+        c.close()
+    assert (g.status, g.levels_done) == (want["status"], want["done"])
+    assert g.level_new[1:] == want["E"] and g.level_candidates[1:] == want["C"]
+    if want["status"] == 0:
+        assert (g.cost, g.solution_index, g.solution) == (want["cost"], want["first"], want["sol"])
 
 
 @pytest.mark.parametrize("seed", sorted(LONG_GOLDEN))
