@@ -4,9 +4,10 @@
 A step is one pass of the whole hot path over one batch of synthetic input: the
 learning jobs of the long-trace workload (5 propositions, 4096 + 4096 traces of
 length 64..512, Bernoulli(0.3) letters, planted formula of size 11, unit costs,
-cost bound 13, multi-word 64-bit rows), seeds 0..3, each solved by ltl_learn
-from a device-resident specification, one job after another on one stream.  The
-metric is the number of canonical candidates evaluated, over the timed wall time.
+cost bound 13, multi-word 64-bit rows), seeds 0..3, each solved from a
+device-resident specification, the four in flight together on the 4 lanes of a
+batch executor (own stream, equal workspace slice, hash table each).  The metric is
+the number of canonical candidates evaluated, over the timed wall time.
 
 The same line carries the scale workload (3 propositions, 1024 + 1024 traces of
 length 16..32, bound 11, 32-bit rows; 8 jobs, 4 in flight) as a secondary object.
@@ -160,9 +161,9 @@ def main():
     ap.add_argument("--ham-delta", type=int, default=2, help="hamming workload: bit distance of the negatives")
     ap.add_argument("--jobs", type=int, default=256, help="batched workload: number of jobs")
     ap.add_argument("--lanes", type=int, default=0,
-                    help="jobs in flight (lanes of a batch executor: own stream, workspace slice, hash table); "
-                         "default 4 for the fixed workloads, 1 for long (each long job needs the whole "
-                         "workspace), 4 for batched; 1 = one job after another")
+                    help="jobs in flight (lanes of a batch executor: own stream, equal workspace slice, hash "
+                         "table); default 4 (a long job needs ~41 GiB, a slice of the default workspace 50); "
+                         "1 = one job after another on one stream")
     ap.add_argument("--seeds", default="", help="job seeds, e.g. 0-7 (default: 0-3 for long, else 0-7)")
     ap.add_argument("--bound", type=int, default=0, help="cost bound (default: the workload's)")
     ap.add_argument("--workspace-gb", type=float, default=0.0)
@@ -280,13 +281,18 @@ def bench_fixed(args):
     # pass: events around every kernel group (time per kernel kind)
     timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
     full_flags = (0 if args.no_timing else ltl.CTX_TIMING) | ucarry
-    lanes = args.lanes or (1 if args.workload == "long" else 4)
+    lanes = args.lanes or 4
     lanes = max(1, min(lanes, len(dev)))
-    # lanes > 1: the batch executor takes the workspace; the one-stream comparison run gets a
-    # workspace of one lane's size, so both see the same capacity per job
-    ctx_bytes = ws_bytes if lanes == 1 else (ws_bytes // (lanes + 1)) & ~255
-    ctx = ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots, flags=full_flags if lanes > 1 else timed_flags,
-                      split_tiles=args.split_tiles)
+    # lanes > 1: the batch executor takes the workspace in equal slices; the one-stream
+    # comparison run afterwards gets a workspace of one lane's size, so both see the same
+    # capacity per job
+    ctx_bytes = ws_bytes if lanes == 1 else (ws_bytes // lanes) & ~255
+
+    def one_stream_context():
+        return ltl.Context(workspace_bytes=ctx_bytes, hash_slots_log2=slots,
+                           flags=full_flags if lanes > 1 else timed_flags, split_tiles=args.split_tiles)
+
+    ctx = None if lanes > 1 else one_stream_context()
     if lanes > 1:
         ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots,
                        flags=timed_flags | (ltl.BATCH_BIG_ALONE if args.big_alone else 0))
@@ -322,6 +328,11 @@ def bench_fixed(args):
     t1 = time.perf_counter()
     gc.enable()
     wall = t1 - t0
+    if lanes > 1:          # the batch's workspace goes back before the one-stream context takes its own
+        ex.close()
+        del ex
+        torch.cuda.empty_cache()
+        ctx = one_stream_context()
 
     cands = sum(r.candidates for r in results)
     value = cands / wall
@@ -436,8 +447,6 @@ def bench_fixed(args):
     if failed:
         print(f"warning: jobs of seeds {failed} ended in an error (statuses {out['statuses']}); "
               "fewer lanes or a larger workspace give each job more memory", file=sys.stderr, flush=True)
-    if lanes > 1:
-        ex.close()
     ctx.close()
     return out
 
