@@ -187,7 +187,8 @@ def main():
                     help="batched: skip the autotuner (ltl_autotune on the largest of the first 16 jobs chooses "
                          "the binary tile shape and the whole-row level size for the plain and batched runs)")
     ap.add_argument("--one-stream", action="store_true",
-                    help="batched/served: lanes run the U class on their own stream (LTL_CTX_ONE_STREAM)")
+                    help="lanes > 1: each lane runs every kernel on its own stream, the U class of a "
+                         "whole-row level included (LTL_CTX_ONE_STREAM)")
     ap.add_argument("--slices", action="store_true",
                     help="batched/served: equal workspace slices per lane instead of one shared budget "
                          "with regions sized per job (LTL_BATCH_SHARED_BUDGET)")
@@ -295,7 +296,8 @@ def bench_fixed(args):
     ctx = None if lanes > 1 else one_stream_context()
     if lanes > 1:
         ex = ltl.Batch(lanes=lanes, workspace_bytes=ctx_bytes * lanes, hash_slots_log2=slots,
-                       flags=timed_flags | (ltl.BATCH_BIG_ALONE if args.big_alone else 0))
+                       flags=timed_flags | (ltl.BATCH_BIG_ALONE if args.big_alone else 0)
+                       | (ltl.CTX_ONE_STREAM if args.one_stream else 0))
 
         def step():
             res, dur, done = ex.run(dev, [cfg["bound"]] * len(dev), ops=ops)
