@@ -35,7 +35,10 @@ namespace {
 constexpr int ORDER[7] = {LTL_F, LTL_U, LTL_G, LTL_X, LTL_AND, LTL_OR, LTL_NOT};   // Sec. 3 listing
 constexpr uint32_t MAX_GRID = 8192;
 // Row-split levels: the number of waves their row chunks aim for.
-constexpr uint64_t TARGET_WAVES = 8192;
+#ifndef LTL_TARGET_WAVES
+#define LTL_TARGET_WAVES 8192
+#endif
+constexpr uint64_t TARGET_WAVES = LTL_TARGET_WAVES;
 // Levels with fewer tiles than this are row-split (waves take chunks of row
 // blocks), so that small levels are not one long chain of dependent row-block
 // loads per wave (a tuning constant; ltl_ctx_opts.split_tiles overrides it).
