@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, 8 TB/s
+LONG_JOB_GIB = 46                # workspace a long job needs (its largest: ~41 GiB), with a margin
 KERNEL_SRC = os.path.join(ROOT, "paper_2402_12373_amd", "csrc", "ltl_kernels.hip")
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in ("traffic_long.json", "traffic_scale.json")]
 
@@ -283,6 +284,8 @@ def bench_fixed(args):
     timed_flags = (0 if args.no_timing else ltl.CTX_TIMING_LEVEL) | ucarry
     full_flags = (0 if args.no_timing else ltl.CTX_TIMING) | ucarry
     lanes = args.lanes or 4
+    if args.workload == "long" and not args.lanes:
+        lanes = min(lanes, max(1, ws_bytes // (LONG_JOB_GIB << 30)))    # every lane must hold a whole job
     lanes = max(1, min(lanes, len(dev)))
     # lanes > 1: the batch executor takes the workspace in equal slices; the one-stream
     # comparison run afterwards gets a workspace of one lane's size, so both see the same
